@@ -1,0 +1,181 @@
+#!/usr/bin/env python3
+"""Throughput of the exact-GP hot path on one MI355X.
+
+One step = covariance assembly + tiled Cholesky + predictive mean + full
+posterior covariance (n = 16384 training points, n_test = 4096, D = 8,
+tile 512, FP64), inputs resident in HBM. Reported as GFLOP/s with the flop
+convention n^3/3 (Cholesky) + n^2 n_test (V solve) + n_test^2 n (W) + 2 n^2
+(vector solves) + 2 n n_test (mean); assembly time counts, its flops do not.
+
+Prints one JSON line. `--gpus` above 1 is refused: this path runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Cholesky+predict GFLOP/s & % peak at n=16384, FP64 vs mixed, at stated error"
+FP64_PEAK_TFLOPS = 78.6     # MI355X dense FP64 (vector = matrix)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def path_flops(n, ns):
+    return n ** 3 / 3 + n * n * ns + ns * ns * n + 2 * n * n + 2 * n * ns
+
+
+def cpu_baseline(h, target_s=15.0):
+    """The oracle (plain C, OpenMP) on a bounded sample of the same workload:
+    a smaller n with n_test = n / 4, timed once; GFLOP/s by the same flop count."""
+    import oracle
+    from gpr_inputs import nfir_train_test
+    n0 = 1536
+    X, y, Xs = nfir_train_test(n0, n0 // 4)
+    t = time.perf_counter()
+    oracle.predict(X, y, Xs, h, want=("mean", "cov"))
+    t0 = time.perf_counter() - t
+    n = int(n0 * (target_s / max(t0, 1e-3)) ** (1.0 / 3.0)) // 256 * 256
+    n = max(n0, min(n, 16384))
+    X, y, Xs = nfir_train_test(n, n // 4)
+    t = time.perf_counter()
+    oracle.predict(X, y, Xs, h, want=("mean", "cov"))
+    dt = time.perf_counter() - t
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": path_flops(n, n // 4) / dt / 1e9, "unit": "GFLOP/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"oracle predict (mean + full covariance), n={n}, n_test={n // 4}, D=8, "
+                      f"one run of {dt:.1f} s"}
+
+
+def error_check(ctx, K, X, y, Xs, mean, h, Xd, yd):
+    """Errors at the benchmark size from outputs the oracle computes one by
+    one: the residual of K alpha = y and sampled predictive means."""
+    import numpy as np
+    import oracle
+    import torch
+    alpha = ctx.solve(K, yd)
+    torch.cuda.synchronize()
+    a = alpha.cpu().numpy()
+    m = mean.cpu().numpy()
+    rng = np.random.default_rng(3)
+    idx = rng.choice(len(Xs), 128, replace=False)
+    m_ref = oracle.kernel_matrix(Xs[idx], X, h) @ a
+    rows = rng.choice(len(X), 256, replace=False)
+    r = y[rows] - (oracle.kernel_matrix(X[rows], X, h) @ a + h[2] * a[rows])
+    return {"rel_mean_sampled": float(np.linalg.norm(m[idx] - m_ref) / np.linalg.norm(m_ref)),
+            "rel_residual_sampled_rows": float(np.linalg.norm(r) / np.linalg.norm(y[rows]))}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=16384)
+    ap.add_argument("--n-test", type=int, default=4096)
+    ap.add_argument("--tile", type=int, default=512)
+    ap.add_argument("--precision", default="fp64", choices=["fp64"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-check", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs the GP hot path on one GPU only; "
+              "multi-GPU sharding is a design note, not a measured path (use --gpus 1)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from gpr_inputs import DEFAULT_HYPER, nfir_train_test
+    from paper_2602_19683_amd import Context
+
+    n, ns, tile, D = args.n, args.n_test, args.tile, 8
+    h = DEFAULT_HYPER
+    log(f"bench: n={n} n_test={ns} tile={tile} precision={args.precision} "
+        f"steps={args.steps} warmup={args.warmup}")
+    X, y, Xs = nfir_train_test(n, ns, D)
+    dev = lambda a: torch.from_numpy(a).to("cuda:0")
+    Xd, yd, Xsd = dev(X), dev(y), dev(Xs)
+    mean = torch.empty(ns, dtype=torch.float64, device="cuda:0")
+    cov = torch.empty(ns, ns, dtype=torch.float64, device="cuda:0")
+    ctx = Context(0)
+    K = ctx.assemble(Xd, h, tile)
+
+    def step():
+        ctx.assemble(Xd, h, tile, K=K)
+        ctx.cholesky(K, args.precision)
+        ctx.predict(K, Xd, yd, Xsd, h, mean=mean, cov=cov)
+
+    for i in range(args.warmup):
+        step()
+        ctx.sync()
+        log(f"warmup step {i + 1}/{args.warmup} done")
+    ctx.profile(True)
+    ctx.profile_read(reset=True)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t_wall = time.perf_counter()
+    e0.record()
+    for _ in range(args.steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t_wall
+    ctx.sync()
+    ms = e0.elapsed_time(e1) / args.steps
+    prof = ctx.profile_read(reset=True)
+    ctx.profile(False)
+    log(f"timed {args.steps} steps: {ms:.3f} ms/step (wall {t_wall / args.steps * 1e3:.3f})")
+    for k, (nl, tms, fl, by) in prof.items():
+        rate = f"{fl / (tms * 1e-3) / 1e12:7.2f} TFLOP/s" if fl and tms else \
+               (f"{by / (tms * 1e-3) / 1e9:7.1f} GB/s" if by and tms else "")
+        log(f"  {k:9s} launches/step {nl / args.steps:7.1f}  ms/step {tms / args.steps:8.3f}  {rate}")
+
+    flops = path_flops(n, ns)
+    value = flops / (ms * 1e-3) / 1e9
+    nl, tms, fl, _ = prof["update"]
+    achieved = fl / (tms * 1e-3) / 1e12 if tms else 0.0
+    roofline = {"bound": "mfma", "kernel": "k_update_f64 (GEMM/SYRK tile updates)",
+                "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None,
+                "avg_launch_ms": round(tms / max(nl, 1), 4),
+                "flops_per_launch": round(fl / max(nl, 1), 1)}
+    errors = None
+    if not args.no_check:
+        errors = error_check(ctx, K, X, y, Xs, mean, h, Xd, yd)
+        log(f"errors: {errors}")
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(h)
+        log(f"cpu baseline: {cpu}")
+    out = {
+        "metric": METRIC, "value": round(value, 2), "unit": "GFLOP/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"exact GP, SE kernel: assembly + tiled Cholesky + mean + full "
+                               f"covariance, n={n}, n_test={ns}, D={D}, tile {tile}, "
+                               f"{args.precision}",
+                   "n": n, "n_test": ns, "D": D, "tile": tile, "precision": args.precision,
+                   "parallelism": "single GPU"},
+        "pct_fp64_peak": round(100 * value / (FP64_PEAK_TFLOPS * 1e3), 2),
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "errors": errors,
+        "phases_ms_per_step": {k: round(v[1] / args.steps, 4) for k, v in prof.items()},
+    }
+    print(json.dumps(out), flush=True)
+    K.free()
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,244 @@
+/*
+ * gpr.h -- C ABI of libgpr, an MI355X (gfx950) library for exact Gaussian-
+ * process regression with the squared-exponential kernel.
+ *
+ * What it computes (Sec. 4.1 of the paper):
+ *   k(a, b) = v * exp(-sum_d (a_d - b_d)^2 / (2 l))            eq. (1)
+ *   K = k(X, X) + sigma^2 I        (noise by index, training set only)
+ *   mean = K_{X*,X} K^{-1} y                                   eq. (2)
+ *   cov  = K_{X*,X*} - K_{X*,X} K^{-1} K_{X,X*}                 eq. (3)
+ * through the Cholesky factor K = L L^T, computed with the right-looking
+ * tiled algorithm of Sec. 4.2 (Fig. 1: POTRF, TRSM, SYRK and GEMM tile tasks),
+ * followed by the triangular solves L beta = y, L^T alpha = beta, and
+ * L V = K_{X,X*}, W = V^T V.
+ *
+ * Readings taken where the paper is silent or garbled:
+ *   - eq. (1) divides by 2 l, as printed (l acts as a squared lengthscale);
+ *   - the noise term is an index Kronecker delta on the training set only, so
+ *     k(X*, X) and k(X*, X*) carry no noise and cov is the latent posterior;
+ *   - the hyperparameters are (l, v, sigma^2), sigma^2 a variance;
+ *   - the TRSM of Fig. 1 is L_IJ = K_IJ L_JJ^{-T}, the operation that makes
+ *     K = L L^T hold for row-major lower tiles;
+ *   - everything is row-major and 0-based (Sec. 4.3).
+ *
+ * Conventions for every call:
+ *   - matrices are row-major double arrays; X is n x D, Xs is n_test x D;
+ *   - pointers to data are DEVICE pointers unless stated otherwise; the
+ *     caller owns them and keeps them alive until the stream reaches the call;
+ *   - `stream` is a hipStream_t (NULL = the null stream); all work is
+ *     stream-ordered and asynchronous to the host unless stated; calls on one
+ *     context are additionally ordered among themselves, whatever stream
+ *     they use;
+ *   - the library owns gpr_ctx, gpr_tiled and its workspace;
+ *   - return value: GPR_OK or a negative error code. Argument errors are
+ *     detected on the host before any work is queued. A non-positive-definite
+ *     pivot is found on the device: it is reported through `info_dev` and by
+ *     gpr_sync (GPR_ENOTPD), never by the call that queued the work.
+ *   - sizes: n >= 1 training points; any n is accepted. Internally the
+ *     problem is padded to a whole number of tiles (K with an identity block,
+ *     the cross covariance with zeros), which leaves every result unchanged.
+ *     tile must be a multiple of 32 in [32, 1024].
+ */
+#ifndef GPR_H
+#define GPR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GPR_ABI_VERSION 1
+
+/* Status codes. */
+enum {
+    GPR_OK = 0,
+    GPR_ENOTPD = 1,   /* a pivot of the Cholesky factorisation was not > 0 */
+    GPR_EINVAL = -1,  /* bad argument (null pointer, size, hyperparameter)  */
+    GPR_ENOMEM = -2,  /* device allocation failed or exceeded the cap      */
+    GPR_EHIP = -3,    /* a HIP runtime call failed                         */
+    GPR_ENODEV = -4,  /* no usable GPU                                     */
+    GPR_ENOTSUP = -5  /* option not available in this build                */
+};
+
+/* Hyperparameters of eq. (1): lengthscale l, vertical variance v and noise
+ * variance sigma^2 (Sec. 4.1). All must be > 0, except that sigma^2 may be
+ * any finite value (a negative one makes K indefinite, which the Cholesky
+ * then reports as GPR_ENOTPD). */
+typedef struct {
+    double lengthscale;
+    double vertical_variance;
+    double noise_variance;
+} gpr_hyper;
+
+/* Precision of the off-diagonal tile updates (GEMM/SYRK) of the Cholesky and
+ * of the covariance solve. POTRF, TRSM, the vector solves and the residual
+ * of the iterative refinement are always FP64. Mixed modes keep FP64 tile
+ * storage and subtract an FP32 MFMA accumulator into it. */
+typedef enum {
+    GPR_FP64 = 0,
+    GPR_MIXED_FP32 = 1,
+    GPR_MIXED_BF16 = 2
+} gpr_precision;
+
+/* How the tile task graph is executed. GPR_EXEC_STREAMS: batched tile-task
+ * launches on two HIP streams with one step of look-ahead.
+ * GPR_EXEC_PERSISTENT is reserved (GPR_ENOTSUP in this build). */
+typedef enum {
+    GPR_EXEC_STREAMS = 0,
+    GPR_EXEC_PERSISTENT = 1
+} gpr_executor;
+
+typedef struct gpr_ctx gpr_ctx;      /* device, streams, events, workspace   */
+typedef struct gpr_tiled gpr_tiled;  /* lower-tiled symmetric / triangular n x n matrix */
+
+/* Host-side refinement statistics, filled when gpr_predict returns in a
+ * mixed precision (it synchronises the stream in that case). */
+typedef struct {
+    int32_t iters;              /* refinement steps taken                        */
+    double rel_residual;        /* ||y - K alpha||_2 / ||y||_2 after the last one */
+    int32_t fallback_precision; /* precision the factor was finally computed in  */
+} gpr_ir_stats;
+
+/* Tiled-matrix states. */
+enum { GPR_STATE_EMPTY = 0, GPR_STATE_K = 1, GPR_STATE_L = 2 };
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Creates a context on `device` (HIP ordinal). n_streams: number of streams
+ * the executor may use (>= 1; the executor uses at most 2 -- a critical-path
+ * stream and a bulk-update stream -- Sec. 4.3 uses a user-sized pool).
+ * Returns GPR_ENODEV if the device does not exist, GPR_ENOTSUP for an
+ * executor this build lacks. On success *out must later go to
+ * gpr_ctx_destroy. */
+int gpr_ctx_create(gpr_ctx** out, int device, int n_streams, gpr_executor ex);
+
+/* Waits for all work of the context, frees its workspace and the context. */
+int gpr_ctx_destroy(gpr_ctx* ctx);
+
+/* ---- the hot path --------------------------------------------------------- */
+
+/* Assembles K = k(X, X) + sigma^2 I (eq. (1)) into lower tiles of size
+ * tile x tile (Sec. 4.2: only the lower tiles are stored and computed).
+ * X: device, n x D row-major. If *K_inout is NULL a new handle is allocated
+ * (library-owned device memory); otherwise the handle is reused and must have
+ * been made with the same n and tile. Afterwards the handle holds K. */
+int gpr_assemble(gpr_ctx* ctx, const double* X, int64_t n, int32_t D,
+                 gpr_hyper h, int32_t tile, gpr_tiled** K_inout, void* stream);
+
+/* Factorises K = L L^T in place with the tiled right-looking algorithm of
+ * Sec. 4.2 (Fig. 1). The handle must hold K (GPR_EINVAL otherwise); it holds
+ * L afterwards, plus the inverse of every diagonal tile of L, which the
+ * solves use. prec chooses the precision of the GEMM/SYRK updates.
+ * info_dev (optional, device int32): set to 0, or to the 1-based global
+ * column of the first pivot that was not > 0 (LAPACK convention); gpr_sync
+ * then returns GPR_ENOTPD. After a failed pivot the factor is garbage. */
+int gpr_cholesky(gpr_ctx* ctx, gpr_tiled* K, gpr_precision prec,
+                 int32_t* info_dev, void* stream);
+
+/* Dense variant for tests: A is n x n row-major (device), only its lower
+ * triangle is read; on return its lower triangle holds L and its strict
+ * upper triangle is zero. Uses the same tile kernels via a scratch handle. */
+int gpr_cholesky_dense(gpr_ctx* ctx, double* A, int64_t n, int32_t tile,
+                       gpr_precision prec, int32_t* info_dev, void* stream);
+
+/* Predictive mean (eq. (2)) and, if cov != NULL, the full posterior
+ * covariance (eq. (3)) at the n_test rows of Xs.
+ * L: handle produced by gpr_cholesky from k(X, X) + sigma^2 I with the same
+ * X, n and h (GPR_EINVAL if it does not hold a factor or n differs).
+ * y: device, n. mean: device, n_test. cov: device, n_test x n_test
+ * row-major, both triangles written (exactly symmetric), or NULL.
+ * n_test == 0 is a no-op. In a mixed precision the mean is recovered by FP64
+ * iterative refinement (stop at ||r|| / ||y|| <= 1e-14, stagnation, or 50
+ * steps), the call synchronises the stream and fills *ir if non-NULL. */
+int gpr_predict(gpr_ctx* ctx, gpr_tiled* L, const double* X, const double* y,
+                int64_t n, const double* Xs, int64_t n_test, int32_t D,
+                gpr_hyper h, double* mean, double* cov, gpr_ir_stats* ir,
+                void* stream);
+
+/* x = K^{-1} b through the factor: forward substitution L beta = b, then
+ * backward substitution L^T x = beta (the solve recipe after eq. (2)).
+ * L: handle holding a factor; b, x: device vectors of length n (may alias).
+ */
+int gpr_solve(gpr_ctx* ctx, gpr_tiled* L, const double* b, double* x, void* stream);
+
+/* Negative log marginal likelihood
+ *   NLML = 1/2 y^T K^{-1} y + 1/2 log det K + n/2 log(2 pi)
+ * and its gradient with respect to (l, v, sigma^2), from a Cholesky adjoint
+ * (reverse sweep over the tile tasks) and the solve adjoint.
+ * out_nlml: device, 1 double. out_grad3: device, 3 doubles (may be NULL to
+ * skip the gradient). Returns GPR_ENOTSUP until the adjoint kernels exist. */
+int gpr_nlml_grad(gpr_ctx* ctx, const double* X, const double* y, int64_t n,
+                  int32_t D, gpr_hyper h, int32_t tile, gpr_precision prec,
+                  double* out_nlml, double* out_grad3, void* stream);
+
+/* ---- handles and utilities ----------------------------------------------- */
+
+/* Shape and state of a handle (host call, no device work); any out pointer
+ * may be NULL. */
+int gpr_tiled_info(const gpr_tiled* T, int64_t* n, int32_t* tile,
+                   int32_t* state);
+
+/* Copies the handle into a dense n x n row-major device array. For a factor
+ * (state L) the strict upper triangle is written as 0; for K both triangles
+ * are written (mirrored from the stored lower tiles). */
+int gpr_tiled_to_dense(gpr_ctx* ctx, const gpr_tiled* T, double* out,
+                       void* stream);
+
+/* Frees a handle (waits for the device to finish with it first). */
+int gpr_tiled_free(gpr_tiled* T);
+
+/* Blocks until `stream` has finished the context's queued work, then
+ * returns GPR_ENOTPD if any factorisation queued since the previous gpr_sync
+ * hit a non-positive pivot (its column in *column if non-NULL, else 0),
+ * GPR_OK otherwise. */
+int gpr_sync(gpr_ctx* ctx, void* stream, int64_t* column);
+
+/* ---- instrumentation ------------------------------------------------------
+ * Per-kernel timers (the role APEX plays in Sec. 3.1): while enabled, every
+ * launch the context issues is bracketed by HIP timing events on the stream
+ * it runs on. Kinds: 0 POTRF (with the diagonal-tile inverse), 1 TRSM,
+ * 2 tile update (GEMM / SYRK), 3 assembly, 4 triangular-solve GEMV,
+ * 5 kernel matvec (mean / residual), 6 export to dense. */
+int gpr_profile_enable(gpr_ctx* ctx, int on);
+
+/* Totals for one kind over the launches recorded since the last reset:
+ * number of launches, summed device time in ms, and summed algorithmic
+ * flops (GEMM tile 2 m^3, SYRK / TRSM tile m^3, POTRF + inverse 2 m^3 / 3,
+ * GEMV tile 2 m^2, kernel matvec 2 per entry) and bytes (assembly and export:
+ * bytes written). Blocks until the recorded work is done. reset != 0 clears
+ * all kinds after reading. Any out pointer may be NULL. */
+int gpr_profile_read(gpr_ctx* ctx, int kind, int64_t* launches, double* total_ms,
+                     double* flops, double* bytes, int reset);
+
+/* Static description of a status code. */
+const char* gpr_strerror(int status);
+
+/* ---- schedule introspection (host only, no device needed) -----------------
+ * The executor turns the tile task graph into a list of batched launches on
+ * two streams. This call returns that list for M training tile rows and
+ * Mhat test tile rows without running anything, so the schedule can be
+ * checked on a machine without a GPU.
+ * mode: 0 = Cholesky only, 1 = covariance solve with a given factor
+ * (rows M..M+Mhat-1 only), 2 = both in one sweep.
+ * tasks: host array of 5 int32 per task: kind (0 POTRF, 1 TRSM, 2 SYRK,
+ * 3 GEMM), I, K, J, launch index. Tile (I, K) is the one written; for POTRF
+ * I = K = J, for TRSM K = J. Rows I >= M are test rows.
+ * launches: host array of 3 int32 per launch: stream (0 critical, 1 bulk),
+ * index of the last launch on the other stream that must finish before it
+ * starts (-1 if none), and the task kind it runs.
+ * Capacities are in records; counts are always written. Returns
+ * GPR_EINVAL if a capacity is too small (counts still written). */
+int gpr_schedule_describe(int32_t M, int32_t Mhat, int32_t mode,
+                          int32_t* tasks, int64_t task_cap, int64_t* n_tasks,
+                          int32_t* launches, int64_t launch_cap,
+                          int64_t* n_launches);
+
+/* ABI version of the loaded library (GPR_ABI_VERSION it was built with). */
+int gpr_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GPR_H */

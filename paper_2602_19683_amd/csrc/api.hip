@@ -1,0 +1,738 @@
+// api.hip -- C entry points of libgpr: context, tiled handles, and the
+// executor that runs the tile schedule (schedule.cpp) on two HIP streams.
+//
+// Memory layout in HBM (n padded up to M m, test size up to Mhat m):
+//   K / L      lower tiles, M (M + 1) / 2 tiles of m x m, tile-contiguous
+//              row-major (Sec. 4.2: only the lower tiles are stored);
+//   Tinv       M tiles, the inverses of the diagonal tiles of L;
+//   V^T        Mhat x M tiles of K_{X*,X} solved in place into K_{X*,X} L^{-T};
+//   Sigma      Mhat (Mhat + 1) / 2 lower tiles, exported to the caller's
+//              dense row-major n_test x n_test array with both triangles;
+//   vectors    y, beta, alpha padded to M m.
+// Task descriptors for every launch of a call are built on the host, copied
+// to the device in one transfer, and the launches index into them.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "gpr_internal.h"
+
+using namespace gpr;
+
+struct gpr_ctx {
+    int device = 0;
+    hipStream_t bulk = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_last = nullptr, ev_desc = nullptr;
+    bool last_valid = false, desc_valid = false;
+    std::vector<hipEvent_t> evpool;
+    int* d_info = nullptr;        // [0]: this factorisation, [1]: sticky since gpr_sync
+    char* d_desc = nullptr;
+    size_t desc_cap = 0;
+    char* h_desc = nullptr;       // pinned staging
+    size_t hdesc_cap = 0;
+    char* d_ws = nullptr;         // prediction workspace
+    size_t ws_cap = 0;
+    gpr_tiled* scratch = nullptr; // for gpr_cholesky_dense
+    // instrumentation
+    bool prof_on = false;
+    std::vector<hipEvent_t> tpool;  // timing events, reused after each read
+    size_t tpool_used = 0;
+    struct ProfRec {
+        int kind;
+        hipEvent_t a, b;
+        double flops, bytes;
+    };
+    std::vector<ProfRec> pending;
+    int64_t p_launches[8] = {};
+    double p_ms[8] = {}, p_flops[8] = {}, p_bytes[8] = {};
+};
+
+struct gpr_tiled {
+    int device = 0;
+    int64_t n = 0;
+    int m = 0;
+    int M = 0;
+    double* data = nullptr;
+    double* tinv = nullptr;
+    int state = GPR_STATE_EMPTY;
+    int prec = GPR_FP64;
+};
+
+namespace {
+
+#define HIP_TRY(expr)                                 \
+    do {                                              \
+        if ((expr) != hipSuccess) return GPR_EHIP;    \
+    } while (0)
+
+int check_device(int device)
+{
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return GPR_ENODEV;
+    if (device < 0 || device >= count) return GPR_ENODEV;
+    if (hipSetDevice(device) != hipSuccess) return GPR_EHIP;
+    return GPR_OK;
+}
+
+bool valid_tile(int32_t tile) { return tile >= 32 && tile <= 1024 && tile % 32 == 0; }
+
+bool valid_hyper(const gpr_hyper& h)
+{
+    return std::isfinite(h.lengthscale) && std::isfinite(h.vertical_variance) &&
+           std::isfinite(h.noise_variance) && h.lengthscale > 0 && h.vertical_variance > 0;
+}
+
+int ensure_device_bytes(char** p, size_t* cap, size_t need)
+{
+    if (need <= *cap) return GPR_OK;
+    if (*p) {
+        if (hipDeviceSynchronize() != hipSuccess) return GPR_EHIP;
+        (void)hipFree(*p);
+        *p = nullptr;
+        *cap = 0;
+    }
+    size_t want = need + need / 4;
+    if (hipMalloc(reinterpret_cast<void**>(p), want) != hipSuccess) {
+        (void)hipGetLastError();
+        return GPR_ENOMEM;
+    }
+    *cap = want;
+    return GPR_OK;
+}
+
+// Host-side builder for the task descriptors of one call. Each segment is
+// 64-byte aligned; `upload` copies everything to the device in one transfer.
+struct DescBuffer {
+    std::vector<char> host;
+    size_t add(const void* data, size_t bytes)
+    {
+        size_t off = (host.size() + 63) & ~size_t(63);
+        host.resize(off + bytes);
+        if (bytes) std::memcpy(host.data() + off, data, bytes);
+        return off;
+    }
+    int upload(gpr_ctx* ctx, hipStream_t s)
+    {
+        if (host.empty()) return GPR_OK;
+        const size_t bytes = host.size();
+        if (ctx->desc_valid) HIP_TRY(hipEventSynchronize(ctx->ev_desc));
+        if (bytes > ctx->hdesc_cap) {
+            if (ctx->h_desc) (void)hipHostFree(ctx->h_desc);
+            ctx->h_desc = nullptr;
+            ctx->hdesc_cap = 0;
+            if (hipHostMalloc(reinterpret_cast<void**>(&ctx->h_desc), bytes * 2) != hipSuccess)
+                return GPR_ENOMEM;
+            ctx->hdesc_cap = bytes * 2;
+        }
+        int rc = ensure_device_bytes(&ctx->d_desc, &ctx->desc_cap, bytes);
+        if (rc) return rc;
+        std::memcpy(ctx->h_desc, host.data(), bytes);
+        HIP_TRY(hipMemcpyAsync(ctx->d_desc, ctx->h_desc, bytes, hipMemcpyHostToDevice, s));
+        HIP_TRY(hipEventRecord(ctx->ev_desc, s));
+        ctx->desc_valid = true;
+        return GPR_OK;
+    }
+    template <class T>
+    const T* dev(gpr_ctx* ctx, size_t off) const
+    {
+        return reinterpret_cast<const T*>(ctx->d_desc + off);
+    }
+};
+
+int ensure_events(gpr_ctx* ctx, size_t n)
+{
+    while (ctx->evpool.size() < n) {
+        hipEvent_t e;
+        HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        ctx->evpool.push_back(e);
+    }
+    return GPR_OK;
+}
+
+enum ProfKind { PK_POTRF = 0, PK_TRSM = 1, PK_UPDATE = 2, PK_ASSEMBLE = 3, PK_GEMV = 4,
+                PK_MATVEC = 5, PK_EXPORT = 6 };
+
+hipEvent_t timing_event(gpr_ctx* ctx)
+{
+    if (ctx->tpool_used == ctx->tpool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        ctx->tpool.push_back(e);
+    }
+    return ctx->tpool[ctx->tpool_used++];
+}
+
+// Brackets one launch with timing events while profiling is on.
+struct ProfScope {
+    gpr_ctx* c;
+    hipStream_t s;
+    int kind;
+    double flops, bytes;
+    hipEvent_t a = nullptr;
+    ProfScope(gpr_ctx* c_, hipStream_t s_, int k, double f, double b)
+        : c(c_), s(s_), kind(k), flops(f), bytes(b)
+    {
+        if (c->prof_on && (a = timing_event(c)) != nullptr) (void)hipEventRecord(a, s);
+    }
+    ~ProfScope()
+    {
+        if (!a) return;
+        hipEvent_t b = timing_event(c);
+        if (!b) return;
+        (void)hipEventRecord(b, s);
+        c->pending.push_back({kind, a, b, flops, bytes});
+    }
+};
+
+int resolve_profile(gpr_ctx* ctx)
+{
+    for (const auto& r : ctx->pending) {
+        HIP_TRY(hipEventSynchronize(r.b));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, r.a, r.b));
+        ctx->p_launches[r.kind] += 1;
+        ctx->p_ms[r.kind] += ms;
+        ctx->p_flops[r.kind] += r.flops;
+        ctx->p_bytes[r.kind] += r.bytes;
+    }
+    ctx->pending.clear();
+    ctx->tpool_used = 0;
+    return GPR_OK;
+}
+
+// Start of every call: order after the previous call of this context.
+int begin_call(gpr_ctx* ctx, hipStream_t s)
+{
+    int rc = check_device(ctx->device);
+    if (rc) return rc;
+    if (ctx->last_valid) HIP_TRY(hipStreamWaitEvent(s, ctx->ev_last, 0));
+    return GPR_OK;
+}
+
+int end_call(gpr_ctx* ctx, hipStream_t s)
+{
+    HIP_TRY(hipEventRecord(ctx->ev_last, s));
+    ctx->last_valid = true;
+    return GPR_OK;
+}
+
+// Pointers of the extended lower-tiled matrix used by the sweep.
+struct SweepMats {
+    TileMat K;        // training lower tiles
+    double* tinv;     // M tiles
+    TileMat V;        // Mhat x M
+    TileMat S;        // Mhat lower tiles
+    int M, Mhat, m;
+    double* at(int I, int K_) const
+    {
+        if (I < M) return tile_ptr(K, I, K_);
+        if (K_ < M) return tile_ptr(V, I - M, K_);
+        return tile_ptr(S, I - M, K_ - M);
+    }
+};
+
+struct SweepPlan {
+    Schedule sched;
+    std::vector<size_t> off;  // descriptor offset per launch
+};
+
+// Builds the descriptors of a sweep into `db`.
+SweepPlan plan_sweep(const SweepMats& X, int mode, DescBuffer& db)
+{
+    SweepPlan P;
+    P.sched = build_schedule(X.M, X.Mhat, mode);
+    P.off.assign(P.sched.launches.size(), 0);
+    const int m = X.m;
+    for (size_t li = 0; li < P.sched.launches.size(); ++li) {
+        const SchedLaunch& L = P.sched.launches[li];
+        if (L.kind == LK_TRSM) {
+            std::vector<TrsmTask> v;
+            for (int t = L.first; t < L.first + L.count; ++t) {
+                const SchedTask& k = P.sched.tasks[t];
+                v.push_back({X.at(k.I, k.J), X.tinv + (size_t)k.J * m * m, m, m});
+            }
+            P.off[li] = db.add(v.data(), v.size() * sizeof(TrsmTask));
+        } else if (L.kind == LK_UPDATE) {
+            std::vector<UpdateTask> v;
+            for (int t = L.first; t < L.first + L.count; ++t) {
+                const SchedTask& k = P.sched.tasks[t];
+                v.push_back({X.at(k.I, k.K), X.at(k.I, k.J), X.at(k.K, k.J), m, m, m,
+                             k.kind == K_SYRK ? TASK_DIAG : 0});
+            }
+            P.off[li] = db.add(v.data(), v.size() * sizeof(UpdateTask));
+        }
+    }
+    return P;
+}
+
+// Issues the launches of a planned sweep: critical stream = s, bulk stream =
+// ctx->bulk, forked from and joined back into s.
+int run_sweep(gpr_ctx* ctx, const SweepMats& X, const SweepPlan& P, const DescBuffer& db,
+              hipStream_t s)
+{
+    const auto& Ls = P.sched.launches;
+    int rc = ensure_events(ctx, Ls.size());
+    if (rc) return rc;
+    std::vector<char> waited(Ls.size(), 0);
+    for (const auto& L : Ls)
+        if (L.wait >= 0) waited[L.wait] = 1;
+    HIP_TRY(hipEventRecord(ctx->ev_fork, s));
+    HIP_TRY(hipStreamWaitEvent(ctx->bulk, ctx->ev_fork, 0));
+    const int m = X.m;
+    for (size_t li = 0; li < Ls.size(); ++li) {
+        const SchedLaunch& L = Ls[li];
+        hipStream_t st = L.stream == 0 ? s : ctx->bulk;
+        if (L.wait >= 0) HIP_TRY(hipStreamWaitEvent(st, ctx->evpool[L.wait], 0));
+        const double m3 = (double)m * m * m;
+        if (L.kind == LK_POTRF) {
+            const int J = L.step;
+            double* A = X.at(J, J);
+            double* Ti = X.tinv + (size_t)J * m * m;
+            ProfScope ps(ctx, st, PK_POTRF, 2.0 * m3 / 3.0, 0.0);
+            HIP_TRY(launch_potrf_f64(A, m, m, Ti, m, ctx->d_info, (int64_t)J * m, st));
+            HIP_TRY(launch_trtri_f64(A, m, Ti, m, m, st));
+        } else if (L.kind == LK_TRSM) {
+            ProfScope ps(ctx, st, PK_TRSM, L.count * m3, 0.0);
+            HIP_TRY(launch_trsm_f64(db.dev<TrsmTask>(ctx, P.off[li]), L.count, m, st));
+        } else {
+            double f = 0.0;
+            for (int t = L.first; t < L.first + L.count; ++t)
+                f += P.sched.tasks[t].kind == K_SYRK ? m3 : 2.0 * m3;
+            ProfScope ps(ctx, st, PK_UPDATE, f, 0.0);
+            HIP_TRY(launch_update_f64(db.dev<UpdateTask>(ctx, P.off[li]), L.count, m, st));
+        }
+        if (waited[li]) HIP_TRY(hipEventRecord(ctx->evpool[li], st));
+    }
+    HIP_TRY(hipEventRecord(ctx->ev_join, ctx->bulk));
+    HIP_TRY(hipStreamWaitEvent(s, ctx->ev_join, 0));
+    return GPR_OK;
+}
+
+int alloc_tiled(gpr_ctx* ctx, int64_t n, int m, gpr_tiled** out)
+{
+    gpr_tiled* T = new (std::nothrow) gpr_tiled;
+    if (!T) return GPR_ENOMEM;
+    T->device = ctx->device;
+    T->n = n;
+    T->m = m;
+    T->M = (int)((n + m - 1) / m);
+    const size_t tiles = (size_t)T->M * (T->M + 1) / 2;
+    if (hipMalloc(reinterpret_cast<void**>(&T->data), tiles * m * m * sizeof(double)) != hipSuccess) {
+        (void)hipGetLastError();
+        delete T;
+        return GPR_ENOMEM;
+    }
+    *out = T;
+    return GPR_OK;
+}
+
+TileMat kmat(const gpr_tiled* T) { return TileMat{T->data, T->m, 0, 0}; }
+
+// Vector solves with the factor: beta = L^{-1} r, alpha = L^{-T} beta.
+// r, beta, alpha are device vectors of length M m; r is overwritten.
+struct SolvePlan {
+    std::vector<size_t> off;  // per launch
+    std::vector<int> count;
+};
+
+SolvePlan plan_solves(const gpr_tiled* L, double* r, double* beta, double* alpha, DescBuffer& db)
+{
+    SolvePlan P;
+    const int M = L->M, m = L->m;
+    const TileMat Km = kmat(L);
+    auto add = [&](const std::vector<GemvTask>& v) {
+        P.off.push_back(db.add(v.data(), v.size() * sizeof(GemvTask)));
+        P.count.push_back((int)v.size());
+    };
+    for (int J = 0; J < M; ++J) {  // forward
+        add({GemvTask{L->tinv + (size_t)J * m * m, r + (size_t)J * m, beta + (size_t)J * m, m, 0, 1, 0}});
+        std::vector<GemvTask> up;
+        for (int K = J + 1; K < M; ++K)
+            up.push_back({tile_ptr(Km, K, J), beta + (size_t)J * m, r + (size_t)K * m, m, 0, 0, 0});
+        if (!up.empty()) add(up);
+    }
+    for (int J = M - 1; J >= 0; --J) {  // backward, in place on beta
+        add({GemvTask{L->tinv + (size_t)J * m * m, beta + (size_t)J * m, alpha + (size_t)J * m, m, 1, 1, 0}});
+        std::vector<GemvTask> up;
+        for (int K = 0; K < J; ++K)
+            up.push_back({tile_ptr(Km, J, K), alpha + (size_t)J * m, beta + (size_t)K * m, m, 1, 0, 0});
+        if (!up.empty()) add(up);
+    }
+    return P;
+}
+
+int run_solves(gpr_ctx* ctx, const gpr_tiled* L, const SolvePlan& P, const DescBuffer& db,
+               hipStream_t s)
+{
+    const double m2 = (double)L->m * L->m;
+    for (size_t i = 0; i < P.off.size(); ++i) {
+        ProfScope ps(ctx, s, PK_GEMV, 2.0 * m2 * P.count[i], 0.0);
+        HIP_TRY(launch_gemv_f64(db.dev<GemvTask>(ctx, P.off[i]), P.count[i], L->m, s));
+    }
+    return GPR_OK;
+}
+
+int finish_info(gpr_ctx* ctx, int32_t* info_dev, hipStream_t s);
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+
+__global__ void k_info_finish(int* info, int32_t* out)
+{
+    if (info[0] > 0 && info[1] == 0) info[1] = info[0];
+    if (out) *out = info[0];
+}
+
+namespace {
+int finish_info(gpr_ctx* ctx, int32_t* info_dev, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_info_finish, dim3(1), dim3(1), 0, s, ctx->d_info, info_dev);
+    return hipGetLastError() == hipSuccess ? GPR_OK : GPR_EHIP;
+}
+}  // namespace
+
+extern "C" {
+
+int gpr_abi_version(void) { return GPR_ABI_VERSION; }
+
+const char* gpr_strerror(int status)
+{
+    switch (status) {
+    case GPR_OK: return "success";
+    case GPR_ENOTPD: return "matrix is not positive definite (non-positive Cholesky pivot)";
+    case GPR_EINVAL: return "invalid argument";
+    case GPR_ENOMEM: return "device allocation failed";
+    case GPR_EHIP: return "HIP runtime error";
+    case GPR_ENODEV: return "no usable GPU device";
+    case GPR_ENOTSUP: return "not supported by this build";
+    default: return "unknown status";
+    }
+}
+
+int gpr_ctx_create(gpr_ctx** out, int device, int n_streams, gpr_executor ex)
+{
+    if (!out || n_streams < 1) return GPR_EINVAL;
+    *out = nullptr;
+    if (ex != GPR_EXEC_STREAMS && ex != GPR_EXEC_PERSISTENT) return GPR_EINVAL;
+    int rc = check_device(device);
+    if (rc) return rc;
+    if (ex == GPR_EXEC_PERSISTENT) return GPR_ENOTSUP;
+    gpr_ctx* c = new (std::nothrow) gpr_ctx;
+    if (!c) return GPR_ENOMEM;
+    c->device = device;
+    bool ok = hipStreamCreateWithFlags(&c->bulk, hipStreamNonBlocking) == hipSuccess &&
+              hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) == hipSuccess &&
+              hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) == hipSuccess &&
+              hipEventCreateWithFlags(&c->ev_last, hipEventDisableTiming) == hipSuccess &&
+              hipEventCreateWithFlags(&c->ev_desc, hipEventDisableTiming) == hipSuccess &&
+              hipMalloc(reinterpret_cast<void**>(&c->d_info), 2 * sizeof(int)) == hipSuccess &&
+              hipMemset(c->d_info, 0, 2 * sizeof(int)) == hipSuccess;
+    if (!ok) {
+        gpr_ctx_destroy(c);
+        return GPR_EHIP;
+    }
+    *out = c;
+    return GPR_OK;
+}
+
+int gpr_ctx_destroy(gpr_ctx* c)
+{
+    if (!c) return GPR_EINVAL;
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    if (c->scratch) gpr_tiled_free(c->scratch);
+    for (auto e : c->evpool) (void)hipEventDestroy(e);
+    for (auto e : c->tpool) (void)hipEventDestroy(e);
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+    if (c->ev_last) (void)hipEventDestroy(c->ev_last);
+    if (c->ev_desc) (void)hipEventDestroy(c->ev_desc);
+    if (c->bulk) (void)hipStreamDestroy(c->bulk);
+    if (c->d_info) (void)hipFree(c->d_info);
+    if (c->d_desc) (void)hipFree(c->d_desc);
+    if (c->h_desc) (void)hipHostFree(c->h_desc);
+    if (c->d_ws) (void)hipFree(c->d_ws);
+    delete c;
+    return GPR_OK;
+}
+
+int gpr_assemble(gpr_ctx* ctx, const double* X, int64_t n, int32_t D, gpr_hyper h, int32_t tile,
+                 gpr_tiled** K_inout, void* stream)
+{
+    if (!ctx || !X || !K_inout || n < 1 || D < 1 || !valid_tile(tile) || !valid_hyper(h))
+        return GPR_EINVAL;
+    if (*K_inout && ((*K_inout)->n != n || (*K_inout)->m != tile)) return GPR_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int rc = begin_call(ctx, s);
+    if (rc) return rc;
+    gpr_tiled* K = *K_inout;
+    if (!K) {
+        rc = alloc_tiled(ctx, n, tile, &K);
+        if (rc) return rc;
+    }
+    hipError_t e;
+    {
+        ProfScope ps(ctx, s, PK_ASSEMBLE, 0.0,
+                     (double)K->M * (K->M + 1) / 2 * (double)K->m * K->m * sizeof(double));
+        e = launch_assemble(kmat(K), K->M, X, n, X, n, D, h.lengthscale, h.vertical_variance,
+                            h.noise_variance, true, true, s);
+    }
+    if (e != hipSuccess) {
+        if (!*K_inout) gpr_tiled_free(K);
+        return GPR_EHIP;
+    }
+    K->state = GPR_STATE_K;
+    K->prec = GPR_FP64;
+    *K_inout = K;
+    return end_call(ctx, s);
+}
+
+int gpr_cholesky(gpr_ctx* ctx, gpr_tiled* K, gpr_precision prec, int32_t* info_dev, void* stream)
+{
+    if (!ctx || !K || K->state != GPR_STATE_K || K->device != ctx->device) return GPR_EINVAL;
+    if (prec != GPR_FP64 && prec != GPR_MIXED_FP32 && prec != GPR_MIXED_BF16) return GPR_EINVAL;
+    if (prec != GPR_FP64) return GPR_ENOTSUP;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int rc = begin_call(ctx, s);
+    if (rc) return rc;
+    const int m = K->m, M = K->M;
+    if (!K->tinv) {
+        if (hipMalloc(reinterpret_cast<void**>(&K->tinv), (size_t)M * m * m * sizeof(double)) !=
+            hipSuccess) {
+            (void)hipGetLastError();
+            return GPR_ENOMEM;
+        }
+    }
+    SweepMats X{kmat(K), K->tinv, TileMat{nullptr, m, 1, M}, TileMat{nullptr, m, 0, 0}, M, 0, m};
+    DescBuffer db;
+    SweepPlan P = plan_sweep(X, SWEEP_CHOLESKY, db);
+    rc = db.upload(ctx, s);
+    if (rc) return rc;
+    HIP_TRY(launch_set_int(ctx->d_info, 0, s));
+    rc = run_sweep(ctx, X, P, db, s);
+    if (rc) return rc;
+    rc = finish_info(ctx, info_dev, s);
+    if (rc) return rc;
+    K->state = GPR_STATE_L;
+    K->prec = prec;
+    return end_call(ctx, s);
+}
+
+int gpr_cholesky_dense(gpr_ctx* ctx, double* A, int64_t n, int32_t tile, gpr_precision prec,
+                       int32_t* info_dev, void* stream)
+{
+    if (!ctx || !A || n < 1 || !valid_tile(tile)) return GPR_EINVAL;
+    if (prec != GPR_FP64 && prec != GPR_MIXED_FP32 && prec != GPR_MIXED_BF16) return GPR_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int rc = begin_call(ctx, s);
+    if (rc) return rc;
+    gpr_tiled* T = ctx->scratch;
+    if (T && (T->n != n || T->m != tile)) {
+        gpr_tiled_free(T);
+        T = ctx->scratch = nullptr;
+    }
+    if (!T) {
+        rc = alloc_tiled(ctx, n, tile, &T);
+        if (rc) return rc;
+        ctx->scratch = T;
+    }
+    HIP_TRY(launch_dense_to_tiled(A, n, n, kmat(T), T->M, s));
+    T->state = GPR_STATE_K;
+    rc = end_call(ctx, s);
+    if (rc) return rc;
+    rc = gpr_cholesky(ctx, T, prec, info_dev, stream);
+    if (rc) return rc;
+    rc = begin_call(ctx, s);
+    if (rc) return rc;
+    HIP_TRY(launch_tiled_to_dense(kmat(T), n, A, n, false, s));
+    return end_call(ctx, s);
+}
+
+int gpr_predict(gpr_ctx* ctx, gpr_tiled* L, const double* X, const double* y, int64_t n,
+                const double* Xs, int64_t n_test, int32_t D, gpr_hyper h, double* mean,
+                double* cov, gpr_ir_stats* ir, void* stream)
+{
+    if (!ctx || !L || !X || !y || n < 1 || D < 1 || n_test < 0 || !valid_hyper(h))
+        return GPR_EINVAL;
+    if (L->state != GPR_STATE_L || L->n != n || L->device != ctx->device) return GPR_EINVAL;
+    if (n_test > 0 && (!Xs || !mean)) return GPR_EINVAL;
+    if (n_test == 0) return GPR_OK;
+    if (L->prec != GPR_FP64) return GPR_ENOTSUP;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int rc = begin_call(ctx, s);
+    if (rc) return rc;
+    const int m = L->m, M = L->M;
+    const int Mhat = (int)((n_test + m - 1) / m);
+    const size_t npad = (size_t)M * m;
+    const size_t vec_bytes = 3 * npad * sizeof(double);
+    const size_t v_bytes = cov ? (size_t)Mhat * M * m * m * sizeof(double) : 0;
+    const size_t s_bytes = cov ? (size_t)Mhat * (Mhat + 1) / 2 * m * m * sizeof(double) : 0;
+    rc = ensure_device_bytes(&ctx->d_ws, &ctx->ws_cap, vec_bytes + v_bytes + s_bytes + 256);
+    if (rc) return rc;
+    double* r = reinterpret_cast<double*>(ctx->d_ws);
+    double* beta = r + npad;
+    double* alpha = beta + npad;
+    double* Vb = alpha + npad;
+    double* Sb = reinterpret_cast<double*>(reinterpret_cast<char*>(Vb) + v_bytes);
+
+    DescBuffer db;
+    SolvePlan SP = plan_solves(L, r, beta, alpha, db);
+    SweepMats SM{kmat(L), L->tinv, TileMat{Vb, m, 1, M}, TileMat{Sb, m, 0, 0}, M, Mhat, m};
+    SweepPlan PP;
+    if (cov) PP = plan_sweep(SM, SWEEP_PREDICT, db);
+    rc = db.upload(ctx, s);
+    if (rc) return rc;
+
+    // alpha = K^{-1} y via the two triangular solves (Sec. 4.1)
+    HIP_TRY(launch_copy_f64(y, r, n, (int64_t)npad, s));
+    rc = run_solves(ctx, L, SP, db, s);
+    if (rc) return rc;
+    // mean = K_{X*,X} alpha, eq. (2), without storing K_{X*,X}
+    {
+        ProfScope ps(ctx, s, PK_MATVEC, 2.0 * (double)n_test * (double)n, 0.0);
+        HIP_TRY(launch_kernel_matvec(Xs, n_test, X, n, D, h.lengthscale, h.vertical_variance,
+                                     h.noise_variance, false, alpha, nullptr, mean, s));
+    }
+    if (cov) {
+        // K_{X*,X} tiles (to become V^T) and lower tiles of K_{X*,X*}; no noise
+        {
+            ProfScope ps(ctx, s, PK_ASSEMBLE, 0.0, (double)(v_bytes + s_bytes));
+            HIP_TRY(launch_assemble(SM.V, Mhat, Xs, n_test, X, n, D, h.lengthscale,
+                                    h.vertical_variance, h.noise_variance, false, false, s));
+            HIP_TRY(launch_assemble(SM.S, Mhat, Xs, n_test, Xs, n_test, D, h.lengthscale,
+                                    h.vertical_variance, h.noise_variance, false, false, s));
+        }
+        rc = run_sweep(ctx, SM, PP, db, s);
+        if (rc) return rc;
+        ProfScope ps(ctx, s, PK_EXPORT, 0.0, (double)n_test * n_test * sizeof(double));
+        HIP_TRY(launch_tiled_to_dense(SM.S, n_test, cov, n_test, true, s));
+    }
+    if (ir) {
+        ir->iters = 0;
+        ir->rel_residual = -1.0;
+        ir->fallback_precision = L->prec;
+    }
+    return end_call(ctx, s);
+}
+
+int gpr_solve(gpr_ctx* ctx, gpr_tiled* L, const double* b, double* x, void* stream)
+{
+    if (!ctx || !L || !b || !x || L->state != GPR_STATE_L || L->device != ctx->device)
+        return GPR_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int rc = begin_call(ctx, s);
+    if (rc) return rc;
+    const size_t npad = (size_t)L->M * L->m;
+    rc = ensure_device_bytes(&ctx->d_ws, &ctx->ws_cap, 3 * npad * sizeof(double) + 256);
+    if (rc) return rc;
+    double* r = reinterpret_cast<double*>(ctx->d_ws);
+    double* beta = r + npad;
+    double* alpha = beta + npad;
+    DescBuffer db;
+    SolvePlan SP = plan_solves(L, r, beta, alpha, db);
+    rc = db.upload(ctx, s);
+    if (rc) return rc;
+    HIP_TRY(launch_copy_f64(b, r, L->n, (int64_t)npad, s));
+    rc = run_solves(ctx, L, SP, db, s);
+    if (rc) return rc;
+    HIP_TRY(launch_copy_f64(alpha, x, L->n, L->n, s));
+    return end_call(ctx, s);
+}
+
+int gpr_nlml_grad(gpr_ctx* ctx, const double* X, const double* y, int64_t n, int32_t D,
+                  gpr_hyper h, int32_t tile, gpr_precision prec, double* out_nlml,
+                  double* out_grad3, void* stream)
+{
+    if (!ctx || !X || !y || n < 1 || D < 1 || !valid_tile(tile) || !valid_hyper(h) || !out_nlml)
+        return GPR_EINVAL;
+    (void)prec;
+    (void)out_grad3;
+    (void)stream;
+    return GPR_ENOTSUP;
+}
+
+int gpr_profile_enable(gpr_ctx* ctx, int on)
+{
+    if (!ctx) return GPR_EINVAL;
+    ctx->prof_on = on != 0;
+    return GPR_OK;
+}
+
+int gpr_profile_read(gpr_ctx* ctx, int kind, int64_t* launches, double* total_ms, double* flops,
+                     double* bytes, int reset)
+{
+    if (!ctx || kind < 0 || kind > 6) return GPR_EINVAL;
+    int rc = check_device(ctx->device);
+    if (rc) return rc;
+    rc = resolve_profile(ctx);
+    if (rc) return rc;
+    if (launches) *launches = ctx->p_launches[kind];
+    if (total_ms) *total_ms = ctx->p_ms[kind];
+    if (flops) *flops = ctx->p_flops[kind];
+    if (bytes) *bytes = ctx->p_bytes[kind];
+    if (reset) {
+        for (int k = 0; k < 8; ++k) {
+            ctx->p_launches[k] = 0;
+            ctx->p_ms[k] = ctx->p_flops[k] = ctx->p_bytes[k] = 0.0;
+        }
+    }
+    return GPR_OK;
+}
+
+int gpr_tiled_info(const gpr_tiled* T, int64_t* n, int32_t* tile, int32_t* state)
+{
+    if (!T) return GPR_EINVAL;
+    if (n) *n = T->n;
+    if (tile) *tile = T->m;
+    if (state) *state = T->state;
+    return GPR_OK;
+}
+
+int gpr_tiled_to_dense(gpr_ctx* ctx, const gpr_tiled* T, double* out, void* stream)
+{
+    if (!ctx || !T || !out || T->state == GPR_STATE_EMPTY || T->device != ctx->device)
+        return GPR_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int rc = begin_call(ctx, s);
+    if (rc) return rc;
+    HIP_TRY(launch_tiled_to_dense(kmat(T), T->n, out, T->n, T->state == GPR_STATE_K, s));
+    return end_call(ctx, s);
+}
+
+int gpr_tiled_free(gpr_tiled* T)
+{
+    if (!T) return GPR_EINVAL;
+    (void)hipSetDevice(T->device);
+    (void)hipDeviceSynchronize();
+    if (T->data) (void)hipFree(T->data);
+    if (T->tinv) (void)hipFree(T->tinv);
+    delete T;
+    return GPR_OK;
+}
+
+int gpr_sync(gpr_ctx* ctx, void* stream, int64_t* column)
+{
+    if (!ctx) return GPR_EINVAL;
+    if (column) *column = 0;
+    int rc = check_device(ctx->device);
+    if (rc) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    HIP_TRY(hipStreamSynchronize(s));
+    if (ctx->last_valid) HIP_TRY(hipEventSynchronize(ctx->ev_last));
+    int info[2] = {0, 0};
+    HIP_TRY(hipMemcpy(info, ctx->d_info, sizeof(info), hipMemcpyDeviceToHost));
+    if (info[1] > 0) {
+        if (column) *column = info[1];
+        const int zero = 0;
+        HIP_TRY(hipMemcpy(ctx->d_info + 1, &zero, sizeof(int), hipMemcpyHostToDevice));
+        return GPR_ENOTPD;
+    }
+    return GPR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,142 @@
+// gpr_internal.h -- declarations shared by the libgpr sources (not installed).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+#include "gpr.h"
+
+namespace gpr {
+
+// ---------------------------------------------------------------------------
+// Tile addressing
+// ---------------------------------------------------------------------------
+
+// A grid of m x m row-major tiles, each contiguous (leading dimension m).
+// layout 0: lower tiles of a symmetric / triangular matrix, tile (I, J) with
+//           J <= I at index I (I + 1) / 2 + J  (Sec. 4.2: lower tiles only).
+// layout 1: full rectangular grid with `ncolt` tiles per tile row, tile (I, J)
+//           at index I * ncolt + J.
+struct TileMat {
+    double* base;
+    int m;
+    int layout;
+    int ncolt;
+};
+
+__host__ __device__ inline size_t tile_index(const TileMat& T, int I, int J)
+{
+    return T.layout == 0 ? (size_t)I * (I + 1) / 2 + J : (size_t)I * T.ncolt + J;
+}
+
+__host__ __device__ inline double* tile_ptr(const TileMat& T, int I, int J)
+{
+    return T.base + tile_index(T, I, J) * (size_t)T.m * T.m;
+}
+
+// ---------------------------------------------------------------------------
+// Task descriptors consumed by the batched tile kernels
+// ---------------------------------------------------------------------------
+
+enum : int { TASK_DIAG = 1 };  // symmetric update: only lower 128-blocks needed
+
+// C -= A * B^T on m x m tiles (GEMM of Fig. 1; SYRK when A == B and
+// flags & TASK_DIAG).
+struct UpdateTask {
+    double* C;
+    const double* A;
+    const double* B;
+    int ldc, lda, ldb, flags;
+};
+
+// B := B * Tinv^T in place (TRSM of Fig. 1 written as L_IJ = K_IJ L_JJ^{-T},
+// with Tinv = L_JJ^{-1} lower triangular).
+struct TrsmTask {
+    double* B;
+    const double* Tinv;
+    int ldb, ldt;
+};
+
+// y (-)= op(T) x on one m x m tile; op = transpose if trans; set: y = op(T) x.
+struct GemvTask {
+    const double* T;
+    const double* x;
+    double* y;
+    int ld, trans, set, pad;
+};
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (defined in the k_*.hip files). All return hipError_t of
+// the launch; grid sizes are derived from the arguments.
+// ---------------------------------------------------------------------------
+
+// Assemble `ntiles` tiles of T (lower tiles if layout 0, all if layout 1).
+// Entry (i, j) of the padded matrix: for i < na and j < nb,
+// v exp(-|a_i - b_j|^2 / (2 l)) plus s2 where diag_noise and i == j;
+// otherwise (padding) 1 where identity_pad and i == j, else 0.
+hipError_t launch_assemble(const TileMat& T, int tile_rows, const double* A, int64_t na,
+                           const double* B, int64_t nb, int D, double l, double v,
+                           double s2, bool diag_noise, bool identity_pad,
+                           hipStream_t s);
+
+// Dense row-major n x n (ld) -> lower tiles of T (padding: identity).
+hipError_t launch_dense_to_tiled(const double* A, int64_t n, int64_t lda, const TileMat& T,
+                                 int tile_rows, hipStream_t s);
+
+// Lower tiles of T -> dense row-major n x n (ld). mirror: upper triangle
+// copied from the lower one; else the strict upper triangle is zero.
+hipError_t launch_tiled_to_dense(const TileMat& T, int64_t n, double* out, int64_t ldo,
+                                 bool mirror, hipStream_t s);
+
+hipError_t launch_update_f64(const UpdateTask* d_tasks, int ntask, int m, hipStream_t s);
+hipError_t launch_trsm_f64(const TrsmTask* d_tasks, int ntask, int m, hipStream_t s);
+hipError_t launch_potrf_f64(double* A, int lda, int m, double* Tinv, int ldt, int* info,
+                            int64_t col_base, hipStream_t s);
+hipError_t launch_trtri_f64(const double* L, int lda, double* Tinv, int ldt, int m,
+                            hipStream_t s);
+hipError_t launch_gemv_f64(const GemvTask* d_tasks, int ntask, int m, hipStream_t s);
+
+// out_i = base_i - k(A_i, B) x  (subtract) or out_i = k(A_i, B) x  (base == nullptr),
+// where k(A_i, B) x = sum_j k(a_i, b_j) x_j + (noise ? s2 x_i : 0) over j < nb.
+hipError_t launch_kernel_matvec(const double* A, int64_t na, const double* B, int64_t nb,
+                                int D, double l, double v, double s2, bool noise,
+                                const double* x, const double* base, double* out,
+                                hipStream_t s);
+
+hipError_t launch_set_int(int* p, int value, hipStream_t s);
+hipError_t launch_copy_f64(const double* src, double* dst, int64_t n, int64_t n_pad,
+                           hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Schedule of the tiled sweep (host only; schedule.cpp)
+// ---------------------------------------------------------------------------
+
+enum TaskKind : int { K_POTRF = 0, K_TRSM = 1, K_SYRK = 2, K_GEMM = 3 };
+enum LaunchKind : int { LK_POTRF = 0, LK_TRSM = 1, LK_UPDATE = 2 };
+enum SweepMode : int { SWEEP_CHOLESKY = 0, SWEEP_PREDICT = 1, SWEEP_FUSED = 2 };
+
+struct SchedTask {
+    int kind, I, K, J;
+};
+
+struct SchedLaunch {
+    int stream;      // 0 critical, 1 bulk
+    int wait;        // index of a launch on the other stream to wait for, or -1
+    int kind;        // LaunchKind
+    int first, count;  // task range
+    int step;        // J
+};
+
+struct Schedule {
+    std::vector<SchedTask> tasks;
+    std::vector<SchedLaunch> launches;
+};
+
+// Tile sweep over M training tile rows and Mhat test tile rows (see gpr.h,
+// gpr_schedule_describe).
+Schedule build_schedule(int M, int Mhat, int mode);
+
+}  // namespace gpr

@@ -1,0 +1,265 @@
+"""Python binding of libgpr: argument marshalling for torch tensors on a HIP
+device. Every step of the computation runs in the library's HIP kernels;
+torch only provides device memory and the current stream."""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import (GPR_EXEC_STREAMS, GPR_FP64, GPR_MIXED_BF16, GPR_MIXED_FP32, GPR_OK,
+                   GPR_ENOTPD, GPR_STATE_K, GPR_STATE_L, Hyper, IRStats)
+
+PRECISIONS = {"fp64": GPR_FP64, "fp32": GPR_MIXED_FP32, "bf16": GPR_MIXED_BF16}
+
+
+class GPRError(RuntimeError):
+    def __init__(self, status, where="", column=0):
+        msg = _lib.load().gpr_strerror(status).decode()
+        if column:
+            msg += f" (column {column})"
+        super().__init__(f"{where}: {msg} [status {status}]" if where else msg)
+        self.status = status
+        self.column = column
+
+
+def _check(status, where):
+    if status != GPR_OK:
+        raise GPRError(status, where)
+
+
+def _hyper(h):
+    if isinstance(h, Hyper):
+        return h
+    l, v, s2 = (float(t) for t in h)
+    return Hyper(l, v, s2)
+
+
+def _dev_ptr(t, name, numel=None):
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous float64 tensor on the GPU")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, has {t.numel()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _prec(p):
+    if isinstance(p, str):
+        return PRECISIONS[p]
+    return int(p)
+
+
+class Tiled:
+    """Library-owned lower-tiled n x n matrix (K, then its factor L)."""
+
+    def __init__(self, handle, ctx):
+        self._h = handle
+        self._ctx = ctx
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self):
+        n = ctypes.c_int64()
+        tile = ctypes.c_int32()
+        state = ctypes.c_int32()
+        _check(_lib.load().gpr_tiled_info(self._h, ctypes.byref(n), ctypes.byref(tile),
+                                          ctypes.byref(state)), "gpr_tiled_info")
+        return n.value, tile.value, state.value
+
+    @property
+    def n(self):
+        return self.info()[0]
+
+    @property
+    def tile(self):
+        return self.info()[1]
+
+    @property
+    def state(self):
+        return self.info()[2]
+
+    def free(self):
+        if self._h:
+            _lib.load().gpr_tiled_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Context:
+    """A libgpr context on one GPU (streams, events, workspace)."""
+
+    def __init__(self, device=0, n_streams=2, executor=GPR_EXEC_STREAMS):
+        self._lib = _lib.load()
+        h = ctypes.c_void_p()
+        _check(self._lib.gpr_ctx_create(ctypes.byref(h), int(device), int(n_streams),
+                                        int(executor)), "gpr_ctx_create")
+        self._h = h
+        self.device = device
+
+    def close(self):
+        if self._h:
+            self._lib.gpr_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # ---- hot path -------------------------------------------------------
+    def assemble(self, X, hyper, tile, K=None, stream=None):
+        n, D = X.shape
+        h = ctypes.c_void_p(K.handle.value) if K is not None else ctypes.c_void_p()
+        _check(self._lib.gpr_assemble(self._h, _dev_ptr(X, "X"), n, D, _hyper(hyper), int(tile),
+                                      ctypes.byref(h), _stream(stream)), "gpr_assemble")
+        return K if K is not None else Tiled(h, self)
+
+    def cholesky(self, K, precision="fp64", info=None, stream=None):
+        ip = _dev_ptr_int(info) if info is not None else None
+        _check(self._lib.gpr_cholesky(self._h, K.handle, _prec(precision), ip, _stream(stream)),
+               "gpr_cholesky")
+        return K
+
+    def cholesky_dense(self, A, tile, precision="fp64", info=None, stream=None):
+        n = A.shape[0]
+        ip = _dev_ptr_int(info) if info is not None else None
+        _check(self._lib.gpr_cholesky_dense(self._h, _dev_ptr(A, "A", n * n), n, int(tile),
+                                            _prec(precision), ip, _stream(stream)),
+               "gpr_cholesky_dense")
+        return A
+
+    def predict(self, L, X, y, Xs, hyper, full_cov=True, mean=None, cov=None, stream=None,
+                ir_stats=False):
+        import torch
+        n, D = X.shape
+        ns = Xs.shape[0]
+        if mean is None:
+            mean = torch.empty(ns, dtype=torch.float64, device=X.device)
+        if full_cov and cov is None:
+            cov = torch.empty(ns, ns, dtype=torch.float64, device=X.device)
+        st = IRStats()
+        _check(self._lib.gpr_predict(self._h, L.handle, _dev_ptr(X, "X"), _dev_ptr(y, "y", n), n,
+                                     _dev_ptr(Xs, "Xs"), ns, D, _hyper(hyper),
+                                     _dev_ptr(mean, "mean", ns),
+                                     _dev_ptr(cov, "cov", ns * ns) if full_cov else None,
+                                     ctypes.byref(st), _stream(stream)), "gpr_predict")
+        out = (mean, cov if full_cov else None)
+        if ir_stats:
+            return out + ({"iters": st.iters, "rel_residual": st.rel_residual,
+                           "precision": st.fallback_precision},)
+        return out
+
+    def solve(self, L, b, x=None, stream=None):
+        """x = K^{-1} b with the factor held by L."""
+        import torch
+        n = L.n
+        if x is None:
+            x = torch.empty(n, dtype=torch.float64, device=b.device)
+        _check(self._lib.gpr_solve(self._h, L.handle, _dev_ptr(b, "b", n), _dev_ptr(x, "x", n),
+                                   _stream(stream)), "gpr_solve")
+        return x
+
+    def nlml_grad(self, X, y, hyper, tile, precision="fp64", out_nlml=None, out_grad=None,
+                  stream=None):
+        import torch
+        n, D = X.shape
+        if out_nlml is None:
+            out_nlml = torch.empty(1, dtype=torch.float64, device=X.device)
+        if out_grad is None:
+            out_grad = torch.empty(3, dtype=torch.float64, device=X.device)
+        _check(self._lib.gpr_nlml_grad(self._h, _dev_ptr(X, "X"), _dev_ptr(y, "y", n), n, D,
+                                       _hyper(hyper), int(tile), _prec(precision),
+                                       _dev_ptr(out_nlml, "out_nlml", 1),
+                                       _dev_ptr(out_grad, "out_grad", 3), _stream(stream)),
+               "gpr_nlml_grad")
+        return out_nlml, out_grad
+
+    # ---- instrumentation --------------------------------------------------
+    PROFILE_KINDS = ("potrf", "trsm", "update", "assemble", "gemv", "matvec", "export")
+
+    def profile(self, on=True):
+        _check(self._lib.gpr_profile_enable(self._h, int(bool(on))), "gpr_profile_enable")
+
+    def profile_read(self, reset=True):
+        """{kind: (launches, total_ms, flops, bytes)} since the last reset."""
+        out = {}
+        for k, name in enumerate(self.PROFILE_KINDS):
+            nl = ctypes.c_int64()
+            ms, fl, by = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+            last = reset and k == len(self.PROFILE_KINDS) - 1
+            _check(self._lib.gpr_profile_read(self._h, k, ctypes.byref(nl), ctypes.byref(ms),
+                                              ctypes.byref(fl), ctypes.byref(by), int(last)),
+                   "gpr_profile_read")
+            out[name] = (nl.value, ms.value, fl.value, by.value)
+        return out
+
+    # ---- utilities ------------------------------------------------------
+    def to_dense(self, T, out=None, stream=None):
+        import torch
+        n = T.n
+        if out is None:
+            out = torch.empty(n, n, dtype=torch.float64, device=f"cuda:{self.device}")
+        _check(self._lib.gpr_tiled_to_dense(self._h, T.handle, _dev_ptr(out, "out", n * n),
+                                            _stream(stream)), "gpr_tiled_to_dense")
+        return out
+
+    def sync(self, stream=None, raise_on_error=True):
+        col = ctypes.c_int64()
+        st = self._lib.gpr_sync(self._h, _stream(stream), ctypes.byref(col))
+        if st != GPR_OK and raise_on_error:
+            raise GPRError(st, "gpr_sync", col.value)
+        return st, col.value
+
+
+def _dev_ptr_int(t):
+    import torch
+    if t.dtype != torch.int32 or not t.is_cuda or t.numel() < 1:
+        raise ValueError("info must be an int32 tensor on the GPU")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def schedule_describe(M, Mhat, mode):
+    """Host-only: the batched launch list of the tile sweep (see gpr.h).
+
+    Returns ``(tasks, launches)``: int32 arrays of shape (T, 5) = (kind, I, K,
+    J, launch) and (L, 3) = (stream, wait, launch kind)."""
+    lib = _lib.load()
+    nt = ctypes.c_int64()
+    nl = ctypes.c_int64()
+    st = lib.gpr_schedule_describe(M, Mhat, mode, None, 0, ctypes.byref(nt), None, 0,
+                                   ctypes.byref(nl))
+    if st not in (GPR_OK, _lib.GPR_EINVAL) or nt.value < 0:
+        raise GPRError(st, "gpr_schedule_describe")
+    tasks = np.zeros((nt.value, 5), dtype=np.int32)
+    launches = np.zeros((nl.value, 3), dtype=np.int32)
+    _check(lib.gpr_schedule_describe(M, Mhat, mode,
+                                     tasks.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                     nt.value, ctypes.byref(nt),
+                                     launches.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                     nl.value, ctypes.byref(nl)), "gpr_schedule_describe")
+    return tasks, launches

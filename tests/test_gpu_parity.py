@@ -1,0 +1,285 @@
+"""GPU path vs the CPU oracle, through the C ABI (libgpr.so).
+
+FP64 bar: normwise relative error <= 1e-10 against the double oracle
+(Frobenius norm over the lower triangle for L, 2-norm for the mean,
+Frobenius for the covariance). The achieved figures are printed; they are
+expected near 1e-14. At the full benchmark size (n = 16384, n_test = 4096,
+tile 512) the oracle would take minutes, so the check there uses outputs the
+oracle computes one by one plus properties that hold at any size.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from gpr_inputs import DEFAULT_HYPER, nfir, nfir_train_test, random_spd
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+U = np.finfo(np.float64).eps / 2
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2602_19683_amd import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to("cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+# --------------------------------------------------------------------------
+# assembly (eq. (1))
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,tile,h", [(100, 32, DEFAULT_HYPER), (256, 64, (0.3, 2.0, 0.5)),
+                                      (512, 128, DEFAULT_HYPER), (300, 256, (2.0, 0.7, 0.01))])
+def test_assemble_matches_oracle(ctx, n, tile, h):
+    say(f"assemble n={n} tile={tile} h={h}")
+    X, _ = nfir(n)
+    K = ctx.assemble(dev(X), h, tile)
+    got = host(ctx.to_dense(K))
+    ref = oracle.assemble_K(X, h)
+    np.testing.assert_array_equal(got, got.T)
+    assert oracle.max_rel(got, ref) <= 1e-14
+    np.testing.assert_array_equal(np.diag(got), np.diag(ref))
+    K.free()
+
+
+# --------------------------------------------------------------------------
+# Cholesky (Fig. 1): single tile = POTRF + inverse; 2 tiles add TRSM and
+# SYRK; 3+ tiles add GEMM; ragged n exercises the identity padding
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n,tile", [(32, 32), (64, 64), (256, 256), (512, 512), (1024, 1024),
+                                    (64, 32), (96, 32), (100, 32), (256, 64), (1000, 128),
+                                    (1024, 256), (2048, 512), (1536, 512)])
+def test_cholesky_dense_matches_oracle(ctx, n, tile):
+    say(f"cholesky_dense n={n} tile={tile}")
+    A = random_spd(n, seed=n + tile)
+    d = dev(A)
+    info = torch.full((1,), -7, dtype=torch.int32, device="cuda")
+    ctx.cholesky_dense(d, tile, info=info)
+    L = host(d)
+    assert int(info.item()) == 0
+    assert ctx.sync()[0] == 0
+    Lref, inf = oracle.cholesky(A)
+    assert inf == 0
+    np.testing.assert_array_equal(np.triu(L, 1), 0.0)
+    e = oracle.rel_err_lower(L, Lref)
+    be = np.linalg.norm(L @ L.T - A) / np.linalg.norm(A)
+    say(f"  rel(L) = {e:.3e}  backward = {be:.3e}")
+    assert e <= TOL
+    assert be <= 4 * n * U
+
+
+@pytest.mark.parametrize("n,tile", [(128, 32), (1000, 128), (4096, 256)])
+def test_cholesky_tiled_matches_oracle(ctx, n, tile):
+    say(f"assemble+cholesky n={n} tile={tile}")
+    X, _ = nfir(n)
+    K = ctx.assemble(dev(X), DEFAULT_HYPER, tile)
+    ctx.cholesky(K)
+    L = host(ctx.to_dense(K))
+    Lref, _ = oracle.cholesky(oracle.assemble_K(X, DEFAULT_HYPER))
+    e = oracle.rel_err_lower(L, Lref)
+    say(f"  rel(L) = {e:.3e}")
+    assert e <= TOL
+    K.free()
+
+
+def test_cholesky_reports_failed_pivot(ctx):
+    say("cholesky not positive definite")
+    X, _ = nfir(100)
+    K = ctx.assemble(dev(X), (1.0, 1.0, -2.0), 32)   # diagonal v + s2 = -1
+    info = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ctx.cholesky(K, info=info)
+    st, col = ctx.sync(raise_on_error=False)
+    assert st == 1 and col == 1
+    assert int(info.item()) == 1
+    assert ctx.sync()[0] == 0          # reported once
+    # failure inside a later tile: pivot of global column 41 (tile 1 of 32)
+    A = np.eye(64)
+    A[40, 40] = -1.0
+    d = dev(A)
+    ctx.cholesky_dense(d, 32, info=info)
+    st, col = ctx.sync(raise_on_error=False)
+    assert st == 1 and col == 41 and int(info.item()) == 41
+    K.free()
+
+
+# --------------------------------------------------------------------------
+# solves and prediction (eqs. (2), (3))
+# --------------------------------------------------------------------------
+
+def test_solve_matches_oracle(ctx):
+    n, tile = 700, 64
+    say(f"solve n={n} tile={tile}")
+    X, y = nfir(n)
+    K = ctx.assemble(dev(X), DEFAULT_HYPER, tile)
+    ctx.cholesky(K)
+    a = host(ctx.solve(K, dev(y)))
+    ref = oracle.predict(X, y, X[:1], DEFAULT_HYPER, want=("alpha",))["alpha"]
+    e = oracle.rel_err(a, ref)
+    say(f"  rel(alpha) = {e:.3e}")
+    assert e <= TOL
+    K.free()
+
+
+def run_predict(ctx, X, y, Xs, h, tile):
+    Xd, yd, Xsd = dev(X), dev(y), dev(Xs)
+    K = ctx.assemble(Xd, h, tile)
+    ctx.cholesky(K)
+    mean, cov = ctx.predict(K, Xd, yd, Xsd, h)
+    out = host(mean), host(cov)
+    assert ctx.sync()[0] == 0
+    K.free()
+    return out
+
+
+@pytest.mark.parametrize("n,ns,tile,h", [
+    (128, 128, 32, DEFAULT_HYPER),          # the small configuration, 4 x 4 tiles
+    (70, 5, 32, DEFAULT_HYPER),             # ragged, fewer test points than a tile
+    (1000, 300, 128, (0.3, 2.0, 0.5)),      # ragged in both sizes
+    (512, 512, 128, (2.0, 0.7, 0.01)),
+])
+def test_predict_matches_oracle(ctx, n, ns, tile, h):
+    say(f"predict n={n} n_test={ns} tile={tile} h={h}")
+    X, y, Xs = nfir_train_test(n, ns)
+    mean, cov = run_predict(ctx, X, y, Xs, h, tile)
+    ref = oracle.predict(X, y, Xs, h)
+    em, ec = oracle.rel_err(mean, ref["mean"]), oracle.rel_err(cov, ref["cov"])
+    say(f"  rel(mean) = {em:.3e}  rel(cov) = {ec:.3e}")
+    np.testing.assert_array_equal(cov, cov.T)
+    assert em <= TOL and ec <= TOL
+    if n <= 1000:
+        ld = oracle.predict(X, y, Xs, h, real="long double")
+        say(f"  vs long double: gpu {oracle.rel_err(mean, ld['mean']):.3e} / "
+            f"{oracle.rel_err(cov, ld['cov']):.3e}, double oracle "
+            f"{oracle.rel_err(ref['mean'], ld['mean']):.3e} / {oracle.rel_err(ref['cov'], ld['cov']):.3e}")
+
+
+_C2 = {}
+
+
+@pytest.mark.parametrize("tile", [128, 256, 512])
+def test_predict_4096_tile_sweep(ctx, tile):
+    n, ns = 4096, 1024
+    say(f"predict n={n} n_test={ns} tile={tile}")
+    X, y, Xs = nfir_train_test(n, ns)
+    if "ref" not in _C2:
+        _C2["ref"] = oracle.predict(X, y, Xs, DEFAULT_HYPER, want=("mean", "cov"))
+    ref = _C2["ref"]
+    mean, cov = run_predict(ctx, X, y, Xs, DEFAULT_HYPER, tile)
+    em, ec = oracle.rel_err(mean, ref["mean"]), oracle.rel_err(cov, ref["cov"])
+    say(f"  rel(mean) = {em:.3e}  rel(cov) = {ec:.3e}")
+    assert em <= TOL and ec <= TOL
+
+
+def test_prediction_is_deterministic(ctx):
+    n, ns, tile = 1024, 256, 128
+    say(f"determinism n={n} n_test={ns} tile={tile}")
+    X, y, Xs = nfir_train_test(n, ns)
+    a = run_predict(ctx, X, y, Xs, DEFAULT_HYPER, tile)
+    b = run_predict(ctx, X, y, Xs, DEFAULT_HYPER, tile)
+    np.testing.assert_array_equal(a[0], b[0])
+    np.testing.assert_array_equal(a[1], b[1])
+
+
+def test_far_field_and_identity_cases(ctx):
+    say("far field and test = train")
+    X, y = nfir(200)
+    h = DEFAULT_HYPER
+    mean, cov = run_predict(ctx, X, y, X[:64] + 100.0, h, 64)
+    assert np.all(mean == 0.0)
+    np.testing.assert_allclose(cov, oracle.kernel_matrix(X[:64] + 100.0, X[:64] + 100.0, h),
+                               rtol=0, atol=1e-15)
+    mean, cov = run_predict(ctx, X, y, X, h, 64)
+    alpha = oracle.predict(X, y, X[:1], h, want=("alpha",))["alpha"]
+    np.testing.assert_allclose(y - mean, h[2] * alpha, rtol=0, atol=1e-10)
+
+
+# --------------------------------------------------------------------------
+# full benchmark size, in the benchmark's launch configuration
+# --------------------------------------------------------------------------
+
+def _kernel_rows_times(X, Y, h, v, chunk=1024):
+    """sum_j k(x_i, y_j) v_j for all rows x_i of X (numpy, chunked)."""
+    l, var, _ = h
+    out = np.empty(X.shape[0])
+    sy = (Y * Y).sum(1)
+    for s in range(0, X.shape[0], chunk):
+        A = X[s:s + chunk]
+        d2 = (A * A).sum(1)[:, None] + sy[None, :] - 2.0 * (A @ Y.T)
+        np.maximum(d2, 0.0, out=d2)
+        out[s:s + chunk] = (var * np.exp(-d2 / (2 * l))) @ v
+    return out
+
+
+@pytest.mark.slow
+def test_full_size_properties(ctx):
+    n, ns, tile = 16384, 4096, 512
+    h = DEFAULT_HYPER
+    say(f"full size n={n} n_test={ns} tile={tile}")
+    X, y, Xs = nfir_train_test(n, ns)
+    Xd, yd, Xsd = dev(X), dev(y), dev(Xs)
+    K = ctx.assemble(Xd, h, tile)
+    ctx.cholesky(K)
+    mean_d, cov_d = ctx.predict(K, Xd, yd, Xsd, h)
+    alpha = host(ctx.solve(K, yd))
+    assert ctx.sync()[0] == 0
+    mean, cov = host(mean_d), host(cov_d)
+    rng = np.random.default_rng(7)
+
+    # L: sampled entries of L L^T against K computed one by one
+    Ld = ctx.to_dense(K)
+    rows = np.sort(rng.choice(n, 48, replace=False))
+    Lr = host(Ld[torch.from_numpy(rows).cuda()])
+    del Ld
+    torch.cuda.empty_cache()
+    LLt = Lr @ Lr.T
+    Kr = oracle.kernel_matrix(X[rows], X[rows], h) + h[2] * np.eye(len(rows))
+    err_L = np.abs(LLt - Kr).max()
+    say(f"  max |(L L^T - K)_ij| over sampled pairs = {err_L:.3e}")
+    assert err_L <= 1e-12
+
+    # alpha: residual of K alpha = y (matrix-free on the host)
+    Ka = _kernel_rows_times(X, X, h, alpha) + h[2] * alpha
+    eta = np.linalg.norm(y - Ka) / np.linalg.norm(y)
+    say(f"  ||y - K alpha|| / ||y|| = {eta:.3e}")
+    assert eta <= 1e-10
+
+    # mean: sampled entries recomputed one by one from alpha
+    idx = rng.choice(ns, 256, replace=False)
+    m_ref = oracle.kernel_matrix(Xs[idx], X, h) @ alpha
+    e_mean = oracle.rel_err(mean[idx], m_ref)
+    say(f"  rel(mean, sampled) = {e_mean:.3e}")
+    assert e_mean <= 1e-12
+
+    # covariance: sampled columns via independent vector solves with the factor
+    np.testing.assert_array_equal(cov, cov.T)
+    d = np.diag(cov)
+    assert np.all(d >= -1e-12) and np.all(d <= h[1] + 1e-12)
+    cols = rng.choice(ns, 6, replace=False)
+    Ks = oracle.kernel_matrix(Xs, X, h)
+    for j in cols:
+        w = host(ctx.solve(K, dev(Ks[j])))
+        ref_col = oracle.kernel_matrix(Xs, Xs[j:j + 1], h)[:, 0] - Ks @ w
+        e = oracle.rel_err(cov[:, j], ref_col)
+        say(f"  rel(cov[:, {j}]) = {e:.3e}")
+        assert e <= TOL
+    K.free()

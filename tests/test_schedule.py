@@ -1,0 +1,221 @@
+"""The tile schedule (host logic, no GPU): task multiset of Fig. 1, the
+Fig. 2 example, a race check of the two-stream launch order against the
+sequential loop nest of Fig. 1, and a host execution of the schedule in
+random orders compared with the oracle."""
+import os
+import random
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+import oracle
+from gpr_inputs import nfir_train_test
+from paper_2602_19683_amd import schedule_describe
+
+POTRF, TRSM, SYRK, GEMM = 0, 1, 2, 3
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "fig2_first_iteration.txt")
+
+
+def fig1_program(M, Mhat, mode):
+    """The loop nest of Fig. 1 as a sequential task list, extended with the
+    test rows M..M+Mhat-1 of the covariance solve (mode 1 and 2)."""
+    factor = mode in (0, 2)
+    predict = mode in (1, 2)
+    T = M + (Mhat if predict else 0)
+    rows = [I for I in range(T) if (I < M and factor) or (I >= M and predict)]
+    prog = []
+    for J in range(M):
+        if factor:
+            prog.append((POTRF, J, J, J))
+        for I in rows:
+            if I > J:
+                prog.append((TRSM, I, J, J))
+        for I in rows:
+            if I <= J:
+                continue
+            prog.append((SYRK, I, I, J))
+            for K in range(J + 1, I):
+                if I >= M or factor:
+                    prog.append((GEMM, I, K, J))
+    return prog
+
+
+def accesses(task, M, mode):
+    kind, I, K, J = task
+    fixed = mode == 1  # factor tiles are read-only inputs in mode 1
+    def w(t):
+        return (t, "w")
+    def r(t):
+        return (t, "r")
+    if kind == POTRF:
+        return [w((J, J))]
+    if kind == TRSM:
+        return [r((J, J)), w((I, J))]
+    if kind == SYRK:
+        return [r((I, J)), w((I, I))]
+    return [r((I, J)), r((K, J)), w((I, K))]
+
+
+def happens_before(launches):
+    n = len(launches)
+    pred = [set() for _ in range(n)]
+    last = {0: -1, 1: -1}
+    for i, (st, wait, _) in enumerate(launches):
+        if last[st] >= 0:
+            pred[i].add(last[st])
+        if wait >= 0:
+            pred[i].add(wait)
+        last[st] = i
+    reach = [0] * n  # bitset of launches that happen before i
+    for i in range(n):
+        b = 0
+        for p in pred[i]:
+            b |= reach[p] | (1 << p)
+        reach[i] = b
+    return reach, pred
+
+
+@pytest.mark.parametrize("M", [1, 2, 3, 5, 8, 32])
+def test_fig1_task_counts(M):
+    tasks, launches = schedule_describe(M, 0, 0)
+    kinds = tasks[:, 0]
+    assert (kinds == POTRF).sum() == M
+    assert (kinds == TRSM).sum() == M * (M - 1) // 2
+    assert (kinds == SYRK).sum() == M * (M - 1) // 2
+    assert (kinds == GEMM).sum() == M * (M - 1) * (M - 2) // 6
+
+
+@pytest.mark.parametrize("M,Mhat", [(4, 4), (32, 8), (3, 1)])
+def test_covariance_solve_task_counts(M, Mhat):
+    tasks, _ = schedule_describe(M, Mhat, 1)
+    kinds = tasks[:, 0]
+    assert (kinds == POTRF).sum() == 0
+    assert (kinds == TRSM).sum() == Mhat * M                         # V tiles, one per step
+    # V updates: Mhat * M (M - 1) / 2; Sigma: Mhat (Mhat + 1) / 2 per step
+    assert (kinds == GEMM).sum() + (kinds == SYRK).sum() == \
+        Mhat * M * (M - 1) // 2 + M * Mhat * (Mhat + 1) // 2
+    assert (kinds == SYRK).sum() == M * Mhat
+
+
+def test_fig2_first_iteration_golden():
+    grid = [l.split() for l in open(GOLDEN) if l.strip() and not l.startswith("#")]
+    M = len(grid)
+    tasks, _ = schedule_describe(M, 0, 0)
+    sym = {POTRF: "P", TRSM: "T", SYRK: "S", GEMM: "G"}
+    got = [["." for _ in range(M)] for _ in range(M)]
+    for kind, I, K, J, _ in tasks:
+        if J == 0:
+            got[I][K] = sym[kind]
+    assert got == grid
+
+
+def test_memory_fraction_of_lower_tiles():
+    # Sec. 4.2: lower tiles need 50 % to 75 % of the full matrix; the
+    # assembled entries n^2 (M + 1) / (2 M) shrink as M grows (Sec. 5.1).
+    for M in [2, 4, 8, 32, 64]:
+        frac = (M * (M + 1) // 2) / (M * M)
+        assert 0.5 < frac <= 0.75
+        assert abs(frac - (M + 1) / (2 * M)) < 1e-15
+    assert (32 * 33 // 2) * 512 * 512 * 8 == 1107296256  # bytes of K at n = 16384, m = 512
+
+
+@pytest.mark.parametrize("M,Mhat,mode", [(1, 0, 0), (2, 0, 0), (5, 0, 0), (9, 0, 0),
+                                         (4, 3, 1), (7, 2, 1), (1, 2, 1), (5, 3, 2), (6, 1, 2)])
+def test_schedule_has_no_races(M, Mhat, mode):
+    tasks, launches = schedule_describe(M, Mhat, mode)
+    prog = fig1_program(M, Mhat, mode)
+    got = sorted(tuple(t[:4]) for t in tasks)
+    assert got == sorted(prog), "schedule task multiset differs from Fig. 1"
+    where = {tuple(t[:4]): int(t[4]) for t in tasks}
+    reach, _ = happens_before([tuple(l) for l in launches])
+    # launches only wait on earlier launches of the other stream
+    for i, (st, wait, _) in enumerate(launches):
+        assert wait < i and (wait < 0 or launches[wait][0] != st)
+
+    def ordered(a, b):
+        la, lb = where[a], where[b]
+        return la != lb and (reach[lb] >> la) & 1
+
+    last_w = {}
+    reads = {}
+    for task in prog:
+        for tile, kind in accesses(task, M, mode):
+            if kind == "r":
+                if tile in last_w:
+                    assert ordered(last_w[tile], task), f"RAW race {last_w[tile]} -> {task}"
+                reads.setdefault(tile, []).append(task)
+            else:
+                if tile in last_w:
+                    assert ordered(last_w[tile], task), f"WAW race {last_w[tile]} -> {task}"
+                for rd in reads.get(tile, []):
+                    if rd != task:
+                        assert ordered(rd, task), f"WAR race {rd} -> {task}"
+                reads[tile] = []
+                last_w[tile] = task
+
+
+def run_schedule_on_host(tiles, tinv, tasks, launches, rng):
+    """Executes the launches in a random order allowed by the stream / event
+    semantics, tasks of one launch in random order, tile ops in numpy."""
+    n = len(launches)
+    reach, pred = happens_before([tuple(l) for l in launches])
+    by_launch = {}
+    for t in tasks:
+        by_launch.setdefault(int(t[4]), []).append(tuple(t[:4]))
+    done = set()
+    while len(done) < n:
+        ready = [i for i in range(n) if i not in done and pred[i] <= done]
+        li = rng.choice(ready)
+        todo = list(by_launch.get(li, []))
+        rng.shuffle(todo)
+        for kind, I, K, J in todo:
+            if kind == POTRF:
+                L = np.linalg.cholesky(np.tril(tiles[(J, J)]) + np.tril(tiles[(J, J)], -1).T)
+                tiles[(J, J)] = L
+                tinv[J] = scipy.linalg.solve_triangular(L, np.eye(L.shape[0]), lower=True)
+            elif kind == TRSM:
+                tiles[(I, J)] = tiles[(I, J)] @ tinv[J].T
+            else:
+                tiles[(I, K)] = tiles[(I, K)] - tiles[(I, J)] @ tiles[(K, J)].T
+        done.add(li)
+
+
+@pytest.mark.parametrize("M,Mhat,mode,m", [(4, 0, 0, 8), (5, 3, 2, 6), (3, 2, 1, 7)])
+def test_host_execution_matches_oracle(M, Mhat, mode, m):
+    n, ns = M * m, Mhat * m
+    h = (1.0, 1.0, 0.1)
+    X, y, Xs = nfir_train_test(n, max(ns, 1))
+    K = oracle.assemble_K(X, h)
+    ref = oracle.predict(X, y, Xs, h) if ns else None
+    Lref, _ = oracle.cholesky(K)
+    results = []
+    for seed in range(3):
+        rng = random.Random(seed)
+        tiles, tinv = {}, {}
+        big = np.zeros((n + ns, n + ns))
+        big[:n, :n] = K if mode != 1 else Lref
+        if ns:
+            big[n:, :n] = oracle.kernel_matrix(Xs, X, h)
+            big[n:, n:] = oracle.kernel_matrix(Xs, Xs, h)
+        T = M + (Mhat if mode else 0)
+        for I in range(T):
+            for J in range(I + 1):
+                tiles[(I, J)] = big[I * m:(I + 1) * m, J * m:(J + 1) * m].copy()
+        if mode == 1:
+            for J in range(M):
+                tinv[J] = scipy.linalg.solve_triangular(tiles[(J, J)], np.eye(m), lower=True)
+        tasks, launches = schedule_describe(M, Mhat, mode)
+        run_schedule_on_host(tiles, tinv, tasks, launches, rng)
+        out = np.zeros_like(big)
+        for (I, J), t in tiles.items():
+            out[I * m:(I + 1) * m, J * m:(J + 1) * m] = t
+        results.append(out)
+        if mode != 1:
+            assert oracle.rel_err_lower(np.tril(out[:n, :n]), Lref) <= 1e-13
+        if mode:
+            S = np.tril(out[n:, n:])
+            S = S + np.tril(S, -1).T
+            assert oracle.rel_err(S, ref["cov"]) <= 1e-12
+    for r in results[1:]:
+        np.testing.assert_array_equal(r, results[0])   # order-independent, bitwise
