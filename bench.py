@@ -83,6 +83,8 @@ def main():
     ap.add_argument("--n-test", type=int, default=4096)
     ap.add_argument("--tile", type=int, default=512)
     ap.add_argument("--precision", default="fp64", choices=["fp64"])
+    ap.add_argument("--streams", type=int, default=2,
+                    help="1 = no overlap between launches (isolated kernel timings)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
     args = ap.parse_args()
@@ -105,7 +107,7 @@ def main():
     Xd, yd, Xsd = dev(X), dev(y), dev(Xs)
     mean = torch.empty(ns, dtype=torch.float64, device="cuda:0")
     cov = torch.empty(ns, ns, dtype=torch.float64, device="cuda:0")
-    ctx = Context(0)
+    ctx = Context(0, n_streams=args.streams)
     K = ctx.assemble(Xd, h, tile)
 
     def step():

@@ -106,8 +106,10 @@ enum { GPR_STATE_EMPTY = 0, GPR_STATE_K = 1, GPR_STATE_L = 2 };
 /* ---- context ------------------------------------------------------------ */
 
 /* Creates a context on `device` (HIP ordinal). n_streams: number of streams
- * the executor may use (>= 1; the executor uses at most 2 -- a critical-path
- * stream and a bulk-update stream -- Sec. 4.3 uses a user-sized pool).
+ * the executor may use (>= 1; it uses at most 2 -- the caller's stream for
+ * the critical path and one bulk-update stream; Sec. 4.3 uses a user-sized
+ * pool). With 1, every launch runs on the caller's stream in schedule order
+ * (no overlap; useful to time kernels in isolation).
  * Returns GPR_ENODEV if the device does not exist, GPR_ENOTSUP for an
  * executor this build lacks. On success *out must later go to
  * gpr_ctx_destroy. */

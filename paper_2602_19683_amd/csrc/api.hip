@@ -25,11 +25,15 @@ using namespace gpr;
 
 struct gpr_ctx {
     int device = 0;
+    int n_streams = 2;            // 1: every launch on the caller's stream
     hipStream_t bulk = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_last = nullptr, ev_desc = nullptr;
     bool last_valid = false, desc_valid = false;
     std::vector<hipEvent_t> evpool;
-    int* d_info = nullptr;        // [0]: this factorisation, [1]: sticky since gpr_sync
+    int* d_info = nullptr;        // [0]: this factorisation, [1]: sticky since gpr_sync,
+                                  // [2]: a device-side wait hit its limit
+    unsigned* d_flags = nullptr;  // POTRF row-panel flags
+    unsigned epoch = 0;
     char* d_desc = nullptr;
     size_t desc_cap = 0;
     char* h_desc = nullptr;       // pinned staging
@@ -280,12 +284,15 @@ int run_sweep(gpr_ctx* ctx, const SweepMats& X, const SweepPlan& P, const DescBu
     std::vector<char> waited(Ls.size(), 0);
     for (const auto& L : Ls)
         if (L.wait >= 0) waited[L.wait] = 1;
-    HIP_TRY(hipEventRecord(ctx->ev_fork, s));
-    HIP_TRY(hipStreamWaitEvent(ctx->bulk, ctx->ev_fork, 0));
+    const bool two = ctx->n_streams > 1;
+    if (two) {
+        HIP_TRY(hipEventRecord(ctx->ev_fork, s));
+        HIP_TRY(hipStreamWaitEvent(ctx->bulk, ctx->ev_fork, 0));
+    }
     const int m = X.m;
     for (size_t li = 0; li < Ls.size(); ++li) {
         const SchedLaunch& L = Ls[li];
-        hipStream_t st = L.stream == 0 ? s : ctx->bulk;
+        hipStream_t st = (L.stream == 0 || !two) ? s : ctx->bulk;
         if (L.wait >= 0) HIP_TRY(hipStreamWaitEvent(st, ctx->evpool[L.wait], 0));
         const double m3 = (double)m * m * m;
         if (L.kind == LK_POTRF) {
@@ -293,7 +300,8 @@ int run_sweep(gpr_ctx* ctx, const SweepMats& X, const SweepPlan& P, const DescBu
             double* A = X.at(J, J);
             double* Ti = X.tinv + (size_t)J * m * m;
             ProfScope ps(ctx, st, PK_POTRF, 2.0 * m3 / 3.0, 0.0);
-            HIP_TRY(launch_potrf_f64(A, m, m, Ti, m, ctx->d_info, (int64_t)J * m, st));
+            HIP_TRY(launch_potrf_f64(A, m, m, Ti, m, ctx->d_info, (int64_t)J * m, ctx->d_flags,
+                                     ++ctx->epoch, ctx->d_info + 2, st));
             HIP_TRY(launch_trtri_f64(A, m, Ti, m, m, st));
         } else if (L.kind == LK_TRSM) {
             ProfScope ps(ctx, st, PK_TRSM, L.count * m3, 0.0);
@@ -307,8 +315,10 @@ int run_sweep(gpr_ctx* ctx, const SweepMats& X, const SweepPlan& P, const DescBu
         }
         if (waited[li]) HIP_TRY(hipEventRecord(ctx->evpool[li], st));
     }
-    HIP_TRY(hipEventRecord(ctx->ev_join, ctx->bulk));
-    HIP_TRY(hipStreamWaitEvent(s, ctx->ev_join, 0));
+    if (two) {
+        HIP_TRY(hipEventRecord(ctx->ev_join, ctx->bulk));
+        HIP_TRY(hipStreamWaitEvent(s, ctx->ev_join, 0));
+    }
     return GPR_OK;
 }
 
@@ -425,13 +435,17 @@ int gpr_ctx_create(gpr_ctx** out, int device, int n_streams, gpr_executor ex)
     gpr_ctx* c = new (std::nothrow) gpr_ctx;
     if (!c) return GPR_ENOMEM;
     c->device = device;
+    c->n_streams = n_streams > 1 ? 2 : 1;
     bool ok = hipStreamCreateWithFlags(&c->bulk, hipStreamNonBlocking) == hipSuccess &&
               hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) == hipSuccess &&
               hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) == hipSuccess &&
               hipEventCreateWithFlags(&c->ev_last, hipEventDisableTiming) == hipSuccess &&
               hipEventCreateWithFlags(&c->ev_desc, hipEventDisableTiming) == hipSuccess &&
-              hipMalloc(reinterpret_cast<void**>(&c->d_info), 2 * sizeof(int)) == hipSuccess &&
-              hipMemset(c->d_info, 0, 2 * sizeof(int)) == hipSuccess;
+              hipMalloc(reinterpret_cast<void**>(&c->d_info), 4 * sizeof(int)) == hipSuccess &&
+              hipMemset(c->d_info, 0, 4 * sizeof(int)) == hipSuccess &&
+              hipMalloc(reinterpret_cast<void**>(&c->d_flags), 64 * sizeof(unsigned)) == hipSuccess &&
+              hipMemset(c->d_flags, 0, 64 * sizeof(unsigned)) == hipSuccess &&
+              hipDeviceSynchronize() == hipSuccess;
     if (!ok) {
         gpr_ctx_destroy(c);
         return GPR_EHIP;
@@ -454,6 +468,7 @@ int gpr_ctx_destroy(gpr_ctx* c)
     if (c->ev_desc) (void)hipEventDestroy(c->ev_desc);
     if (c->bulk) (void)hipStreamDestroy(c->bulk);
     if (c->d_info) (void)hipFree(c->d_info);
+    if (c->d_flags) (void)hipFree(c->d_flags);
     if (c->d_desc) (void)hipFree(c->d_desc);
     if (c->h_desc) (void)hipHostFree(c->h_desc);
     if (c->d_ws) (void)hipFree(c->d_ws);
@@ -724,8 +739,9 @@ int gpr_sync(gpr_ctx* ctx, void* stream, int64_t* column)
     hipStream_t s = static_cast<hipStream_t>(stream);
     HIP_TRY(hipStreamSynchronize(s));
     if (ctx->last_valid) HIP_TRY(hipEventSynchronize(ctx->ev_last));
-    int info[2] = {0, 0};
+    int info[3] = {0, 0, 0};
     HIP_TRY(hipMemcpy(info, ctx->d_info, sizeof(info), hipMemcpyDeviceToHost));
+    if (info[2] != 0) return GPR_EHIP;  // a device-side wait timed out
     if (info[1] > 0) {
         if (column) *column = info[1];
         const int zero = 0;

@@ -2,14 +2,18 @@
 // of the resulting triangular factor, which turns every TRSM and triangular
 // vector solve into a product.
 //
-// POTRF: one workgroup (8 waves) per m x m tile, blocked left-looking over
-// 32-column panels. For panel p (columns c0 = 32 p .. c0 + 31) every wave
-// takes 16-row blocks of the rows below c0 and accumulates
-//     acc = K[rows, panel] - L[rows, 0:c0] L[panel, 0:c0]^T
-// with FP64 MFMA; the 32 x 32 diagonal block is then factored by one wave in
-// registers (unblocked right-looking Cholesky), its inverse Dinv_p is formed
-// by column substitution, and the rows below become acc Dinv_p^T. Each panel
-// is written once, so the tile makes one pass through L2 per panel.
+// POTRF, left-looking over 32-row panels, one workgroup per row panel w of
+// the m x m tile (m / 32 workgroups). Workgroup w computes its blocks in
+// column order q = 0 .. w:
+//     acc = K[w, q] - L[w, 0:32q] L[q, 0:32q]^T      (FP64 MFMA, LDS-staged)
+//     L[w, q] = acc Dinv_q^T                          (q < w)
+//     L[w, w] = chol(acc), Dinv_w = L[w, w]^{-1}      (q = w, one wave)
+// Block (w, q) needs row panel q to be complete (rows of L and Dinv_q): that
+// is signalled by workgroup q through flag[q] (release / acquire at device
+// scope, so it holds across XCDs). A workgroup only ever waits for
+// lower-numbered workgroups, which the hardware dispatches first, so every
+// wait ends; a spin limit turns a broken invariant into an error report
+// instead of a hang.
 //
 // TRTRI: block column c of Tinv = L^{-1} is X_c = Dinv_c and
 //     X_r = -Dinv_r sum_{s=c}^{r-1} L[r, s] X_s,   r > c,
@@ -20,8 +24,10 @@
 namespace gpr {
 
 namespace {
-constexpr int NB = 32;      // panel width
-constexpr int NW = 8;       // waves per POTRF workgroup
+constexpr int NB = 32;       // panel width
+constexpr int KC = 32;       // k-chunk staged in LDS
+constexpr int SP = NB + 4;   // padded LDS row
+constexpr unsigned SPIN_LIMIT = 1u << 22;
 }  // namespace
 
 // Unblocked Cholesky of the 32 x 32 block in S (lower triangle read), by one
@@ -70,109 +76,154 @@ __device__ static int factor_diag32(double (*S)[NB + 1], double (*Si)[NB + 1], i
     return bad;
 }
 
-// MAXQ: 16-row blocks per wave, m <= 16 * NW * MAXQ.
-template <int MAXQ>
-__global__ __launch_bounds__(NW * 64, 1) void k_potrf_f64(double* __restrict__ A, int lda, int m,
-                                                          double* __restrict__ Tinv, int ldt,
-                                                          int* __restrict__ info, int64_t col_base)
+// acc += sign * sum_{k < K} A[i][k] * B(k, j) for this wave's 16 x 16 quadrant
+// (qi, qj) of a 32 x 32 block; A is 32 rows row-major (lda). NT: B(k, j) =
+// B[j * ldb + k] (32 rows of B); otherwise B(k, j) = B[k * ldb + j]. K is a
+// multiple of KC. Chunks of KC columns go through LDS (k-major, so the 16
+// lanes sharing a k read consecutive words), double-buffered. All 256
+// threads of the workgroup must call it.
+template <bool NT>
+__device__ static dbl4 accum32(const double* __restrict__ A, int lda, const double* __restrict__ B,
+                               int ldb, int K, dbl4 acc, double sign, double (*As)[KC][SP],
+                               double (*Bs)[KC][SP])
 {
-    __shared__ double Sd[NB][NB + 1];
-    __shared__ double Si[NB][NB + 1];
-    __shared__ double Sw[NW][16][NB + 1];
-    __shared__ int s_bad;
-
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int lr = lane & 15, lk = lane >> 4;
-    if (tid == 0) s_bad = -1;
-
-    const int P = m / NB;
-    for (int p = 0; p < P; ++p) {
-        const int c0 = p * NB;
-        const int nrb = (m - c0) / 16;
-
-        // 1. left-looking accumulation of the panel
-        dbl4 acc[MAXQ][2];
+    const int qi = wave >> 1, qj = wave & 1;
+    // 32 x KC doubles per operand = 512 double2 -> 2 per thread
+    double2 ra[2], rb[2];
+    auto gload = [&](int k0) {
 #pragma unroll
-        for (int q = 0; q < MAXQ; ++q) {
-            const int rb = wave + NW * q;
-            if (rb < nrb) {
-                const int r0 = c0 + 16 * rb;
+        for (int u = 0; u < 2; ++u) {
+            const int e = tid + 256 * u;
+            const int r = e >> 4, c = (e & 15) * 2;  // row r, columns c and c + 1
+            ra[u] = *reinterpret_cast<const double2*>(A + (size_t)r * lda + k0 + c);
+            if (NT) rb[u] = *reinterpret_cast<const double2*>(B + (size_t)r * ldb + k0 + c);
+            else rb[u] = *reinterpret_cast<const double2*>(B + (size_t)(k0 + r) * ldb + c);
+        }
+    };
+    auto swrite = [&](int buf) {
 #pragma unroll
-                for (int t = 0; t < 2; ++t)
-#pragma unroll
-                    for (int v = 0; v < 4; ++v)
-                        acc[q][t][v] = A[(size_t)(r0 + drow(lk, v)) * lda + c0 + 16 * t + lr];
-                const double* arow = A + (size_t)(r0 + lr) * lda + lk;
-                const double* b0 = A + (size_t)(c0 + lr) * lda + lk;
-                const double* b1 = A + (size_t)(c0 + 16 + lr) * lda + lk;
-                for (int k = 0; k < c0; k += 4) {
-                    const double a = -arow[k];
-                    acc[q][0] = mfma16(a, b0[k], acc[q][0]);
-                    acc[q][1] = mfma16(a, b1[k], acc[q][1]);
-                }
+        for (int u = 0; u < 2; ++u) {
+            const int e = tid + 256 * u;
+            const int r = e >> 4, c = (e & 15) * 2;
+            As[buf][c][r] = sign * ra[u].x;
+            As[buf][c + 1][r] = sign * ra[u].y;
+            if (NT) {
+                Bs[buf][c][r] = rb[u].x;
+                Bs[buf][c + 1][r] = rb[u].y;
+            } else {
+                Bs[buf][r][c] = rb[u].x;
+                Bs[buf][r][c + 1] = rb[u].y;
             }
         }
-        // 2. diagonal block (row blocks 0 and 1 belong to waves 0 and 1, q = 0)
-        if (wave < 2) {
+    };
+    const int nk = K / KC;
+    if (nk == 0) return acc;
+    __syncthreads();  // LDS buffers free
+    gload(0);
+    swrite(0);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        const int cur = kt & 1;
+        if (kt + 1 < nk) gload((kt + 1) * KC);
+        dbl4 acc2 = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int t = 0; t < 2; ++t)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) Sd[16 * wave + drow(lk, v)][16 * t + lr] = acc[0][t][v];
+        for (int kk = 0; kk < KC; kk += 8) {
+            acc = mfma16(As[cur][kk + lk][16 * qi + lr], Bs[cur][kk + lk][16 * qj + lr], acc);
+            acc2 = mfma16(As[cur][kk + 4 + lk][16 * qi + lr], Bs[cur][kk + 4 + lk][16 * qj + lr],
+                          acc2);
         }
+        acc += acc2;
+        if (kt + 1 < nk) swrite(cur ^ 1);
         __syncthreads();
-        if (wave == 0) {
-            const int bad = factor_diag32(Sd, Si, lane);
-            if (lane == 0 && bad >= 0 && s_bad < 0) s_bad = c0 + bad;
+    }
+    return acc;
+}
+
+__device__ static bool wait_flag(const unsigned* f, unsigned epoch)
+{
+    unsigned it = 0;
+    while (__hip_atomic_load(f, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
+        __builtin_amdgcn_s_sleep(2);
+        if (++it > SPIN_LIMIT) return false;
+    }
+    return true;
+}
+
+__global__ __launch_bounds__(256) void k_potrf_f64(double* __restrict__ A, int lda, int m,
+                                                   double* __restrict__ Tinv, int ldt,
+                                                   int* __restrict__ info, int64_t col_base,
+                                                   unsigned* __restrict__ flags, unsigned epoch,
+                                                   int* __restrict__ err)
+{
+    __shared__ double As[2][KC][SP];
+    __shared__ double Bs[2][KC][SP];
+    __shared__ double Sacc[NB][NB + 1];
+    __shared__ double Si[NB][NB + 1];
+    const int w = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int qi = wave >> 1, qj = wave & 1;
+    const int row0 = NB * w;
+    double* Aw = A + (size_t)row0 * lda;  // row panel w
+
+    for (int q = 0; q <= w; ++q) {
+        if (q < w) {
+            if (tid == 0 && !wait_flag(flags + q, epoch)) *err = 1;
+            __syncthreads();
         }
+        dbl4 acc;
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            acc[v] = Aw[(size_t)(16 * qi + drow(lk, v)) * lda + NB * q + 16 * qj + lr];
+        acc = accum32<true>(Aw, lda, A + (size_t)NB * q * lda, lda, NB * q, acc, -1.0, As, Bs);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Sacc[16 * qi + drow(lk, v)][16 * qj + lr] = acc[v];
         __syncthreads();
-        for (int e = tid; e < NB * NB; e += NW * 64) {
-            const int r = e / NB, c = e % NB;
-            A[(size_t)(c0 + r) * lda + c0 + c] = Sd[r][c];
-            Tinv[(size_t)(c0 + r) * ldt + c0 + c] = Si[r][c];
-        }
-        // 3. rows below the diagonal block: L = acc Dinv^T
+        if (q < w) {
+            // L[w, q] = acc Dinv_q^T; Dinv_q is the diagonal block q of Tinv
+            const double* dq = Tinv + (size_t)(NB * q + 16 * qj + lr) * ldt + NB * q + lk;
+            dbl4 o = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int q = 0; q < MAXQ; ++q) {
-            const int rb = wave + NW * q;
-            if (rb >= 2 && rb < nrb) {
-                const int r0 = c0 + 16 * rb;
+            for (int k = 0; k < NB; k += 4) o = mfma16(Sacc[16 * qi + lr][k + lk], dq[k], o);
 #pragma unroll
-                for (int t = 0; t < 2; ++t)
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) Sw[wave][drow(lk, v)][16 * t + lr] = acc[q][t][v];
-                wave_lds_sync();
-                dbl4 o0 = {0.0, 0.0, 0.0, 0.0}, o1 = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                for (int k = 0; k < NB; k += 4) {
-                    const double a = Sw[wave][lr][k + lk];
-                    o0 = mfma16(a, Si[lr][k + lk], o0);
-                    o1 = mfma16(a, Si[16 + lr][k + lk], o1);
-                }
-                wave_lds_sync();
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    A[(size_t)(r0 + drow(lk, v)) * lda + c0 + lr] = o0[v];
-                    A[(size_t)(r0 + drow(lk, v)) * lda + c0 + 16 + lr] = o1[v];
-                }
+            for (int v = 0; v < 4; ++v)
+                Aw[(size_t)(16 * qi + drow(lk, v)) * lda + NB * q + 16 * qj + lr] = o[v];
+            __syncthreads();  // Sacc reuse; L[w, q] visible to the workgroup
+        } else {
+            int bad = -1;
+            if (wave == 0) bad = factor_diag32(Sacc, Si, lane);
+            __syncthreads();
+            for (int e = tid; e < NB * NB; e += 256) {
+                const int r = e / NB, c = e % NB;
+                Aw[(size_t)r * lda + row0 + c] = Sacc[r][c];
+                Tinv[(size_t)(row0 + r) * ldt + row0 + c] = Si[r][c];
             }
+            // strict upper triangle of the tile in this row panel
+            const int rest = m - row0 - NB;
+            for (int e = tid; e < NB * rest; e += 256) {
+                const int r = e / rest, c = e % rest;
+                Aw[(size_t)r * lda + row0 + NB + c] = 0.0;
+            }
+            // every earlier panel is complete (flags acquired), so the first
+            // failure seen here in column order is the first overall
+            if (tid == 0 && bad >= 0 && info != nullptr && *info == 0)
+                *info = (int)(col_base + row0 + bad + 1);
+            __syncthreads();
+            if (tid == 0)
+                __hip_atomic_store(flags + w, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         }
-        __syncthreads();
-    }
-    // zero the strict upper triangle of the tile (outside the diagonal blocks,
-    // which were written with zeros above their diagonal)
-    for (int r = tid / 64; r < m; r += NW) {
-        const int cstart = (r / NB + 1) * NB;
-        for (int c = cstart + lane; c < m; c += 64) A[(size_t)r * lda + c] = 0.0;
-    }
-    if (tid == 0 && s_bad >= 0 && info != nullptr) {
-        if (*info == 0) *info = (int)(col_base + s_bad + 1);
     }
 }
 
 __global__ __launch_bounds__(256) void k_trtri_f64(const double* __restrict__ L, int lda,
                                                    double* __restrict__ Tinv, int ldt, int m)
 {
+    __shared__ double As[2][KC][SP];
+    __shared__ double Bs[2][KC][SP];
     __shared__ double Sacc[NB][NB + 1];
     const int c = blockIdx.x;
     const int P = m / NB;
@@ -187,20 +238,19 @@ __global__ __launch_bounds__(256) void k_trtri_f64(const double* __restrict__ L,
         Tinv[(size_t)r * ldt + c * NB + cc] = 0.0;
     }
     for (int r = c + 1; r < P; ++r) {
-        dbl4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
-        const double* arow = L + (size_t)(r * NB + 16 * qi + lr) * lda + lk;
-        const double* bcol = Tinv + (size_t)lk * ldt + c * NB + 16 * qj + lr;
-        for (int k = c * NB; k < r * NB; k += 8) {
-            acc0 = mfma16(arow[k], bcol[(size_t)k * ldt], acc0);
-            acc1 = mfma16(arow[k + 4], bcol[(size_t)(k + 4) * ldt], acc1);
-        }
+        // acc = sum_{s=c}^{r-1} L[r, s] X_s  (X_s = Tinv block (s, c))
+        dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+        acc = accum32<false>(L + (size_t)r * NB * lda + c * NB, lda,
+                             Tinv + (size_t)c * NB * ldt + c * NB, ldt, NB * (r - c), acc, 1.0,
+                             As, Bs);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) Sacc[16 * qi + drow(lk, v)][16 * qj + lr] = acc0[v] + acc1[v];
+        for (int v = 0; v < 4; ++v) Sacc[16 * qi + drow(lk, v)][16 * qj + lr] = acc[v];
         __syncthreads();
+        // X_r = -Dinv_r acc
+        const double* dr = Tinv + (size_t)(r * NB + 16 * qi + lr) * ldt + r * NB + lk;
         dbl4 o = {0.0, 0.0, 0.0, 0.0};
-        const double* dinv_row = Tinv + (size_t)(r * NB + 16 * qi + lr) * ldt + r * NB + lk;
 #pragma unroll
-        for (int k = 0; k < NB; k += 4) o = mfma16(-dinv_row[k], Sacc[k + lk][16 * qj + lr], o);
+        for (int k = 0; k < NB; k += 4) o = mfma16(-dr[k], Sacc[k + lk][16 * qj + lr], o);
 #pragma unroll
         for (int v = 0; v < 4; ++v)
             Tinv[(size_t)(r * NB + 16 * qi + drow(lk, v)) * ldt + c * NB + 16 * qj + lr] = o[v];
@@ -209,14 +259,11 @@ __global__ __launch_bounds__(256) void k_trtri_f64(const double* __restrict__ L,
 }
 
 hipError_t launch_potrf_f64(double* A, int lda, int m, double* Tinv, int ldt, int* info,
-                            int64_t col_base, hipStream_t s)
+                            int64_t col_base, unsigned* flags, unsigned epoch, int* err,
+                            hipStream_t s)
 {
-    if (m <= 16 * NW * 4)
-        hipLaunchKernelGGL(k_potrf_f64<4>, dim3(1), dim3(NW * 64), 0, s, A, lda, m, Tinv, ldt,
-                           info, col_base);
-    else
-        hipLaunchKernelGGL(k_potrf_f64<8>, dim3(1), dim3(NW * 64), 0, s, A, lda, m, Tinv, ldt,
-                           info, col_base);
+    hipLaunchKernelGGL(k_potrf_f64, dim3(m / NB), dim3(256), 0, s, A, lda, m, Tinv, ldt, info,
+                       col_base, flags, epoch, err);
     return hipGetLastError();
 }
 

@@ -18,9 +18,10 @@ __device__ inline double wave_sum(double x)
 }
 
 // y (-)= op(T) x for each task, in blocks of 32 output entries.
-// Non-transposed: each wave owns 8 rows, the lanes stride over the columns
-// and a fixed butterfly adds them. Transposed: thread (g, c) sums column c
-// over row group g of 8; the groups are added in order.
+// Non-transposed: each wave owns 8 rows and walks their columns together
+// (eight independent loads per step), then a fixed butterfly adds the lanes.
+// Transposed: thread (g, c) sums column c over row group g of 8 (unrolled);
+// the groups are added in order.
 __global__ __launch_bounds__(256) void k_gemv_f64(const GemvTask* __restrict__ tasks, int m)
 {
     __shared__ double part[8][32];
@@ -29,21 +30,39 @@ __global__ __launch_bounds__(256) void k_gemv_f64(const GemvTask* __restrict__ t
     const GemvTask tk = tasks[t];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     if (!tk.trans) {
-        for (int rr = 0; rr < 8; ++rr) {
-            const int row = blk * 32 + wave * 8 + rr;
-            const double* Tr = tk.T + (size_t)row * tk.ld;
-            double s = 0.0;
-            for (int c = lane; c < m; c += 64) s += Tr[c] * tk.x[c];
-            s = wave_sum(s);
-            if (lane == 0) tk.y[row] = tk.set ? s : tk.y[row] - s;
+        const int row0 = blk * 32 + wave * 8;
+        const double* Tr = tk.T + (size_t)row0 * tk.ld;
+        double s[8];
+#pragma unroll
+        for (int rr = 0; rr < 8; ++rr) s[rr] = 0.0;
+        for (int c = lane; c < m; c += 64) {
+            const double xc = tk.x[c];
+#pragma unroll
+            for (int rr = 0; rr < 8; ++rr) s[rr] += Tr[(size_t)rr * tk.ld + c] * xc;
+        }
+#pragma unroll
+        for (int rr = 0; rr < 8; ++rr) s[rr] = wave_sum(s[rr]);
+        if (lane < 8) {
+            double v = s[0];
+#pragma unroll
+            for (int rr = 1; rr < 8; ++rr) v = (lane == rr) ? s[rr] : v;
+            const int row = row0 + lane;
+            tk.y[row] = tk.set ? v : tk.y[row] - v;
         }
     } else {
         const int c = tid & 31, g = tid >> 5;
         const int col = blk * 32 + c;
         const int rows = m / 8;
-        double s = 0.0;
-        for (int r = g * rows; r < (g + 1) * rows; ++r) s += tk.T[(size_t)r * tk.ld + col] * tk.x[r];
-        part[g][c] = s;
+        const double* Tc = tk.T + (size_t)g * rows * tk.ld + col;
+        const double* xg = tk.x + g * rows;
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        for (int r = 0; r < rows; r += 4) {
+            s0 += Tc[(size_t)r * tk.ld] * xg[r];
+            s1 += Tc[(size_t)(r + 1) * tk.ld] * xg[r + 1];
+            s2 += Tc[(size_t)(r + 2) * tk.ld] * xg[r + 2];
+            s3 += Tc[(size_t)(r + 3) * tk.ld] * xg[r + 3];
+        }
+        part[g][c] = (s0 + s1) + (s2 + s3);
         __syncthreads();
         if (tid < 32) {
             double tot = part[0][c];
@@ -62,8 +81,17 @@ hipError_t launch_gemv_f64(const GemvTask* d_tasks, int ntask, int m, hipStream_
 }
 
 // out_i = [base_i -] (sum_{j < nb} v exp(-|a_i - b_j|^2 / (2 l)) x_j + [noise] s2 x_i)
-// A workgroup owns 32 rows of A, 8 lanes per row striding over j; the 8
-// partial sums are combined by a fixed butterfly.
+// A workgroup owns 64 rows of A; each group of 16 lanes owns 4 of them (kept
+// in registers), and lane t % 16 of the group takes the points j = t % 16
+// (mod 16) of every chunk of 256 points of B staged in LDS with their x_j.
+// The 16 partial sums of a row are combined by a fixed butterfly.
+namespace {
+constexpr int MV_ROWS = 64;   // rows per workgroup
+constexpr int MV_R = 4;       // rows per thread
+constexpr int MV_CH = 256;    // training points per LDS chunk
+constexpr int MV_MAXD = 16;   // features kept in registers / LDS
+}
+
 __global__ __launch_bounds__(256) void k_kernel_matvec(const double* __restrict__ A, int64_t na,
                                                        const double* __restrict__ B, int64_t nb,
                                                        int D, double l, double v, double s2,
@@ -71,29 +99,76 @@ __global__ __launch_bounds__(256) void k_kernel_matvec(const double* __restrict_
                                                        const double* __restrict__ base,
                                                        double* __restrict__ out)
 {
+    __shared__ double Sb[MV_MAXD][MV_CH + 1];
+    __shared__ double Sx[MV_CH];
     const int tid = threadIdx.x;
-    const int64_t i = (int64_t)blockIdx.x * 32 + tid / 8;
-    const int sub = tid & 7;
+    const int sub = tid & 15, grp = tid >> 4;  // 16 groups of 16 lanes
+    const int64_t i0 = (int64_t)blockIdx.x * MV_ROWS + grp * MV_R;
     const double inv2l = 1.0 / (2.0 * l);
-    double s = 0.0;
-    if (i < na) {
-        const double* a = A + i * D;
-        for (int64_t j = sub; j < nb; j += 8) {
-            const double* b = B + j * D;
-            double d2 = 0.0;
-            for (int d = 0; d < D; ++d) {
-                const double t = a[d] - b[d];
-                d2 += t * t;
+    double a[MV_R][MV_MAXD];
+#pragma unroll
+    for (int r = 0; r < MV_R; ++r)
+#pragma unroll
+        for (int d = 0; d < MV_MAXD; ++d)
+            a[r][d] = (i0 + r < na && d < D) ? A[(i0 + r) * D + d] : 0.0;
+    double acc[MV_R];
+#pragma unroll
+    for (int r = 0; r < MV_R; ++r) acc[r] = 0.0;
+
+    for (int64_t j0 = 0; j0 < nb; j0 += MV_CH) {
+        __syncthreads();
+        for (int e = tid; e < MV_CH * MV_MAXD; e += 256) {
+            const int jj = e / MV_MAXD, d = e % MV_MAXD;
+            Sb[d][jj] = (j0 + jj < nb && d < D) ? B[(j0 + jj) * D + d] : 0.0;
+        }
+        if (tid < MV_CH) Sx[tid] = (j0 + tid < nb) ? x[j0 + tid] : 0.0;
+        __syncthreads();
+        for (int jj = sub; jj < MV_CH; jj += 16) {
+            const double xj = Sx[jj];
+            double d2[MV_R];
+#pragma unroll
+            for (int r = 0; r < MV_R; ++r) d2[r] = 0.0;
+#pragma unroll
+            for (int d = 0; d < MV_MAXD; ++d) {
+                const double bd = Sb[d][jj];
+#pragma unroll
+                for (int r = 0; r < MV_R; ++r) {
+                    const double q = a[r][d] - bd;
+                    d2[r] += q * q;
+                }
             }
-            s += v * exp(-d2 * inv2l) * x[j];
+#pragma unroll
+            for (int r = 0; r < MV_R; ++r) acc[r] += v * exp(-d2[r] * inv2l) * xj;
         }
     }
-    s += __shfl_xor(s, 4, 64);
-    s += __shfl_xor(s, 2, 64);
-    s += __shfl_xor(s, 1, 64);
-    if (i < na && sub == 0) {
-        if (noise && i < nb) s += s2 * x[i];
-        out[i] = base ? base[i] - s : s;
+    // features beyond MV_MAXD (rare): recompute those rows' sums exactly
+    if (D > MV_MAXD) {
+#pragma unroll
+        for (int r = 0; r < MV_R; ++r) {
+            acc[r] = 0.0;
+            if (i0 + r >= na) continue;
+            for (int64_t j = sub; j < nb; j += 16) {
+                double d2 = 0.0;
+                for (int d = 0; d < D; ++d) {
+                    const double q = A[(i0 + r) * D + d] - B[j * D + d];
+                    d2 += q * q;
+                }
+                acc[r] += v * exp(-d2 * inv2l) * x[j];
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < MV_R; ++r) {
+        double sr = acc[r];
+        sr += __shfl_xor(sr, 8, 64);
+        sr += __shfl_xor(sr, 4, 64);
+        sr += __shfl_xor(sr, 2, 64);
+        sr += __shfl_xor(sr, 1, 64);
+        const int64_t i = i0 + r;
+        if (sub == 0 && i < na) {
+            if (noise && i < nb) sr += s2 * x[i];
+            out[i] = base ? base[i] - sr : sr;
+        }
     }
 }
 
@@ -102,7 +177,7 @@ hipError_t launch_kernel_matvec(const double* A, int64_t na, const double* B, in
                                 const double* base, double* out, hipStream_t s)
 {
     if (na <= 0) return hipSuccess;
-    const unsigned grid = (unsigned)((na + 31) / 32);
+    const unsigned grid = (unsigned)((na + MV_ROWS - 1) / MV_ROWS);
     hipLaunchKernelGGL(k_kernel_matvec, dim3(grid), dim3(256), 0, s, A, na, B, nb, D, l, v, s2,
                        noise ? 1 : 0, x, base, out);
     return hipGetLastError();
