@@ -23,6 +23,18 @@ sys.path.insert(0, ROOT)
 METRIC = "Cholesky+predict GFLOP/s & % peak at n=16384, FP64 vs mixed, at stated error"
 FP64_PEAK_TFLOPS = 78.6     # MI355X dense FP64 (vector = matrix)
 
+# HBM bytes per dispatch of the tile-update kernel from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE runs scaled by a 1 GiB copy (profiles/fp64_c3_hbm_traffic.md); only
+# valid for the kernel source they were taken on.
+UPDATE_TRAFFIC = {"k_update_sha256_16": "5f340a6b621493c1", "bytes_per_launch": 681831762}
+
+
+def update_traffic():
+    import hashlib
+    path = os.path.join(ROOT, "paper_2602_19683_amd", "csrc", "k_update.hip")
+    h = hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+    return UPDATE_TRAFFIC["bytes_per_launch"] if h == UPDATE_TRAFFIC["k_update_sha256_16"] else None
+
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
@@ -87,6 +99,8 @@ def main():
                     help="1 = no overlap between launches (isolated kernel timings)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run one device-to-device copy of MIB MiB (for HBM counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs the GP hot path on one GPU only; "
@@ -95,6 +109,15 @@ def main():
         sys.exit(2)
 
     import torch
+    if args.calibrate_copy:
+        nel = args.calibrate_copy * (1 << 20) // 8
+        a = torch.ones(nel, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copied {args.calibrate_copy} MiB (read {args.calibrate_copy} MiB, write {args.calibrate_copy} MiB)")
+        return
     from gpr_inputs import DEFAULT_HYPER, nfir_train_test
     from paper_2602_19683_amd import Context
 
@@ -147,7 +170,8 @@ def main():
     achieved = fl / (tms * 1e-3) / 1e12 if tms else 0.0
     roofline = {"bound": "mfma", "kernel": "k_update_f64 (GEMM/SYRK tile updates)",
                 "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None,
+                "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": update_traffic(),
+                "traffic_unit": "bytes per launch",
                 "avg_launch_ms": round(tms / max(nl, 1), 4),
                 "flops_per_launch": round(fl / max(nl, 1), 1)}
     errors = None
