@@ -95,6 +95,8 @@ def main():
     ap.add_argument("--n-test", type=int, default=4096)
     ap.add_argument("--tile", type=int, default=512)
     ap.add_argument("--precision", default="fp64", choices=["fp64"])
+    ap.add_argument("--path", default="fused", choices=["fused", "calls"],
+                    help="fused: gpr_fit_predict (one sweep); calls: assemble + cholesky + predict")
     ap.add_argument("--streams", type=int, default=2,
                     help="1 = no overlap between launches (isolated kernel timings)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -123,7 +125,7 @@ def main():
 
     n, ns, tile, D = args.n, args.n_test, args.tile, 8
     h = DEFAULT_HYPER
-    log(f"bench: n={n} n_test={ns} tile={tile} precision={args.precision} "
+    log(f"bench: path={args.path} n={n} n_test={ns} tile={tile} precision={args.precision} "
         f"steps={args.steps} warmup={args.warmup}")
     X, y, Xs = nfir_train_test(n, ns, D)
     dev = lambda a: torch.from_numpy(a).to("cuda:0")
@@ -134,9 +136,12 @@ def main():
     K = ctx.assemble(Xd, h, tile)
 
     def step():
-        ctx.assemble(Xd, h, tile, K=K)
-        ctx.cholesky(K, args.precision)
-        ctx.predict(K, Xd, yd, Xsd, h, mean=mean, cov=cov)
+        if args.path == "fused":
+            ctx.fit_predict(Xd, yd, Xsd, h, tile, args.precision, K=K, mean=mean, cov=cov)
+        else:
+            ctx.assemble(Xd, h, tile, K=K)
+            ctx.cholesky(K, args.precision)
+            ctx.predict(K, Xd, yd, Xsd, h, mean=mean, cov=cov)
 
     for i in range(args.warmup):
         step()
@@ -191,6 +196,8 @@ def main():
                                f"covariance, n={n}, n_test={ns}, D={D}, tile {tile}, "
                                f"{args.precision}",
                    "n": n, "n_test": ns, "D": D, "tile": tile, "precision": args.precision,
+                   "entry": "gpr_fit_predict" if args.path == "fused" else
+                            "gpr_assemble + gpr_cholesky + gpr_predict",
                    "parallelism": "single GPU"},
         "pct_fp64_peak": round(100 * value / (FP64_PEAK_TFLOPS * 1e3), 2),
         "roofline": roofline,

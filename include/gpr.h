@@ -158,6 +158,22 @@ int gpr_predict(gpr_ctx* ctx, gpr_tiled* L, const double* X, const double* y,
                 gpr_hyper h, double* mean, double* cov, gpr_ir_stats* ir,
                 void* stream);
 
+/* The whole path in one call: assembles K = k(X, X) + sigma^2 I into
+ * *K_inout (allocated if NULL, reused otherwise, as in gpr_assemble),
+ * factorises it and, in the same tile sweep, turns the appended test rows
+ * into V^T = K_{X*,X} L^{-T} and the test block into
+ * K_{X*,X*} - V^T V (eq. (3)); then the mean (eq. (2)). The results equal
+ * those of gpr_assemble + gpr_cholesky + gpr_predict bit for bit; the single
+ * sweep gives every step more independent tile updates to overlap with the
+ * diagonal-tile chain. Afterwards *K_inout holds the factor L (usable by
+ * gpr_predict and gpr_solve). cov may be NULL (mean only: no covariance
+ * rows are swept). info_dev as in gpr_cholesky. */
+int gpr_fit_predict(gpr_ctx* ctx, const double* X, const double* y, int64_t n,
+                    const double* Xs, int64_t n_test, int32_t D, gpr_hyper h,
+                    int32_t tile, gpr_precision prec, gpr_tiled** K_inout,
+                    double* mean, double* cov, int32_t* info_dev,
+                    gpr_ir_stats* ir, void* stream);
+
 /* x = K^{-1} b through the factor: forward substitution L beta = b, then
  * backward substitution L^T x = beta (the solve recipe after eq. (2)).
  * L: handle holding a factor; b, x: device vectors of length n (may alias).
@@ -199,14 +215,14 @@ int gpr_sync(gpr_ctx* ctx, void* stream, int64_t* column);
 /* ---- instrumentation ------------------------------------------------------
  * Per-kernel timers (the role APEX plays in Sec. 3.1): while enabled, every
  * launch the context issues is bracketed by HIP timing events on the stream
- * it runs on. Kinds: 0 POTRF (with the diagonal-tile inverse), 1 TRSM,
- * 2 tile update (GEMM / SYRK), 3 assembly, 4 triangular-solve GEMV,
- * 5 kernel matvec (mean / residual), 6 export to dense. */
+ * it runs on. Kinds: 0 POTRF, 1 inverse of the diagonal tiles, 2 TRSM,
+ * 3 tile update (GEMM / SYRK), 4 assembly, 5 triangular-solve GEMV,
+ * 6 kernel matvec (mean / residual), 7 export to dense. */
 int gpr_profile_enable(gpr_ctx* ctx, int on);
 
 /* Totals for one kind over the launches recorded since the last reset:
  * number of launches, summed device time in ms, and summed algorithmic
- * flops (GEMM tile 2 m^3, SYRK / TRSM tile m^3, POTRF + inverse 2 m^3 / 3,
+ * flops (GEMM tile 2 m^3, SYRK / TRSM tile m^3, POTRF and inverse m^3 / 3 each,
  * GEMV tile 2 m^2, kernel matvec 2 per entry) and bytes (assembly and export:
  * bytes written). Blocks until the recorded work is done. reset != 0 clears
  * all kinds after reading. Any out pointer may be NULL. */

@@ -157,8 +157,8 @@ int ensure_events(gpr_ctx* ctx, size_t n)
     return GPR_OK;
 }
 
-enum ProfKind { PK_POTRF = 0, PK_TRSM = 1, PK_UPDATE = 2, PK_ASSEMBLE = 3, PK_GEMV = 4,
-                PK_MATVEC = 5, PK_EXPORT = 6 };
+enum ProfKind { PK_POTRF = 0, PK_TRTRI = 1, PK_TRSM = 2, PK_UPDATE = 3, PK_ASSEMBLE = 4,
+                PK_GEMV = 5, PK_MATVEC = 6, PK_EXPORT = 7, PK_COUNT = 8 };
 
 hipEvent_t timing_event(gpr_ctx* ctx)
 {
@@ -257,7 +257,8 @@ SweepPlan plan_sweep(const SweepMats& X, int mode, DescBuffer& db)
             std::vector<TrsmTask> v;
             for (int t = L.first; t < L.first + L.count; ++t) {
                 const SchedTask& k = P.sched.tasks[t];
-                v.push_back({X.at(k.I, k.J), X.tinv + (size_t)k.J * m * m, m, m});
+                v.push_back({X.at(k.I, k.J), X.at(k.J, k.J), X.tinv + (size_t)k.J * m * m,
+                             nullptr, m, m, m, 0});
             }
             P.off[li] = db.add(v.data(), v.size() * sizeof(TrsmTask));
         } else if (L.kind == LK_UPDATE) {
@@ -299,10 +300,9 @@ int run_sweep(gpr_ctx* ctx, const SweepMats& X, const SweepPlan& P, const DescBu
             const int J = L.step;
             double* A = X.at(J, J);
             double* Ti = X.tinv + (size_t)J * m * m;
-            ProfScope ps(ctx, st, PK_POTRF, 2.0 * m3 / 3.0, 0.0);
+            ProfScope ps(ctx, st, PK_POTRF, m3 / 3.0, 0.0);
             HIP_TRY(launch_potrf_f64(A, m, m, Ti, m, ctx->d_info, (int64_t)J * m, ctx->d_flags,
                                      ++ctx->epoch, ctx->d_info + 2, st));
-            HIP_TRY(launch_trtri_f64(A, m, Ti, m, m, st));
         } else if (L.kind == LK_TRSM) {
             ProfScope ps(ctx, st, PK_TRSM, L.count * m3, 0.0);
             HIP_TRY(launch_trsm_f64(db.dev<TrsmTask>(ctx, P.off[li]), L.count, m, st));
@@ -531,6 +531,11 @@ int gpr_cholesky(gpr_ctx* ctx, gpr_tiled* K, gpr_precision prec, int32_t* info_d
     HIP_TRY(launch_set_int(ctx->d_info, 0, s));
     rc = run_sweep(ctx, X, P, db, s);
     if (rc) return rc;
+    {
+        // full inverses of the diagonal tiles for the vector solves, all at once
+        ProfScope ps(ctx, s, PK_TRTRI, M * (double)m * m * m / 3.0, 0.0);
+        HIP_TRY(launch_trtri_f64(kmat(K), M, K->tinv, s));
+    }
     rc = finish_info(ctx, info_dev, s);
     if (rc) return rc;
     K->state = GPR_STATE_L;
@@ -568,6 +573,89 @@ int gpr_cholesky_dense(gpr_ctx* ctx, double* A, int64_t n, int32_t tile, gpr_pre
     return end_call(ctx, s);
 }
 
+}  // extern "C"
+
+namespace {
+
+// Mean (and covariance) with the factor in L. fused: L still holds K, and
+// the factorisation runs in the same sweep as the covariance rows.
+int predict_impl(gpr_ctx* ctx, gpr_tiled* L, const double* X, const double* y, int64_t n,
+                 const double* Xs, int64_t n_test, int32_t D, const gpr_hyper& h, double* mean,
+                 double* cov, int32_t* info_dev, hipStream_t s, bool fused)
+{
+    const int m = L->m, M = L->M;
+    const int Mhat = (int)((n_test + m - 1) / m);
+    const size_t npad = (size_t)M * m;
+    const size_t vec_bytes = 3 * npad * sizeof(double);
+    const size_t v_bytes = cov ? (size_t)Mhat * M * m * m * sizeof(double) : 0;
+    const size_t s_bytes = cov ? (size_t)Mhat * (Mhat + 1) / 2 * m * m * sizeof(double) : 0;
+    int rc = ensure_device_bytes(&ctx->d_ws, &ctx->ws_cap, vec_bytes + v_bytes + s_bytes + 256);
+    if (rc) return rc;
+    if (fused && !L->tinv) {
+        if (hipMalloc(reinterpret_cast<void**>(&L->tinv), (size_t)M * m * m * sizeof(double)) !=
+            hipSuccess) {
+            (void)hipGetLastError();
+            return GPR_ENOMEM;
+        }
+    }
+    double* r = reinterpret_cast<double*>(ctx->d_ws);
+    double* beta = r + npad;
+    double* alpha = beta + npad;
+    double* Vb = alpha + npad;
+    double* Sb = reinterpret_cast<double*>(reinterpret_cast<char*>(Vb) + v_bytes);
+
+    DescBuffer db;
+    SolvePlan SP = plan_solves(L, r, beta, alpha, db);
+    SweepMats SM{kmat(L), L->tinv, TileMat{Vb, m, 1, M}, TileMat{Sb, m, 0, 0}, M, cov ? Mhat : 0, m};
+    SweepPlan PP;
+    const int mode = fused ? (cov ? SWEEP_FUSED : SWEEP_CHOLESKY) : SWEEP_PREDICT;
+    if (fused || cov) PP = plan_sweep(SM, mode, db);
+    rc = db.upload(ctx, s);
+    if (rc) return rc;
+
+    if (cov) {
+        // K_{X*,X} tiles (to become V^T) and lower tiles of K_{X*,X*}; no noise
+        ProfScope ps(ctx, s, PK_ASSEMBLE, 0.0, (double)(v_bytes + s_bytes));
+        HIP_TRY(launch_assemble(SM.V, Mhat, Xs, n_test, X, n, D, h.lengthscale,
+                                h.vertical_variance, h.noise_variance, false, false, s));
+        HIP_TRY(launch_assemble(SM.S, Mhat, Xs, n_test, Xs, n_test, D, h.lengthscale,
+                                h.vertical_variance, h.noise_variance, false, false, s));
+    }
+    if (fused) HIP_TRY(launch_set_int(ctx->d_info, 0, s));
+    if (fused || cov) {
+        rc = run_sweep(ctx, SM, PP, db, s);
+        if (rc) return rc;
+    }
+    if (fused) {
+        ProfScope ps(ctx, s, PK_TRTRI, M * (double)m * m * m / 3.0, 0.0);
+        HIP_TRY(launch_trtri_f64(kmat(L), M, L->tinv, s));
+    }
+    if (fused) {
+        rc = finish_info(ctx, info_dev, s);
+        if (rc) return rc;
+        L->state = GPR_STATE_L;
+    }
+    // alpha = K^{-1} y via the two triangular solves (Sec. 4.1)
+    HIP_TRY(launch_copy_f64(y, r, n, (int64_t)npad, s));
+    rc = run_solves(ctx, L, SP, db, s);
+    if (rc) return rc;
+    // mean = K_{X*,X} alpha, eq. (2), without storing K_{X*,X}
+    {
+        ProfScope ps(ctx, s, PK_MATVEC, 2.0 * (double)n_test * (double)n, 0.0);
+        HIP_TRY(launch_kernel_matvec(Xs, n_test, X, n, D, h.lengthscale, h.vertical_variance,
+                                     h.noise_variance, false, alpha, nullptr, mean, s));
+    }
+    if (cov) {
+        ProfScope ps(ctx, s, PK_EXPORT, 0.0, (double)n_test * n_test * sizeof(double));
+        HIP_TRY(launch_tiled_to_dense(SM.S, n_test, cov, n_test, true, s));
+    }
+    return GPR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int gpr_predict(gpr_ctx* ctx, gpr_tiled* L, const double* X, const double* y, int64_t n,
                 const double* Xs, int64_t n_test, int32_t D, gpr_hyper h, double* mean,
                 double* cov, gpr_ir_stats* ir, void* stream)
@@ -581,56 +669,39 @@ int gpr_predict(gpr_ctx* ctx, gpr_tiled* L, const double* X, const double* y, in
     hipStream_t s = static_cast<hipStream_t>(stream);
     int rc = begin_call(ctx, s);
     if (rc) return rc;
-    const int m = L->m, M = L->M;
-    const int Mhat = (int)((n_test + m - 1) / m);
-    const size_t npad = (size_t)M * m;
-    const size_t vec_bytes = 3 * npad * sizeof(double);
-    const size_t v_bytes = cov ? (size_t)Mhat * M * m * m * sizeof(double) : 0;
-    const size_t s_bytes = cov ? (size_t)Mhat * (Mhat + 1) / 2 * m * m * sizeof(double) : 0;
-    rc = ensure_device_bytes(&ctx->d_ws, &ctx->ws_cap, vec_bytes + v_bytes + s_bytes + 256);
+    rc = predict_impl(ctx, L, X, y, n, Xs, n_test, D, h, mean, cov, nullptr, s, false);
     if (rc) return rc;
-    double* r = reinterpret_cast<double*>(ctx->d_ws);
-    double* beta = r + npad;
-    double* alpha = beta + npad;
-    double* Vb = alpha + npad;
-    double* Sb = reinterpret_cast<double*>(reinterpret_cast<char*>(Vb) + v_bytes);
-
-    DescBuffer db;
-    SolvePlan SP = plan_solves(L, r, beta, alpha, db);
-    SweepMats SM{kmat(L), L->tinv, TileMat{Vb, m, 1, M}, TileMat{Sb, m, 0, 0}, M, Mhat, m};
-    SweepPlan PP;
-    if (cov) PP = plan_sweep(SM, SWEEP_PREDICT, db);
-    rc = db.upload(ctx, s);
-    if (rc) return rc;
-
-    // alpha = K^{-1} y via the two triangular solves (Sec. 4.1)
-    HIP_TRY(launch_copy_f64(y, r, n, (int64_t)npad, s));
-    rc = run_solves(ctx, L, SP, db, s);
-    if (rc) return rc;
-    // mean = K_{X*,X} alpha, eq. (2), without storing K_{X*,X}
-    {
-        ProfScope ps(ctx, s, PK_MATVEC, 2.0 * (double)n_test * (double)n, 0.0);
-        HIP_TRY(launch_kernel_matvec(Xs, n_test, X, n, D, h.lengthscale, h.vertical_variance,
-                                     h.noise_variance, false, alpha, nullptr, mean, s));
-    }
-    if (cov) {
-        // K_{X*,X} tiles (to become V^T) and lower tiles of K_{X*,X*}; no noise
-        {
-            ProfScope ps(ctx, s, PK_ASSEMBLE, 0.0, (double)(v_bytes + s_bytes));
-            HIP_TRY(launch_assemble(SM.V, Mhat, Xs, n_test, X, n, D, h.lengthscale,
-                                    h.vertical_variance, h.noise_variance, false, false, s));
-            HIP_TRY(launch_assemble(SM.S, Mhat, Xs, n_test, Xs, n_test, D, h.lengthscale,
-                                    h.vertical_variance, h.noise_variance, false, false, s));
-        }
-        rc = run_sweep(ctx, SM, PP, db, s);
-        if (rc) return rc;
-        ProfScope ps(ctx, s, PK_EXPORT, 0.0, (double)n_test * n_test * sizeof(double));
-        HIP_TRY(launch_tiled_to_dense(SM.S, n_test, cov, n_test, true, s));
-    }
     if (ir) {
         ir->iters = 0;
         ir->rel_residual = -1.0;
         ir->fallback_precision = L->prec;
+    }
+    return end_call(ctx, s);
+}
+
+int gpr_fit_predict(gpr_ctx* ctx, const double* X, const double* y, int64_t n, const double* Xs,
+                    int64_t n_test, int32_t D, gpr_hyper h, int32_t tile, gpr_precision prec,
+                    gpr_tiled** K_inout, double* mean, double* cov, int32_t* info_dev,
+                    gpr_ir_stats* ir, void* stream)
+{
+    if (!ctx || !X || !y || !K_inout || n < 1 || D < 1 || n_test < 1 || !Xs || !mean ||
+        !valid_tile(tile) || !valid_hyper(h))
+        return GPR_EINVAL;
+    if (prec != GPR_FP64 && prec != GPR_MIXED_FP32 && prec != GPR_MIXED_BF16) return GPR_EINVAL;
+    if (prec != GPR_FP64) return GPR_ENOTSUP;
+    int rc = gpr_assemble(ctx, X, n, D, h, tile, K_inout, stream);
+    if (rc) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    rc = begin_call(ctx, s);
+    if (rc) return rc;
+    gpr_tiled* K = *K_inout;
+    rc = predict_impl(ctx, K, X, y, n, Xs, n_test, D, h, mean, cov, info_dev, s, true);
+    if (rc) return rc;
+    K->prec = prec;
+    if (ir) {
+        ir->iters = 0;
+        ir->rel_residual = -1.0;
+        ir->fallback_precision = prec;
     }
     return end_call(ctx, s);
 }
@@ -681,7 +752,7 @@ int gpr_profile_enable(gpr_ctx* ctx, int on)
 int gpr_profile_read(gpr_ctx* ctx, int kind, int64_t* launches, double* total_ms, double* flops,
                      double* bytes, int reset)
 {
-    if (!ctx || kind < 0 || kind > 6) return GPR_EINVAL;
+    if (!ctx || kind < 0 || kind >= PK_COUNT) return GPR_EINVAL;
     int rc = check_device(ctx->device);
     if (rc) return rc;
     rc = resolve_profile(ctx);
@@ -691,7 +762,7 @@ int gpr_profile_read(gpr_ctx* ctx, int kind, int64_t* launches, double* total_ms
     if (flops) *flops = ctx->p_flops[kind];
     if (bytes) *bytes = ctx->p_bytes[kind];
     if (reset) {
-        for (int k = 0; k < 8; ++k) {
+        for (int k = 0; k < PK_COUNT; ++k) {
             ctx->p_launches[k] = 0;
             ctx->p_ms[k] = ctx->p_flops[k] = ctx->p_bytes[k] = 0.0;
         }

@@ -52,12 +52,16 @@ struct UpdateTask {
     int ldc, lda, ldb, flags;
 };
 
-// B := B * Tinv^T in place (TRSM of Fig. 1 written as L_IJ = K_IJ L_JJ^{-T},
-// with Tinv = L_JJ^{-1} lower triangular).
+// B := B * L_JJ^{-T} in place (TRSM of Fig. 1 read as L_IJ = K_IJ L_JJ^{-T}).
+// L: the factored diagonal tile; Dinv: an array whose 32 x 32 diagonal blocks
+// hold the inverses of L's 32 x 32 diagonal blocks. B32 (optional): also
+// write the result rounded to FP32 there (m x m, leading dimension m).
 struct TrsmTask {
     double* B;
-    const double* Tinv;
-    int ldb, ldt;
+    const double* L;
+    const double* Dinv;
+    float* B32;
+    int ldb, ldl, ldd, pad;
 };
 
 // y (-)= op(T) x on one m x m tile; op = transpose if trans; set: y = op(T) x.
@@ -99,8 +103,10 @@ hipError_t launch_trsm_f64(const TrsmTask* d_tasks, int ntask, int m, hipStream_
 hipError_t launch_potrf_f64(double* A, int lda, int m, double* Tinv, int ldt, int* info,
                             int64_t col_base, unsigned* flags, unsigned epoch, int* err,
                             hipStream_t s);
-hipError_t launch_trtri_f64(const double* L, int lda, double* Tinv, int ldt, int m,
-                            hipStream_t s);
+// Inverses of the M factored diagonal tiles (J, J) of the lower-tiled K;
+// the inverse of tile J goes to Tinv + J m^2 (leading dimension m), whose
+// 32 x 32 diagonal blocks must already hold the block inverses.
+hipError_t launch_trtri_f64(const TileMat& K, int M, double* Tinv, hipStream_t s);
 hipError_t launch_gemv_f64(const GemvTask* d_tasks, int ntask, int m, hipStream_t s);
 
 // out_i = base_i - k(A_i, B) x  (subtract) or out_i = k(A_i, B) x  (base == nullptr),

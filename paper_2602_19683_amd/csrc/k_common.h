@@ -39,12 +39,14 @@ __device__ inline double lane_bcast(double x, int l)
     return __hiloint2double(hi, lo);
 }
 
-// Orders LDS accesses of the lanes of one wavefront (no workgroup barrier).
+// Orders the LDS accesses of one wavefront around this point (no workgroup
+// barrier): the empty asm with a memory clobber stops the compiler from
+// moving memory accesses across it, and the LDS executes one wave's accesses
+// in issue order, so a lane's read after it sees another lane's earlier write.
 __device__ inline void wave_lds_sync()
 {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __asm__ __volatile__("" ::: "memory");
     __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 }  // namespace gpr

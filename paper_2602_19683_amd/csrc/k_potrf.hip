@@ -17,7 +17,9 @@
 //
 // TRTRI: block column c of Tinv = L^{-1} is X_c = Dinv_c and
 //     X_r = -Dinv_r sum_{s=c}^{r-1} L[r, s] X_s,   r > c,
-// one workgroup per block column, sequential in r.
+// one workgroup per block column, sequential in r; one launch inverts many
+// diagonal tiles at once (it is off the critical path: TRSM uses only the
+// 32 x 32 block inverses).
 #include "gpr_internal.h"
 #include "k_common.h"
 
@@ -31,10 +33,15 @@ constexpr unsigned SPIN_LIMIT = 1u << 22;
 }  // namespace
 
 // Unblocked Cholesky of the 32 x 32 block in S (lower triangle read), by one
-// wave; lane i < 32 owns row i. On return S holds L (zeros above the
+// wave; lane i < 32 owns row i in registers and the entries of column j are
+// fetched from their owners with readlane (right-looking). One reciprocal per
+// pivot scales the column. The inverse is formed column per lane by forward
+// substitution, multiplying by the stored pivot reciprocals, with four
+// independent partial sums per entry. On return S holds L (zeros above the
 // diagonal) and Si holds L^{-1} (zeros above). Returns the first failing
-// local column or -1.
-__device__ static int factor_diag32(double (*S)[NB + 1], double (*Si)[NB + 1], int lane)
+// local column or -1. dv: 32 doubles of LDS scratch.
+__device__ static int factor_diag32(double (*S)[NB + 1], double (*Si)[NB + 1], double* dv,
+                                    int lane)
 {
     const int i = lane & 31;
     double a[NB];
@@ -46,8 +53,9 @@ __device__ static int factor_diag32(double (*S)[NB + 1], double (*Si)[NB + 1], i
         const double d = lane_bcast(a[j], j);
         if (!(d > 0.0) && bad < 0) bad = j;
         const double ljj = sqrt(d);
-        const double lij = (i == j) ? ljj : a[j] / ljj;
-        a[j] = (i >= j) ? lij : 0.0;
+        const double inv = 1.0 / ljj;
+        a[j] = (i == j) ? ljj : (i > j ? a[j] * inv : 0.0);
+        if (lane == 0) dv[j] = inv;
 #pragma unroll
         for (int k = j + 1; k < NB; ++k) {
             const double lkj = lane_bcast(a[j], k);
@@ -64,10 +72,16 @@ __device__ static int factor_diag32(double (*S)[NB + 1], double (*Si)[NB + 1], i
     double x[NB];
 #pragma unroll
     for (int r = 0; r < NB; ++r) {
-        double s = (r == i) ? 1.0 : 0.0;
+        double s0 = (r == i) ? 1.0 : 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
 #pragma unroll
-        for (int k = 0; k < r; ++k) s -= S[r][k] * x[k];
-        x[r] = s / S[r][r];
+        for (int k = 0; k < r; ++k) {
+            const double t = S[r][k] * x[k];
+            if ((k & 3) == 0) s0 -= t;
+            else if ((k & 3) == 1) s1 -= t;
+            else if ((k & 3) == 2) s2 -= t;
+            else s3 -= t;
+        }
+        x[r] = ((s0 + s1) + (s2 + s3)) * dv[r];
     }
     if (lane < 32) {
 #pragma unroll
@@ -162,6 +176,7 @@ __global__ __launch_bounds__(256) void k_potrf_f64(double* __restrict__ A, int l
     __shared__ double Bs[2][KC][SP];
     __shared__ double Sacc[NB][NB + 1];
     __shared__ double Si[NB][NB + 1];
+    __shared__ double dv[NB];
     const int w = blockIdx.x;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -195,7 +210,7 @@ __global__ __launch_bounds__(256) void k_potrf_f64(double* __restrict__ A, int l
             __syncthreads();  // Sacc reuse; L[w, q] visible to the workgroup
         } else {
             int bad = -1;
-            if (wave == 0) bad = factor_diag32(Sacc, Si, lane);
+            if (wave == 0) bad = factor_diag32(Sacc, Si, dv, lane);
             __syncthreads();
             for (int e = tid; e < NB * NB; e += 256) {
                 const int r = e / NB, c = e % NB;
@@ -219,14 +234,17 @@ __global__ __launch_bounds__(256) void k_potrf_f64(double* __restrict__ A, int l
     }
 }
 
-__global__ __launch_bounds__(256) void k_trtri_f64(const double* __restrict__ L, int lda,
-                                                   double* __restrict__ Tinv, int ldt, int m)
+__global__ __launch_bounds__(256) void k_trtri_f64(TileMat K, double* __restrict__ Tall)
 {
     __shared__ double As[2][KC][SP];
     __shared__ double Bs[2][KC][SP];
     __shared__ double Sacc[NB][NB + 1];
-    const int c = blockIdx.x;
+    const int m = K.m;
     const int P = m / NB;
+    const int J = blockIdx.x / P, c = blockIdx.x % P;
+    const double* __restrict__ L = tile_ptr(K, J, J);
+    double* __restrict__ Tinv = Tall + (size_t)J * m * m;
+    const int lda = m, ldt = m;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int lr = lane & 15, lk = lane >> 4;
@@ -267,9 +285,10 @@ hipError_t launch_potrf_f64(double* A, int lda, int m, double* Tinv, int ldt, in
     return hipGetLastError();
 }
 
-hipError_t launch_trtri_f64(const double* L, int lda, double* Tinv, int ldt, int m, hipStream_t s)
+hipError_t launch_trtri_f64(const TileMat& K, int M, double* Tinv, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_trtri_f64, dim3(m / NB), dim3(256), 0, s, L, lda, Tinv, ldt, m);
+    if (M <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_trtri_f64, dim3(M * (K.m / NB)), dim3(256), 0, s, K, Tinv);
     return hipGetLastError();
 }
 

@@ -1,12 +1,16 @@
-// k_trsm.hip -- batched TRSM tasks of Fig. 1, B := B L_JJ^{-T}, applied as
-// B Tinv^T with Tinv = L_JJ^{-1} (lower triangular, from k_trtri).
+// k_trsm.hip -- batched TRSM tasks of Fig. 1, B := B L_JJ^{-T} (the reading
+// L_IJ = K_IJ L_JJ^{-T}), by blocked substitution.
 //
-// One workgroup owns a strip of R rows of one tile: it stages the strip in
-// LDS (so the product can overwrite it in place), then each wave computes
-// R x 16 output blocks, interleaved across waves so that the triangular
-// work (output column j needs k <= j only) is balanced. Each Tinv fragment
-// read from L2 feeds R / 16 MFMAs; the k loop issues eight fragments' loads
-// before their MFMAs.
+// One workgroup owns a strip of R rows of one tile and keeps it in LDS. For
+// each 32-column block p of the diagonal factor, left to right:
+//     X_p = B_p Dinv_p^T                      (Dinv_p = inverse of the 32 x 32
+//                                              diagonal block p of L_JJ, made
+//                                              by POTRF)
+//     B_q -= X_p L_JJ[q, p]^T   for q > p     (right-looking strip update)
+// X_p is final when computed and is written out (and, in a mixed precision,
+// also as a low-precision copy for the tile updates that consume it). Only
+// the 32 x 32 diagonal-block inverses are needed, so no full inverse of L_JJ
+// sits on the critical path.
 #include "gpr_internal.h"
 #include "k_common.h"
 
@@ -23,8 +27,10 @@ __global__ __launch_bounds__(NW * 64) void k_trsm_f64(const TrsmTask* __restrict
     const int t = lid / strips, s = lid - t * strips;
     const TrsmTask tk = tasks[t];
     double* __restrict__ B = tk.B + (size_t)s * R * tk.ldb;
-    const int ldb = tk.ldb, ldt = tk.ldt;
-    const double* __restrict__ Ti = tk.Tinv;
+    const int ldb = tk.ldb, ldl = tk.ldl, ldd = tk.ldd;
+    const double* __restrict__ Lj = tk.L;
+    const double* __restrict__ Dv = tk.Dinv;
+    float* __restrict__ B32 = tk.B32 ? tk.B32 + (size_t)s * R * m : nullptr;
 
     const int tid = threadIdx.x;
     for (int e = 2 * tid; e < R * m; e += 2 * NW * 64) {
@@ -37,41 +43,49 @@ __global__ __launch_bounds__(NW * 64) void k_trsm_f64(const TrsmTask* __restrict
 
     const int lane = tid & 63, wave = tid >> 6;
     const int lr = lane & 15, lk = lane >> 4;
-    const int nct = m / 16;
-    for (int ct = wave; ct < nct; ct += NW) {
-        const int c0 = 16 * ct;
-        dbl4 acc[RT][2];
+    const int P = m / 32;
+    for (int p = 0; p < P; ++p) {
+        const int c0 = 32 * p;
+        // X_p = B_p Dinv_p^T: 2 RT output tiles of 16 x 16, waves 0 .. 2 RT - 1
+        dbl4 o = {0.0, 0.0, 0.0, 0.0};
+        const int rt = wave >> 1, ct = wave & 1;
+        if (wave < 2 * RT) {
+            const double* a = S + (16 * rt + lr) * ld + c0 + lk;
+            const double* b = Dv + (size_t)(c0 + 16 * ct + lr) * ldd + c0 + lk;
 #pragma unroll
-        for (int i = 0; i < RT; ++i) acc[i][0] = acc[i][1] = dbl4{0.0, 0.0, 0.0, 0.0};
-        const double* trow = Ti + (size_t)(c0 + lr) * ldt + lk;  // B[k][j] = Tinv[c0+j][k]
-        const double* srow = S + lr * ld + lk;                    // A[i][k] = strip[i][k]
-        const int kend = c0 + 16;                                 // Tinv[j][k] = 0 for k > j
-        int k = 0;
-        for (; k + 32 <= kend; k += 32) {
-            double b[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) b[u] = trow[k + 4 * u];
-#pragma unroll
-            for (int u = 0; u < 8; ++u)
-#pragma unroll
-                for (int i = 0; i < RT; ++i)
-                    acc[i][u & 1] = mfma16(srow[16 * i * ld + k + 4 * u], b[u], acc[i][u & 1]);
+            for (int k = 0; k < 32; k += 4) o = mfma16(a[k], b[k], o);
         }
-        if (k < kend) {  // remaining 16 columns
-            double b[4];
+        __syncthreads();  // every read of block p done before it is overwritten
+        if (wave < 2 * RT) {
 #pragma unroll
-            for (int u = 0; u < 4; ++u) b[u] = trow[k + 4 * u];
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int i = 0; i < RT; ++i)
-                    acc[i][u & 1] = mfma16(srow[16 * i * ld + k + 4 * u], b[u], acc[i][u & 1]);
+            for (int v = 0; v < 4; ++v) {
+                const int row = 16 * rt + drow(lk, v), col = c0 + 16 * ct + lr;
+                S[row * ld + col] = o[v];
+                B[(size_t)row * ldb + col] = o[v];
+                if (B32) B32[(size_t)row * m + col] = (float)o[v];
+            }
         }
+        __syncthreads();
+        // B_q -= X_p L[q, p]^T for q > p: tiles (q, rt, ct) spread over the waves
+        const int ntile = (P - p - 1) * 2 * RT;
+        for (int tt = wave; tt < ntile; tt += NW) {
+            const int q = p + 1 + tt / (2 * RT);
+            const int rr = (tt % (2 * RT)) >> 1, cc = tt & 1;
+            const int col0 = 32 * q + 16 * cc;
+            dbl4 acc;
 #pragma unroll
-        for (int i = 0; i < RT; ++i)
+            for (int v = 0; v < 4; ++v) acc[v] = S[(16 * rr + drow(lk, v)) * ld + col0 + lr];
+            const double* a = S + (16 * rr + lr) * ld + c0 + lk;
+            const double* b = Lj + (size_t)(col0 + lr) * ldl + c0 + lk;
+            double bv[8];
 #pragma unroll
-            for (int v = 0; v < 4; ++v)
-                B[(size_t)(16 * i + drow(lk, v)) * ldb + c0 + lr] = acc[i][0][v] + acc[i][1][v];
+            for (int u = 0; u < 8; ++u) bv[u] = b[4 * u];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc = mfma16(-a[4 * u], bv[u], acc);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) S[(16 * rr + drow(lk, v)) * ld + col0 + lr] = acc[v];
+        }
+        __syncthreads();
     }
 }
 

@@ -174,6 +174,34 @@ class Context:
                            "precision": st.fallback_precision},)
         return out
 
+    def fit_predict(self, X, y, Xs, hyper, tile, precision="fp64", full_cov=True, K=None,
+                    mean=None, cov=None, info=None, stream=None, ir_stats=False):
+        """Assembly, Cholesky and prediction in one tile sweep. Returns
+        (mean, cov, K) where K is the handle now holding the factor."""
+        import torch
+        n, D = X.shape
+        ns = Xs.shape[0]
+        if mean is None:
+            mean = torch.empty(ns, dtype=torch.float64, device=X.device)
+        if full_cov and cov is None:
+            cov = torch.empty(ns, ns, dtype=torch.float64, device=X.device)
+        h = ctypes.c_void_p(K.handle.value) if K is not None else ctypes.c_void_p()
+        ip = _dev_ptr_int(info) if info is not None else None
+        st = IRStats()
+        _check(self._lib.gpr_fit_predict(self._h, _dev_ptr(X, "X"), _dev_ptr(y, "y", n), n,
+                                         _dev_ptr(Xs, "Xs"), ns, D, _hyper(hyper), int(tile),
+                                         _prec(precision), ctypes.byref(h),
+                                         _dev_ptr(mean, "mean", ns),
+                                         _dev_ptr(cov, "cov", ns * ns) if full_cov else None,
+                                         ip, ctypes.byref(st), _stream(stream)),
+               "gpr_fit_predict")
+        K = K if K is not None else Tiled(h, self)
+        out = (mean, cov if full_cov else None, K)
+        if ir_stats:
+            return out + ({"iters": st.iters, "rel_residual": st.rel_residual,
+                           "precision": st.fallback_precision},)
+        return out
+
     def solve(self, L, b, x=None, stream=None):
         """x = K^{-1} b with the factor held by L."""
         import torch
@@ -200,7 +228,7 @@ class Context:
         return out_nlml, out_grad
 
     # ---- instrumentation --------------------------------------------------
-    PROFILE_KINDS = ("potrf", "trsm", "update", "assemble", "gemv", "matvec", "export")
+    PROFILE_KINDS = ("potrf", "trtri", "trsm", "update", "assemble", "gemv", "matvec", "export")
 
     def profile(self, on=True):
         _check(self._lib.gpr_profile_enable(self._h, int(bool(on))), "gpr_profile_enable")

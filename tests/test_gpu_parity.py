@@ -190,6 +190,30 @@ def test_predict_4096_tile_sweep(ctx, tile):
     assert em <= TOL and ec <= TOL
 
 
+@pytest.mark.parametrize("n,ns,tile", [(128, 128, 32), (1000, 300, 128), (4096, 1024, 256)])
+def test_fused_sweep_equals_three_calls(ctx, n, ns, tile):
+    say(f"fit_predict vs assemble+cholesky+predict n={n} n_test={ns} tile={tile}")
+    X, y, Xs = nfir_train_test(n, ns)
+    a = run_predict(ctx, X, y, Xs, DEFAULT_HYPER, tile)
+    Xd, yd, Xsd = dev(X), dev(y), dev(Xs)
+    info = torch.full((1,), -7, dtype=torch.int32, device="cuda")
+    mean, cov, K = ctx.fit_predict(Xd, yd, Xsd, DEFAULT_HYPER, tile, info=info)
+    m, c = host(mean), host(cov)
+    assert int(info.item()) == 0
+    np.testing.assert_array_equal(m, a[0])
+    np.testing.assert_array_equal(c, a[1])
+    # the handle now holds the factor: a second prediction through it agrees
+    m2, c2 = ctx.predict(K, Xd, yd, Xsd, DEFAULT_HYPER)
+    np.testing.assert_array_equal(host(m2), m)
+    np.testing.assert_array_equal(host(c2), c)
+    # mean only
+    m3, c3, K3 = ctx.fit_predict(Xd, yd, Xsd, DEFAULT_HYPER, tile, full_cov=False)
+    assert c3 is None
+    np.testing.assert_array_equal(host(m3), m)
+    K.free()
+    K3.free()
+
+
 def test_prediction_is_deterministic(ctx):
     n, ns, tile = 1024, 256, 128
     say(f"determinism n={n} n_test={ns} tile={tile}")
