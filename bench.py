@@ -86,6 +86,48 @@ def error_check(ctx, K, X, y, Xs, mean, h, Xd, yd):
             "rel_residual_sampled_rows": float(np.linalg.norm(r) / np.linalg.norm(y[rows]))}
 
 
+def mixed_runs(ctx, K, step, mean64, cov64, ms64, flops, args, log):
+    """FP32 / BF16 tile updates (FP64 POTRF, TRSM, solves, refinement): time
+    per step and errors against the FP64 results of the same GPU run (which
+    match the oracle to ~1e-13, see the parity tests)."""
+    import torch
+    L64 = ctx.to_dense(K)
+    m64, c64 = mean64.clone(), cov64.clone()
+    out = {}
+    for prec in ("fp32", "bf16"):
+        mean = torch.empty_like(m64)
+        cov = torch.empty_like(c64)
+        step(prec, mean, cov)
+        ctx.sync()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            st = step(prec, mean, cov)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        L = ctx.to_dense(K)
+        rel = lambda a, b: float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
+        out[prec] = {
+            "ms_per_step": round(ms, 4),
+            "value": round(flops / (ms * 1e-3) / 1e9, 2),
+            "speedup_vs_fp64": round(ms64 / ms, 3),
+            "precision_used": {0: "fp64", 1: "fp32", 2: "bf16"}[st["precision"]],
+            "ir_steps": st["iters"], "ir_rel_residual": st["rel_residual"],
+            "rel_mean_vs_fp64": rel(mean, m64),
+            "rel_cov_vs_fp64": rel(cov, c64),
+            "rel_L_vs_fp64": rel(torch.tril(L), torch.tril(L64)),
+        }
+        del L
+        torch.cuda.empty_cache()
+        log(f"mixed {prec}: {out[prec]}")
+    del L64
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -94,10 +136,12 @@ def main():
     ap.add_argument("--n", type=int, default=16384)
     ap.add_argument("--n-test", type=int, default=4096)
     ap.add_argument("--tile", type=int, default=512)
-    ap.add_argument("--precision", default="fp64", choices=["fp64"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16"])
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the FP32 / BF16 comparison runs after the FP64 line")
     ap.add_argument("--path", default="fused", choices=["fused", "calls"],
                     help="fused: gpr_fit_predict (one sweep); calls: assemble + cholesky + predict")
-    ap.add_argument("--streams", type=int, default=2,
+    ap.add_argument("--streams", type=int, default=3,
                     help="1 = no overlap between launches (isolated kernel timings)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true")
@@ -135,13 +179,13 @@ def main():
     ctx = Context(0, n_streams=args.streams)
     K = ctx.assemble(Xd, h, tile)
 
-    def step():
+    def step(prec=args.precision, out_mean=mean, out_cov=cov):
         if args.path == "fused":
-            ctx.fit_predict(Xd, yd, Xsd, h, tile, args.precision, K=K, mean=mean, cov=cov)
-        else:
-            ctx.assemble(Xd, h, tile, K=K)
-            ctx.cholesky(K, args.precision)
-            ctx.predict(K, Xd, yd, Xsd, h, mean=mean, cov=cov)
+            return ctx.fit_predict(Xd, yd, Xsd, h, tile, prec, K=K, mean=out_mean, cov=out_cov,
+                                   ir_stats=True)[3]
+        ctx.assemble(Xd, h, tile, K=K)
+        ctx.cholesky(K, prec)
+        return ctx.predict(K, Xd, yd, Xsd, h, mean=out_mean, cov=out_cov, ir_stats=True)[2]
 
     for i in range(args.warmup):
         step()
@@ -183,6 +227,9 @@ def main():
     if not args.no_check:
         errors = error_check(ctx, K, X, y, Xs, mean, h, Xd, yd)
         log(f"errors: {errors}")
+    mixed = None
+    if not args.no_mixed and args.precision == "fp64":
+        mixed = mixed_runs(ctx, K, step, mean, cov, ms, flops, args, log)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(h)
@@ -203,6 +250,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "errors": errors,
+        "mixed": mixed,
         "phases_ms_per_step": {k: round(v[1] / args.steps, 4) for k, v in prof.items()},
     }
     print(json.dumps(out), flush=True)

@@ -82,7 +82,7 @@ typedef enum {
 } gpr_precision;
 
 /* How the tile task graph is executed. GPR_EXEC_STREAMS: batched tile-task
- * launches on two HIP streams with one step of look-ahead.
+ * launches on three HIP streams with one step of look-ahead.
  * GPR_EXEC_PERSISTENT is reserved (GPR_ENOTSUP in this build). */
 typedef enum {
     GPR_EXEC_STREAMS = 0,
@@ -106,10 +106,11 @@ enum { GPR_STATE_EMPTY = 0, GPR_STATE_K = 1, GPR_STATE_L = 2 };
 /* ---- context ------------------------------------------------------------ */
 
 /* Creates a context on `device` (HIP ordinal). n_streams: number of streams
- * the executor may use (>= 1; it uses at most 2 -- the caller's stream for
- * the critical path and one bulk-update stream; Sec. 4.3 uses a user-sized
- * pool). With 1, every launch runs on the caller's stream in schedule order
- * (no overlap; useful to time kernels in isolation).
+ * the executor may use (>= 1; it uses at most 3 -- the caller's stream for
+ * the critical path, a panel stream and a bulk-update stream; Sec. 4.3 uses
+ * a user-sized pool). With 1, every launch runs on the caller's stream in
+ * schedule order (no overlap; useful to time kernels in isolation); with 2
+ * the panel work shares the caller's stream.
  * Returns GPR_ENODEV if the device does not exist, GPR_ENOTSUP for an
  * executor this build lacks. On success *out must later go to
  * gpr_ctx_destroy. */
@@ -242,9 +243,10 @@ const char* gpr_strerror(int status);
  * tasks: host array of 5 int32 per task: kind (0 POTRF, 1 TRSM, 2 SYRK,
  * 3 GEMM), I, K, J, launch index. Tile (I, K) is the one written; for POTRF
  * I = K = J, for TRSM K = J. Rows I >= M are test rows.
- * launches: host array of 3 int32 per launch: stream (0 critical, 1 bulk),
- * index of the last launch on the other stream that must finish before it
- * starts (-1 if none), and the task kind it runs.
+ * launches: host array of 5 int32 per launch: stream (0 critical, 1 panel,
+ * 2 bulk), the indices of up to three launches on other streams that must
+ * finish before it starts (-1 where unused), and the launch kind (0 POTRF,
+ * 1 TRSM, 2 tile updates). Launches on one stream run in list order.
  * Capacities are in records; counts are always written. Returns
  * GPR_EINVAL if a capacity is too small (counts still written). */
 int gpr_schedule_describe(int32_t M, int32_t Mhat, int32_t mode,

@@ -25,8 +25,9 @@ using namespace gpr;
 
 struct gpr_ctx {
     int device = 0;
-    int n_streams = 2;            // 1: every launch on the caller's stream
-    hipStream_t bulk = nullptr;
+    int n_streams = 3;            // 1: every launch on the caller's stream
+    hipStream_t panel = nullptr;  // panel TRSMs and next-column GEMMs
+    hipStream_t bulk = nullptr;   // trailing updates
     hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_last = nullptr, ev_desc = nullptr;
     bool last_valid = false, desc_valid = false;
     std::vector<hipEvent_t> evpool;
@@ -62,6 +63,7 @@ struct gpr_tiled {
     int M = 0;
     double* data = nullptr;
     double* tinv = nullptr;
+    double* kcopy = nullptr;      // FP64 copy of K kept by a mixed-precision factorisation
     int state = GPR_STATE_EMPTY;
     int prec = GPR_FP64;
 };
@@ -231,6 +233,7 @@ struct SweepMats {
     TileMat V;        // Mhat x M
     TileMat S;        // Mhat lower tiles
     int M, Mhat, m;
+    int prec;         // precision of the tile updates
     double* at(int I, int K_) const
     {
         if (I < M) return tile_ptr(K, I, K_);
@@ -274,27 +277,33 @@ SweepPlan plan_sweep(const SweepMats& X, int mode, DescBuffer& db)
     return P;
 }
 
-// Issues the launches of a planned sweep: critical stream = s, bulk stream =
-// ctx->bulk, forked from and joined back into s.
+// Issues the launches of a planned sweep. Logical streams: 0 critical (the
+// caller's stream s), 1 panel, 2 bulk; with fewer streams in the context
+// they fold onto s. The extra streams fork from s and join back into it.
 int run_sweep(gpr_ctx* ctx, const SweepMats& X, const SweepPlan& P, const DescBuffer& db,
               hipStream_t s)
 {
     const auto& Ls = P.sched.launches;
     int rc = ensure_events(ctx, Ls.size());
     if (rc) return rc;
+    hipStream_t phys[3] = {s, ctx->n_streams >= 3 ? ctx->panel : s,
+                           ctx->n_streams >= 2 ? ctx->bulk : s};
     std::vector<char> waited(Ls.size(), 0);
     for (const auto& L : Ls)
-        if (L.wait >= 0) waited[L.wait] = 1;
-    const bool two = ctx->n_streams > 1;
-    if (two) {
-        HIP_TRY(hipEventRecord(ctx->ev_fork, s));
-        HIP_TRY(hipStreamWaitEvent(ctx->bulk, ctx->ev_fork, 0));
+        for (int k = 0; k < L.nwait; ++k)
+            if (phys[Ls[L.wait[k]].stream] != phys[L.stream]) waited[L.wait[k]] = 1;
+    HIP_TRY(hipEventRecord(ctx->ev_fork, s));
+    for (int q = 1; q < 3; ++q) {
+        if (phys[q] == s || (q == 2 && phys[2] == phys[1])) continue;
+        HIP_TRY(hipStreamWaitEvent(phys[q], ctx->ev_fork, 0));
     }
     const int m = X.m;
     for (size_t li = 0; li < Ls.size(); ++li) {
         const SchedLaunch& L = Ls[li];
-        hipStream_t st = (L.stream == 0 || !two) ? s : ctx->bulk;
-        if (L.wait >= 0) HIP_TRY(hipStreamWaitEvent(st, ctx->evpool[L.wait], 0));
+        hipStream_t st = phys[L.stream];
+        for (int k = 0; k < L.nwait; ++k)
+            if (phys[Ls[L.wait[k]].stream] != st)
+                HIP_TRY(hipStreamWaitEvent(st, ctx->evpool[L.wait[k]], 0));
         const double m3 = (double)m * m * m;
         if (L.kind == LK_POTRF) {
             const int J = L.step;
@@ -311,12 +320,17 @@ int run_sweep(gpr_ctx* ctx, const SweepMats& X, const SweepPlan& P, const DescBu
             for (int t = L.first; t < L.first + L.count; ++t)
                 f += P.sched.tasks[t].kind == K_SYRK ? m3 : 2.0 * m3;
             ProfScope ps(ctx, st, PK_UPDATE, f, 0.0);
-            HIP_TRY(launch_update_f64(db.dev<UpdateTask>(ctx, P.off[li]), L.count, m, st));
+            if (X.prec == GPR_FP64)
+                HIP_TRY(launch_update_f64(db.dev<UpdateTask>(ctx, P.off[li]), L.count, m, st));
+            else
+                HIP_TRY(launch_update_mixed(db.dev<UpdateTask>(ctx, P.off[li]), L.count, m,
+                                            X.prec, st));
         }
         if (waited[li]) HIP_TRY(hipEventRecord(ctx->evpool[li], st));
     }
-    if (two) {
-        HIP_TRY(hipEventRecord(ctx->ev_join, ctx->bulk));
+    for (int q = 1; q < 3; ++q) {
+        if (phys[q] == s || (q == 2 && phys[2] == phys[1])) continue;
+        HIP_TRY(hipEventRecord(ctx->ev_join, phys[q]));
         HIP_TRY(hipStreamWaitEvent(s, ctx->ev_join, 0));
     }
     return GPR_OK;
@@ -341,6 +355,31 @@ int alloc_tiled(gpr_ctx* ctx, int64_t n, int m, gpr_tiled** out)
 }
 
 TileMat kmat(const gpr_tiled* T) { return TileMat{T->data, T->m, 0, 0}; }
+
+size_t tiled_bytes(const gpr_tiled* T)
+{
+    return (size_t)T->M * (T->M + 1) / 2 * T->m * T->m * sizeof(double);
+}
+
+// A mixed-precision factorisation keeps an FP64 copy of K for the residual
+// of the iterative refinement.
+int save_kcopy(gpr_tiled* K, hipStream_t s)
+{
+    if (!K->kcopy) {
+        if (hipMalloc(reinterpret_cast<void**>(&K->kcopy), tiled_bytes(K)) != hipSuccess) {
+            (void)hipGetLastError();
+            return GPR_ENOMEM;
+        }
+    }
+    HIP_TRY(hipMemcpyAsync(K->kcopy, K->data, tiled_bytes(K), hipMemcpyDeviceToDevice, s));
+    return GPR_OK;
+}
+
+bool valid_prec(int prec, int m)
+{
+    if (prec == GPR_FP64) return true;
+    return (prec == GPR_MIXED_FP32 || prec == GPR_MIXED_BF16) && m % 64 == 0;
+}
 
 // Vector solves with the factor: beta = L^{-1} r, alpha = L^{-T} beta.
 // r, beta, alpha are device vectors of length M m; r is overwritten.
@@ -435,8 +474,9 @@ int gpr_ctx_create(gpr_ctx** out, int device, int n_streams, gpr_executor ex)
     gpr_ctx* c = new (std::nothrow) gpr_ctx;
     if (!c) return GPR_ENOMEM;
     c->device = device;
-    c->n_streams = n_streams > 1 ? 2 : 1;
+    c->n_streams = n_streams >= 3 ? 3 : n_streams;
     bool ok = hipStreamCreateWithFlags(&c->bulk, hipStreamNonBlocking) == hipSuccess &&
+              hipStreamCreateWithFlags(&c->panel, hipStreamNonBlocking) == hipSuccess &&
               hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) == hipSuccess &&
               hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) == hipSuccess &&
               hipEventCreateWithFlags(&c->ev_last, hipEventDisableTiming) == hipSuccess &&
@@ -467,6 +507,7 @@ int gpr_ctx_destroy(gpr_ctx* c)
     if (c->ev_last) (void)hipEventDestroy(c->ev_last);
     if (c->ev_desc) (void)hipEventDestroy(c->ev_desc);
     if (c->bulk) (void)hipStreamDestroy(c->bulk);
+    if (c->panel) (void)hipStreamDestroy(c->panel);
     if (c->d_info) (void)hipFree(c->d_info);
     if (c->d_flags) (void)hipFree(c->d_flags);
     if (c->d_desc) (void)hipFree(c->d_desc);
@@ -510,12 +551,15 @@ int gpr_assemble(gpr_ctx* ctx, const double* X, int64_t n, int32_t D, gpr_hyper 
 int gpr_cholesky(gpr_ctx* ctx, gpr_tiled* K, gpr_precision prec, int32_t* info_dev, void* stream)
 {
     if (!ctx || !K || K->state != GPR_STATE_K || K->device != ctx->device) return GPR_EINVAL;
-    if (prec != GPR_FP64 && prec != GPR_MIXED_FP32 && prec != GPR_MIXED_BF16) return GPR_EINVAL;
-    if (prec != GPR_FP64) return GPR_ENOTSUP;
+    if (!valid_prec(prec, K->m)) return GPR_EINVAL;
     hipStream_t s = static_cast<hipStream_t>(stream);
     int rc = begin_call(ctx, s);
     if (rc) return rc;
     const int m = K->m, M = K->M;
+    if (prec != GPR_FP64) {
+        rc = save_kcopy(K, s);
+        if (rc) return rc;
+    }
     if (!K->tinv) {
         if (hipMalloc(reinterpret_cast<void**>(&K->tinv), (size_t)M * m * m * sizeof(double)) !=
             hipSuccess) {
@@ -523,7 +567,8 @@ int gpr_cholesky(gpr_ctx* ctx, gpr_tiled* K, gpr_precision prec, int32_t* info_d
             return GPR_ENOMEM;
         }
     }
-    SweepMats X{kmat(K), K->tinv, TileMat{nullptr, m, 1, M}, TileMat{nullptr, m, 0, 0}, M, 0, m};
+    SweepMats X{kmat(K), K->tinv, TileMat{nullptr, m, 1, M}, TileMat{nullptr, m, 0, 0}, M, 0, m,
+                (int)prec};
     DescBuffer db;
     SweepPlan P = plan_sweep(X, SWEEP_CHOLESKY, db);
     rc = db.upload(ctx, s);
@@ -546,8 +591,7 @@ int gpr_cholesky(gpr_ctx* ctx, gpr_tiled* K, gpr_precision prec, int32_t* info_d
 int gpr_cholesky_dense(gpr_ctx* ctx, double* A, int64_t n, int32_t tile, gpr_precision prec,
                        int32_t* info_dev, void* stream)
 {
-    if (!ctx || !A || n < 1 || !valid_tile(tile)) return GPR_EINVAL;
-    if (prec != GPR_FP64 && prec != GPR_MIXED_FP32 && prec != GPR_MIXED_BF16) return GPR_EINVAL;
+    if (!ctx || !A || n < 1 || !valid_tile(tile) || !valid_prec(prec, tile)) return GPR_EINVAL;
     hipStream_t s = static_cast<hipStream_t>(stream);
     int rc = begin_call(ctx, s);
     if (rc) return rc;
@@ -577,19 +621,29 @@ int gpr_cholesky_dense(gpr_ctx* ctx, double* A, int64_t n, int32_t tile, gpr_pre
 
 namespace {
 
-// Mean (and covariance) with the factor in L. fused: L still holds K, and
-// the factorisation runs in the same sweep as the covariance rows.
+// Internal status: the mixed factorisation failed (pivot, or refinement did
+// not converge); the caller may retry in a higher precision.
+constexpr int RETRY_HIGHER = 100;
+
+// Mean (and covariance) with the factor in L. fused: L holds K (assembled),
+// and the factorisation runs in the same sweep as the covariance rows, in
+// precision prec. With a mixed-precision factor, alpha is refined in FP64:
+//   r = y - K alpha (K from the saved FP64 copy), d = L^{-T} L^{-1} r,
+//   alpha += d,
+// until ||r|| / ||y|| <= 1e-14, stagnation, or 50 steps; this synchronises
+// the stream once per step.
 int predict_impl(gpr_ctx* ctx, gpr_tiled* L, const double* X, const double* y, int64_t n,
                  const double* Xs, int64_t n_test, int32_t D, const gpr_hyper& h, double* mean,
-                 double* cov, int32_t* info_dev, hipStream_t s, bool fused)
+                 double* cov, int32_t* info_dev, hipStream_t s, bool fused, int prec,
+                 gpr_ir_stats* ir)
 {
     const int m = L->m, M = L->M;
     const int Mhat = (int)((n_test + m - 1) / m);
     const size_t npad = (size_t)M * m;
-    const size_t vec_bytes = 3 * npad * sizeof(double);
+    const size_t vec_bytes = 5 * npad * sizeof(double) + 256;
     const size_t v_bytes = cov ? (size_t)Mhat * M * m * m * sizeof(double) : 0;
     const size_t s_bytes = cov ? (size_t)Mhat * (Mhat + 1) / 2 * m * m * sizeof(double) : 0;
-    int rc = ensure_device_bytes(&ctx->d_ws, &ctx->ws_cap, vec_bytes + v_bytes + s_bytes + 256);
+    int rc = ensure_device_bytes(&ctx->d_ws, &ctx->ws_cap, vec_bytes + v_bytes + s_bytes);
     if (rc) return rc;
     if (fused && !L->tinv) {
         if (hipMalloc(reinterpret_cast<void**>(&L->tinv), (size_t)M * m * m * sizeof(double)) !=
@@ -601,18 +655,26 @@ int predict_impl(gpr_ctx* ctx, gpr_tiled* L, const double* X, const double* y, i
     double* r = reinterpret_cast<double*>(ctx->d_ws);
     double* beta = r + npad;
     double* alpha = beta + npad;
-    double* Vb = alpha + npad;
+    double* acc = alpha + npad;     // refined alpha
+    double* scal = acc + npad;      // small scalars (norms)
+    double* Vb = scal + npad;
     double* Sb = reinterpret_cast<double*>(reinterpret_cast<char*>(Vb) + v_bytes);
+    const int fprec = fused ? prec : L->prec;
 
     DescBuffer db;
     SolvePlan SP = plan_solves(L, r, beta, alpha, db);
-    SweepMats SM{kmat(L), L->tinv, TileMat{Vb, m, 1, M}, TileMat{Sb, m, 0, 0}, M, cov ? Mhat : 0, m};
+    SweepMats SM{kmat(L), L->tinv, TileMat{Vb, m, 1, M}, TileMat{Sb, m, 0, 0}, M,
+                 cov ? Mhat : 0, m, fprec};
     SweepPlan PP;
     const int mode = fused ? (cov ? SWEEP_FUSED : SWEEP_CHOLESKY) : SWEEP_PREDICT;
     if (fused || cov) PP = plan_sweep(SM, mode, db);
     rc = db.upload(ctx, s);
     if (rc) return rc;
 
+    if (fused && prec != GPR_FP64) {
+        rc = save_kcopy(L, s);
+        if (rc) return rc;
+    }
     if (cov) {
         // K_{X*,X} tiles (to become V^T) and lower tiles of K_{X*,X*}; no noise
         ProfScope ps(ctx, s, PK_ASSEMBLE, 0.0, (double)(v_bytes + s_bytes));
@@ -631,19 +693,69 @@ int predict_impl(gpr_ctx* ctx, gpr_tiled* L, const double* X, const double* y, i
         HIP_TRY(launch_trtri_f64(kmat(L), M, L->tinv, s));
     }
     if (fused) {
+        L->state = GPR_STATE_L;
+        L->prec = prec;
+        if (prec != GPR_FP64) {
+            // a failed pivot in a mixed precision: the caller retries higher,
+            // and the failure is not reported (no finish_info for this attempt)
+            int info = 0;
+            HIP_TRY(hipMemcpyAsync(&info, ctx->d_info, sizeof(int), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            if (info > 0) return RETRY_HIGHER;
+        }
         rc = finish_info(ctx, info_dev, s);
         if (rc) return rc;
-        L->state = GPR_STATE_L;
     }
     // alpha = K^{-1} y via the two triangular solves (Sec. 4.1)
     HIP_TRY(launch_copy_f64(y, r, n, (int64_t)npad, s));
     rc = run_solves(ctx, L, SP, db, s);
     if (rc) return rc;
+    const double* alpha_used = alpha;
+    if (ir) {
+        ir->iters = 0;
+        ir->rel_residual = -1.0;
+        ir->fallback_precision = L->prec;
+    }
+    if (L->prec != GPR_FP64) {
+        if (!L->kcopy) return GPR_EINVAL;
+        const TileMat Kc{L->kcopy, m, 0, 0};
+        HIP_TRY(launch_copy_f64(alpha, acc, (int64_t)npad, (int64_t)npad, s));
+        HIP_TRY(launch_sumsq(y, n, scal, s));
+        double yy = 0.0;
+        HIP_TRY(hipMemcpyAsync(&yy, scal, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        const double yn = std::sqrt(yy);
+        double prev = -1.0, rel = -1.0;
+        int it = 0;
+        for (; it <= 50; ++it) {
+            // r = y - K acc (FP64), padding of r stays zero
+            HIP_TRY(launch_symv_tiled(Kc, M, acc, y, r, n, s));
+            HIP_TRY(launch_sumsq(r, n, scal, s));
+            double rr = 0.0;
+            HIP_TRY(hipMemcpyAsync(&rr, scal, sizeof(double), hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            const double rn = std::sqrt(rr);
+            rel = yn > 0 ? rn / yn : rn;
+            if (rel <= 1e-14 || it == 50) break;
+            if (prev >= 0 && rn > 0.9 * prev) break;   // stagnation
+            prev = rn;
+            rc = run_solves(ctx, L, SP, db, s);          // alpha = L^{-T} L^{-1} r
+            if (rc) return rc;
+            HIP_TRY(launch_axpy(acc, alpha, (int64_t)npad, s));
+        }
+        if (ir) {
+            ir->iters = it;
+            ir->rel_residual = rel;
+        }
+        // not converged to where the mean can be trusted: let a fused caller retry
+        if (fused && !(rel <= 1e-10)) return RETRY_HIGHER;
+        alpha_used = acc;
+    }
     // mean = K_{X*,X} alpha, eq. (2), without storing K_{X*,X}
     {
         ProfScope ps(ctx, s, PK_MATVEC, 2.0 * (double)n_test * (double)n, 0.0);
         HIP_TRY(launch_kernel_matvec(Xs, n_test, X, n, D, h.lengthscale, h.vertical_variance,
-                                     h.noise_variance, false, alpha, nullptr, mean, s));
+                                     h.noise_variance, false, alpha_used, nullptr, mean, s));
     }
     if (cov) {
         ProfScope ps(ctx, s, PK_EXPORT, 0.0, (double)n_test * n_test * sizeof(double));
@@ -665,17 +777,11 @@ int gpr_predict(gpr_ctx* ctx, gpr_tiled* L, const double* X, const double* y, in
     if (L->state != GPR_STATE_L || L->n != n || L->device != ctx->device) return GPR_EINVAL;
     if (n_test > 0 && (!Xs || !mean)) return GPR_EINVAL;
     if (n_test == 0) return GPR_OK;
-    if (L->prec != GPR_FP64) return GPR_ENOTSUP;
     hipStream_t s = static_cast<hipStream_t>(stream);
     int rc = begin_call(ctx, s);
     if (rc) return rc;
-    rc = predict_impl(ctx, L, X, y, n, Xs, n_test, D, h, mean, cov, nullptr, s, false);
+    rc = predict_impl(ctx, L, X, y, n, Xs, n_test, D, h, mean, cov, nullptr, s, false, L->prec, ir);
     if (rc) return rc;
-    if (ir) {
-        ir->iters = 0;
-        ir->rel_residual = -1.0;
-        ir->fallback_precision = L->prec;
-    }
     return end_call(ctx, s);
 }
 
@@ -685,25 +791,27 @@ int gpr_fit_predict(gpr_ctx* ctx, const double* X, const double* y, int64_t n, c
                     gpr_ir_stats* ir, void* stream)
 {
     if (!ctx || !X || !y || !K_inout || n < 1 || D < 1 || n_test < 1 || !Xs || !mean ||
-        !valid_tile(tile) || !valid_hyper(h))
+        !valid_tile(tile) || !valid_hyper(h) || !valid_prec(prec, tile))
         return GPR_EINVAL;
-    if (prec != GPR_FP64 && prec != GPR_MIXED_FP32 && prec != GPR_MIXED_BF16) return GPR_EINVAL;
-    if (prec != GPR_FP64) return GPR_ENOTSUP;
-    int rc = gpr_assemble(ctx, X, n, D, h, tile, K_inout, stream);
-    if (rc) return rc;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    rc = begin_call(ctx, s);
-    if (rc) return rc;
-    gpr_tiled* K = *K_inout;
-    rc = predict_impl(ctx, K, X, y, n, Xs, n_test, D, h, mean, cov, info_dev, s, true);
-    if (rc) return rc;
-    K->prec = prec;
-    if (ir) {
-        ir->iters = 0;
-        ir->rel_residual = -1.0;
-        ir->fallback_precision = prec;
+    // a mixed factorisation that fails (pivot, or refinement) is redone one
+    // precision step higher: BF16 -> FP32 -> FP64
+    for (int p = (int)prec;; p = (p == GPR_MIXED_BF16) ? GPR_MIXED_FP32 : GPR_FP64) {
+        int rc = gpr_assemble(ctx, X, n, D, h, tile, K_inout, stream);
+        if (rc) return rc;
+        rc = begin_call(ctx, s);
+        if (rc) return rc;
+        gpr_tiled* K = *K_inout;
+        rc = predict_impl(ctx, K, X, y, n, Xs, n_test, D, h, mean, cov, info_dev, s, true, p, ir);
+        if (rc == RETRY_HIGHER && p != GPR_FP64) {
+            rc = end_call(ctx, s);
+            if (rc) return rc;
+            continue;
+        }
+        if (rc) return rc;
+        if (ir) ir->fallback_precision = p;
+        return end_call(ctx, s);
     }
-    return end_call(ctx, s);
 }
 
 int gpr_solve(gpr_ctx* ctx, gpr_tiled* L, const double* b, double* x, void* stream)
@@ -797,6 +905,7 @@ int gpr_tiled_free(gpr_tiled* T)
     (void)hipDeviceSynchronize();
     if (T->data) (void)hipFree(T->data);
     if (T->tinv) (void)hipFree(T->tinv);
+    if (T->kcopy) (void)hipFree(T->kcopy);
     delete T;
     return GPR_OK;
 }

@@ -116,6 +116,18 @@ hipError_t launch_kernel_matvec(const double* A, int64_t na, const double* B, in
                                 const double* x, const double* base, double* out,
                                 hipStream_t s);
 
+// Mixed-precision tile updates (prec GPR_MIXED_FP32 or GPR_MIXED_BF16); m % 64 == 0.
+hipError_t launch_update_mixed(const UpdateTask* d_tasks, int ntask, int m, int prec,
+                               hipStream_t s);
+
+// out[0] = sum x_i^2 (deterministic).
+hipError_t launch_sumsq(const double* x, int64_t n, double* out, hipStream_t s);
+// y += x
+hipError_t launch_axpy(double* y, const double* x, int64_t n, hipStream_t s);
+// out = base - K x for K stored as M lower tiles (diagonal tiles full), rows < n.
+hipError_t launch_symv_tiled(const TileMat& K, int M, const double* x, const double* base,
+                             double* out, int64_t n, hipStream_t s);
+
 hipError_t launch_set_int(int* p, int value, hipStream_t s);
 hipError_t launch_copy_f64(const double* src, double* dst, int64_t n, int64_t n_pad,
                            hipStream_t s);
@@ -133,11 +145,12 @@ struct SchedTask {
 };
 
 struct SchedLaunch {
-    int stream;      // 0 critical, 1 bulk
-    int wait;        // index of a launch on the other stream to wait for, or -1
-    int kind;        // LaunchKind
+    int stream;        // 0 critical, 1 panel, 2 bulk
+    int wait[3];       // launches on other streams to wait for (-1: none)
+    int nwait;
+    int kind;          // LaunchKind
     int first, count;  // task range
-    int step;        // J
+    int step;          // J
 };
 
 struct Schedule {

@@ -1,0 +1,219 @@
+// k_update_mixed.hip -- tile updates C -= A B^T with low-precision inputs
+// (the mixed-precision form of the GEMM / SYRK tasks of Fig. 1): the FP64
+// operand tiles are rounded to FP32 or BF16 as they are staged into LDS,
+// multiplied on the matching MFMA with an FP32 accumulator, and the
+// accumulator is subtracted from the FP64 tile. POTRF, TRSM and every solve
+// stay FP64.
+//
+// Same blocking as the FP64 kernel: one workgroup per 128 x 128 (or 64 x 64)
+// block of a tile, 4 waves in 2 x 2, XCD-aware block order, LDS double
+// buffering. FP32: v_mfma_f32_16x16x4_f32, k-slices of 16, LDS k-major.
+// BF16: v_mfma_f32_16x16x32_bf16, k-slices of 32, LDS row-major (each lane
+// reads 8 consecutive bf16 of one row). Both FP32-accumulator layouts put
+// element v of lane l at row 4 (l / 16) + v, column l % 16.
+#include "gpr_internal.h"
+#include "k_common.h"
+
+namespace gpr {
+
+typedef float flt4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+__device__ constexpr int frow(int lk, int v) { return 4 * lk + v; }
+
+template <int BM>
+__global__ __launch_bounds__(256, 2) void k_update_f32(const UpdateTask* __restrict__ tasks, int m)
+{
+    constexpr int KB = 16;
+    constexpr int WM = BM / 2, TM = WM / 16;
+    constexpr int LD = BM + 4;
+    constexpr int NLD = BM * KB / 2 / 256;
+    __shared__ float As[2][KB][LD];
+    __shared__ float Bs[2][KB][LD];
+
+    const int nb = m / BM;
+    const int lid = xcd_remap(blockIdx.x, gridDim.x);
+    const int t = lid / (nb * nb);
+    const int sub = lid - t * nb * nb;
+    const int bi = sub / nb, bj = sub - bi * nb;
+    const UpdateTask tk = tasks[t];
+    if ((tk.flags & TASK_DIAG) && bj > bi) return;
+    const double* __restrict__ A = tk.A + (size_t)bi * BM * tk.lda;
+    const double* __restrict__ B = tk.B + (size_t)bj * BM * tk.ldb;
+    double* __restrict__ C = tk.C + (size_t)bi * BM * tk.ldc + (size_t)bj * BM;
+    const int lda = tk.lda, ldb = tk.ldb, ldc = tk.ldc;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = (wave >> 1) * WM, wc = (wave & 1) * WM;
+    const int lr = lane & 15, lk = lane >> 4;
+
+    double2 ra[NLD], rb[NLD];
+    auto gload = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < NLD; ++q) {
+            const int e = tid + 256 * q;
+            const int r = e / (KB / 2), kk = (e % (KB / 2)) * 2;
+            ra[q] = *reinterpret_cast<const double2*>(A + (size_t)r * lda + k0 + kk);
+            rb[q] = *reinterpret_cast<const double2*>(B + (size_t)r * ldb + k0 + kk);
+        }
+    };
+    auto swrite = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < NLD; ++q) {
+            const int e = tid + 256 * q;
+            const int r = e / (KB / 2), kk = (e % (KB / 2)) * 2;
+            As[buf][kk][r] = (float)ra[q].x;
+            As[buf][kk + 1][r] = (float)ra[q].y;
+            Bs[buf][kk][r] = (float)rb[q].x;
+            Bs[buf][kk + 1][r] = (float)rb[q].y;
+        }
+    };
+    flt4 acc[TM][TM];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TM; ++j) acc[i][j] = flt4{0.f, 0.f, 0.f, 0.f};
+
+    gload(0);
+    swrite(0);
+    __syncthreads();
+    const int nk = m / KB;
+    for (int kt = 0; kt < nk; ++kt) {
+        const int cur = kt & 1;
+        if (kt + 1 < nk) gload((kt + 1) * KB);
+#pragma unroll
+        for (int kk = 0; kk < KB; kk += 4) {
+            float a[TM], b[TM];
+#pragma unroll
+            for (int i = 0; i < TM; ++i) a[i] = As[cur][kk + lk][wr + 16 * i + lr];
+#pragma unroll
+            for (int j = 0; j < TM; ++j) b[j] = Bs[cur][kk + lk][wc + 16 * j + lr];
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TM; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+        if (kt + 1 < nk) swrite(cur ^ 1);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TM; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = wr + 16 * i + frow(lk, v);
+                const int col = wc + 16 * j + lr;
+                C[(size_t)row * ldc + col] -= (double)acc[i][j][v];
+            }
+}
+
+template <int BM>
+__global__ __launch_bounds__(256, 2) void k_update_bf16(const UpdateTask* __restrict__ tasks, int m)
+{
+    constexpr int KB = 32;
+    constexpr int WM = BM / 2, TM = WM / 16;
+    constexpr int LD = KB + 8;                      // bf16 per LDS row (padded)
+    constexpr int NLD = BM * KB / 2 / 256;          // double2 loads per thread per operand
+    __shared__ __bf16 As[2][BM][LD];
+    __shared__ __bf16 Bs[2][BM][LD];
+
+    const int nb = m / BM;
+    const int lid = xcd_remap(blockIdx.x, gridDim.x);
+    const int t = lid / (nb * nb);
+    const int sub = lid - t * nb * nb;
+    const int bi = sub / nb, bj = sub - bi * nb;
+    const UpdateTask tk = tasks[t];
+    if ((tk.flags & TASK_DIAG) && bj > bi) return;
+    const double* __restrict__ A = tk.A + (size_t)bi * BM * tk.lda;
+    const double* __restrict__ B = tk.B + (size_t)bj * BM * tk.ldb;
+    double* __restrict__ C = tk.C + (size_t)bi * BM * tk.ldc + (size_t)bj * BM;
+    const int lda = tk.lda, ldb = tk.ldb, ldc = tk.ldc;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wr = (wave >> 1) * WM, wc = (wave & 1) * WM;
+    const int lr = lane & 15, lk = lane >> 4;
+
+    double2 ra[NLD], rb[NLD];
+    auto gload = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < NLD; ++q) {
+            const int e = tid + 256 * q;
+            const int r = e / (KB / 2), kk = (e % (KB / 2)) * 2;
+            ra[q] = *reinterpret_cast<const double2*>(A + (size_t)r * lda + k0 + kk);
+            rb[q] = *reinterpret_cast<const double2*>(B + (size_t)r * ldb + k0 + kk);
+        }
+    };
+    auto swrite = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < NLD; ++q) {
+            const int e = tid + 256 * q;
+            const int r = e / (KB / 2), kk = (e % (KB / 2)) * 2;
+            bf16x2 pa, pb;
+            pa[0] = (__bf16)(float)ra[q].x;
+            pa[1] = (__bf16)(float)ra[q].y;
+            pb[0] = (__bf16)(float)rb[q].x;
+            pb[1] = (__bf16)(float)rb[q].y;
+            *reinterpret_cast<bf16x2*>(&As[buf][r][kk]) = pa;
+            *reinterpret_cast<bf16x2*>(&Bs[buf][r][kk]) = pb;
+        }
+    };
+    flt4 acc[TM][TM];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TM; ++j) acc[i][j] = flt4{0.f, 0.f, 0.f, 0.f};
+
+    gload(0);
+    swrite(0);
+    __syncthreads();
+    const int nk = m / KB;
+    for (int kt = 0; kt < nk; ++kt) {
+        const int cur = kt & 1;
+        if (kt + 1 < nk) gload((kt + 1) * KB);
+        bf16x8 a[TM], b[TM];
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+            a[i] = *reinterpret_cast<const bf16x8*>(&As[cur][wr + 16 * i + lr][8 * lk]);
+#pragma unroll
+        for (int j = 0; j < TM; ++j)
+            b[j] = *reinterpret_cast<const bf16x8*>(&Bs[cur][wc + 16 * j + lr][8 * lk]);
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TM; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+        if (kt + 1 < nk) swrite(cur ^ 1);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TM; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = wr + 16 * i + frow(lk, v);
+                const int col = wc + 16 * j + lr;
+                C[(size_t)row * ldc + col] -= (double)acc[i][j][v];
+            }
+}
+
+hipError_t launch_update_mixed(const UpdateTask* d_tasks, int ntask, int m, int prec,
+                               hipStream_t s)
+{
+    if (ntask <= 0) return hipSuccess;
+    const bool big = m % 128 == 0;
+    const int BM = big ? 128 : 64;
+    const int nb = m / BM;
+    const dim3 grid(ntask * nb * nb);
+    if (prec == GPR_MIXED_FP32) {
+        if (big) hipLaunchKernelGGL(k_update_f32<128>, grid, dim3(256), 0, s, d_tasks, m);
+        else hipLaunchKernelGGL(k_update_f32<64>, grid, dim3(256), 0, s, d_tasks, m);
+    } else {
+        if (big) hipLaunchKernelGGL(k_update_bf16<128>, grid, dim3(256), 0, s, d_tasks, m);
+        else hipLaunchKernelGGL(k_update_bf16<64>, grid, dim3(256), 0, s, d_tasks, m);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace gpr

@@ -183,6 +183,113 @@ hipError_t launch_kernel_matvec(const double* A, int64_t na, const double* B, in
     return hipGetLastError();
 }
 
+// out[0] = sum_i x_i^2 (one workgroup, fixed order: strided per thread, then
+// a tree over the 256 partial sums).
+__global__ __launch_bounds__(256) void k_sumsq(const double* __restrict__ x, int64_t n,
+                                               double* __restrict__ out)
+{
+    __shared__ double part[256];
+    const int tid = threadIdx.x;
+    double s = 0.0;
+    for (int64_t i = tid; i < n; i += 256) s += x[i] * x[i];
+    part[tid] = s;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if (tid < w) part[tid] += part[tid + w];
+        __syncthreads();
+    }
+    if (tid == 0) out[0] = part[0];
+}
+
+hipError_t launch_sumsq(const double* x, int64_t n, double* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sumsq, dim3(1), dim3(256), 0, s, x, n, out);
+    return hipGetLastError();
+}
+
+// y[i] += x[i]
+__global__ void k_axpy(double* __restrict__ y, const double* __restrict__ x, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        y[i] += x[i];
+}
+
+hipError_t launch_axpy(double* y, const double* x, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 2048) blocks = 2048;
+    hipLaunchKernelGGL(k_axpy, dim3((unsigned)blocks), dim3(256), 0, s, y, x, n);
+    return hipGetLastError();
+}
+
+// out_i = base_i - (K x)_i for the symmetric matrix stored as lower tiles
+// (diagonal tiles hold both triangles). Workgroup (I, b) owns rows
+// I m + 32 b .. + 31: it adds the tile-row part sum_{J <= I} K_IJ x_J and the
+// transposed tile-column part sum_{I' > I} K_{I'I}^T x_{I'} in a fixed order
+// (no atomics), reading each off-diagonal tile twice over the whole launch.
+__global__ __launch_bounds__(256) void k_symv_tiled(TileMat K, int M, const double* __restrict__ x,
+                                                    const double* __restrict__ base,
+                                                    double* __restrict__ out, int64_t n)
+{
+    __shared__ double part[8][32];
+    const int m = K.m;
+    const int per = m / 32;
+    const int I = blockIdx.x / per, b = blockIdx.x % per;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // row part: wave w takes rows 8w .. 8w+7 of the block, lanes stride columns
+    double s[8];
+#pragma unroll
+    for (int r = 0; r < 8; ++r) s[r] = 0.0;
+    for (int J = 0; J <= I; ++J) {
+        const double* T = tile_ptr(K, I, J) + (size_t)(32 * b + 8 * wave) * m;
+        const double* xj = x + (size_t)J * m;
+        for (int c = lane; c < m; c += 64) {
+            const double xc = xj[c];
+#pragma unroll
+            for (int r = 0; r < 8; ++r) s[r] += T[(size_t)r * m + c] * xc;
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        double v = s[r];
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+        s[r] = v;
+    }
+    // transposed part: thread (g, c) sums column 32 b + c over row group g of
+    // every tile below the diagonal in tile column I
+    const int c = tid & 31, g = tid >> 5;
+    double t = 0.0;
+    for (int Ip = I + 1; Ip < M; ++Ip) {
+        const double* T = tile_ptr(K, Ip, I) + 32 * b + c;
+        const double* xi = x + (size_t)Ip * m;
+        const int rows = m / 8;
+        for (int r = g * rows; r < (g + 1) * rows; ++r) t += T[(size_t)r * m] * xi[r];
+    }
+    part[g][c] = t;
+    __syncthreads();
+    if (lane < 8) {
+        const int row = 32 * b + 8 * wave + lane;     // row within the tile row
+        double tot = s[0];
+#pragma unroll
+        for (int r = 1; r < 8; ++r) tot = (lane == r) ? s[r] : tot;
+        double tr = part[0][8 * wave + lane];
+#pragma unroll
+        for (int q = 1; q < 8; ++q) tr += part[q][8 * wave + lane];
+        const int64_t gi = (int64_t)I * m + row;
+        if (gi < n) out[gi] = base[gi] - (tot + tr);
+    }
+}
+
+hipError_t launch_symv_tiled(const TileMat& K, int M, const double* x, const double* base,
+                             double* out, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_symv_tiled, dim3(M * (K.m / 32)), dim3(256), 0, s, K, M, x, base, out, n);
+    return hipGetLastError();
+}
+
 __global__ void k_set_int(int* p, int value) { *p = value; }
 
 hipError_t launch_set_int(int* p, int value, hipStream_t s)

@@ -1,6 +1,7 @@
 // schedule.cpp -- turns the tile task graph of the right-looking tiled
 // Cholesky (Sec. 4.2, Fig. 1) and of the covariance solve (Sec. 4.1: L V =
-// K_{X,X*}, Sigma = K_{X*,X*} - V^T V) into batched launches on two streams.
+// K_{X,X*}, Sigma = K_{X*,X*} - V^T V) into batched launches on three
+// streams.
 //
 // The test rows are appended below the training rows: with
 //   A = [[K, .], [K_{X*,X}, K_{X*,X*}]]
@@ -11,83 +12,118 @@
 // matrix, so one dependency rule covers both.
 //
 // Dependencies (tile (I, K) updated at step J with the panel of column J):
-//   POTRF(J)      after the last update of (J, J)           -- SYRK(J, J-1)
+//   POTRF(J)      after the last update of (J, J)           -- SYRK(J, J, J-1)
 //   TRSM(I, J)    after POTRF(J) and the last update of (I, J)
 //   update(I,K,J) after TRSM(I, J), TRSM(K, J) and update(I, K, J-1).
 //
-// Execution with one step of look-ahead on a critical stream C and a bulk
-// stream B. At step J:
-//   C: POTRF(J); TRSM(column J); [wait for R(J-1)]; N(J)
-//   B: [wait for TRSM(J)]; R(J)
-// where N(J) are the updates of tile column J+1 (the next panel) and R(J)
-// all other updates of step J. Tiles of column J+1 get their step-J' < J
-// updates in R(J'), which N(J) waits for; tiles of columns >= J+2 get all
-// their updates on B in step order. So POTRF(J+1) and TRSM(J+1) run on C
-// while R(J) still runs on B.
+// When the training block is factored (modes 0 and 2), only three tile tasks
+// separate POTRF(J) from POTRF(J+1): TRSM(J+1, J) and SYRK(J+1, J+1, J).
+// They run on the critical stream C; everything else of step J goes to a
+// panel stream P (the other TRSMs of column J, then the GEMMs of column J+1,
+// GEMM(J+2, J+1, J) first because the next step's critical TRSM needs it) or
+// to the bulk stream B (all updates of columns >= J+2):
+//   C: POTRF(J); [wait G1(J-1)] TRSM(J+1, J); [wait R(J-1)] SYRK(J+1, J+1, J)
+//   P: [wait POTRF(J)] TRSM(rest of column J);
+//      [wait TRSM(J+1, J), R(J-1)] G1(J) = GEMM(J+2, J+1, J); N(J) = the other
+//      GEMMs of column J+1
+//   B: [wait TRSM(J+1, J), TRSM(rest of J)] R(J)
+// Tiles of column J+1 get their updates of steps < J in R (waited for), of
+// step J on P; tiles of columns >= J+2 get all their updates on B in step
+// order. The covariance solve with a given factor (mode 1) has no POTRF and
+// uses C (TRSM of the test rows, then the updates of column J+1) and B.
 #include <algorithm>
 
 #include "gpr_internal.h"
 
 namespace gpr {
 
+namespace {
+
+struct Builder {
+    Schedule S;
+    int add(int stream, std::vector<int> waits, int kind, const std::vector<SchedTask>& tasks,
+            int step)
+    {
+        if (tasks.empty()) return -1;
+        SchedLaunch L;
+        L.stream = stream;
+        L.nwait = 0;
+        for (int w : waits)
+            if (w >= 0 && S.launches[w].stream != stream && L.nwait < 3) L.wait[L.nwait++] = w;
+        for (int k = L.nwait; k < 3; ++k) L.wait[k] = -1;
+        L.kind = kind;
+        L.first = (int)S.tasks.size();
+        L.count = (int)tasks.size();
+        L.step = step;
+        S.tasks.insert(S.tasks.end(), tasks.begin(), tasks.end());
+        S.launches.push_back(L);
+        return (int)S.launches.size() - 1;
+    }
+};
+
+SchedTask upd(int I, int K, int J) { return SchedTask{I == K ? K_SYRK : K_GEMM, I, K, J}; }
+
+}  // namespace
+
 Schedule build_schedule(int M, int Mhat, int mode)
 {
-    Schedule S;
+    Builder b;
     const bool factor = (mode == SWEEP_CHOLESKY || mode == SWEEP_FUSED);
     const bool predict = (mode == SWEEP_PREDICT || mode == SWEEP_FUSED);
     const int T = M + (predict ? Mhat : 0);  // tile rows of the extended matrix
-    const int row_lo = factor ? 0 : M;       // first row that is written
+    enum { C = 0, P = 1, B = 2 };
 
-    int last_R = -1;  // index of R(J-1) launch, or -1
-    for (int J = 0; J < M; ++J) {
-        // ---- critical stream: POTRF(J)
-        if (factor) {
-            SchedLaunch L{0, -1, LK_POTRF, (int)S.tasks.size(), 1, J};
-            S.tasks.push_back({K_POTRF, J, J, J});
-            S.launches.push_back(L);
+    if (!factor) {
+        // covariance rows with a given factor: C runs TRSM(column J) and the
+        // updates of column J+1, B the rest
+        int last_R = -1;
+        for (int J = 0; J < M; ++J) {
+            std::vector<SchedTask> tr, N, R;
+            for (int I = M; I < T; ++I) tr.push_back({K_TRSM, I, J, J});
+            for (int I = M; I < T; ++I)
+                for (int K = J + 1; K <= I; ++K) {
+                    if (K == J + 1 && K < M) N.push_back(upd(I, K, J));
+                    else R.push_back(upd(I, K, J));
+                }
+            const int t = b.add(C, {}, LK_TRSM, tr, J);
+            b.add(C, {last_R}, LK_UPDATE, N, J);
+            const int r = b.add(B, {t}, LK_UPDATE, R, J);
+            if (r >= 0) last_R = r;
         }
-        // ---- critical stream: TRSM of column J (rows below the diagonal)
-        int trsm_launch = -1;
-        {
-            SchedLaunch L{0, -1, LK_TRSM, (int)S.tasks.size(), 0, J};
-            for (int I = std::max(J + 1, row_lo); I < T; ++I) {
-                if (I < M && !factor) continue;
-                S.tasks.push_back({K_TRSM, I, J, J});
-            }
-            L.count = (int)S.tasks.size() - L.first;
-            if (L.count > 0) {
-                trsm_launch = (int)S.launches.size();
-                S.launches.push_back(L);
-            }
-        }
-        if (trsm_launch < 0) continue;  // nothing below: no updates at this step
-
-        // ---- updates of step J, split into N(J) (column J+1) and R(J).
-        std::vector<SchedTask> N, R;
-        for (int I = J + 1; I < T; ++I) {
-            if (I < M && !factor) continue;
-            for (int K = J + 1; K <= I; ++K) {
-                if (K < M && I < M && !factor) continue;
-                // training tiles (I, K < M) exist only when factoring; test rows
-                // always pair with training columns K < M (V) or test columns (Sigma)
-                const SchedTask t{I == K ? K_SYRK : K_GEMM, I, K, J};
-                if (K == J + 1 && K < M) N.push_back(t);
-                else R.push_back(t);
-            }
-        }
-        if (!N.empty()) {
-            SchedLaunch L{0, last_R, LK_UPDATE, (int)S.tasks.size(), (int)N.size(), J};
-            S.tasks.insert(S.tasks.end(), N.begin(), N.end());
-            S.launches.push_back(L);
-        }
-        if (!R.empty()) {
-            SchedLaunch L{1, trsm_launch, LK_UPDATE, (int)S.tasks.size(), (int)R.size(), J};
-            S.tasks.insert(S.tasks.end(), R.begin(), R.end());
-            last_R = (int)S.launches.size();
-            S.launches.push_back(L);
-        }
+        return b.S;
     }
-    return S;
+
+    int last_R = -1, last_G1 = -1;
+    for (int J = 0; J < M; ++J) {
+        const int potrf = b.add(C, {}, LK_POTRF, {SchedTask{K_POTRF, J, J, J}}, J);
+        const bool next = J + 1 < M;  // is there a next factored column?
+        // critical TRSM and SYRK
+        int t1 = -1;
+        if (next) {
+            t1 = b.add(C, {last_G1}, LK_TRSM, {SchedTask{K_TRSM, J + 1, J, J}}, J);
+            b.add(C, {last_R}, LK_UPDATE, {upd(J + 1, J + 1, J)}, J);
+        }
+        // the other TRSMs of column J
+        std::vector<SchedTask> trest;
+        for (int I = J + (next ? 2 : 1); I < T; ++I) trest.push_back({K_TRSM, I, J, J});
+        const int tr = b.add(P, {potrf}, LK_TRSM, trest, J);
+        // GEMMs of column J+1: G1 = (J+2, J+1) first, then the rest
+        last_G1 = -1;
+        if (next) {
+            if (J + 2 < M) last_G1 = b.add(P, {t1, last_R}, LK_UPDATE, {upd(J + 2, J + 1, J)}, J);
+            std::vector<SchedTask> N;
+            for (int I = J + 2; I < T; ++I)
+                if (!(I == J + 2 && J + 2 < M)) N.push_back(upd(I, J + 1, J));
+            b.add(P, {t1, last_R}, LK_UPDATE, N, J);
+        }
+        // everything else of step J
+        std::vector<SchedTask> R;
+        for (int I = J + 1; I < T; ++I)
+            for (int K = (next ? J + 2 : J + 1); K <= I; ++K) R.push_back(upd(I, K, J));
+        const int r = b.add(B, {t1, tr}, LK_UPDATE, R, J);
+        if (r >= 0) last_R = r;
+    }
+    return b.S;
 }
 
 }  // namespace gpr
@@ -115,10 +151,12 @@ extern "C" int gpr_schedule_describe(int32_t M, int32_t Mhat, int32_t mode, int3
     }
     if (launches) {
         for (size_t li = 0; li < S.launches.size(); ++li) {
-            int32_t* o = launches + 3 * li;
+            int32_t* o = launches + 5 * li;
             o[0] = S.launches[li].stream;
-            o[1] = S.launches[li].wait;
-            o[2] = S.launches[li].kind;
+            o[1] = S.launches[li].wait[0];
+            o[2] = S.launches[li].wait[1];
+            o[3] = S.launches[li].wait[2];
+            o[4] = S.launches[li].kind;
         }
     }
     return GPR_OK;

@@ -106,7 +106,7 @@ class Tiled:
 class Context:
     """A libgpr context on one GPU (streams, events, workspace)."""
 
-    def __init__(self, device=0, n_streams=2, executor=GPR_EXEC_STREAMS):
+    def __init__(self, device=0, n_streams=3, executor=GPR_EXEC_STREAMS):
         self._lib = _lib.load()
         h = ctypes.c_void_p()
         _check(self._lib.gpr_ctx_create(ctypes.byref(h), int(device), int(n_streams),
@@ -275,7 +275,7 @@ def schedule_describe(M, Mhat, mode):
     """Host-only: the batched launch list of the tile sweep (see gpr.h).
 
     Returns ``(tasks, launches)``: int32 arrays of shape (T, 5) = (kind, I, K,
-    J, launch) and (L, 3) = (stream, wait, launch kind)."""
+    J, launch) and (L, 5) = (stream, wait0, wait1, wait2, launch kind)."""
     lib = _lib.load()
     nt = ctypes.c_int64()
     nl = ctypes.c_int64()
@@ -284,7 +284,7 @@ def schedule_describe(M, Mhat, mode):
     if st not in (GPR_OK, _lib.GPR_EINVAL) or nt.value < 0:
         raise GPRError(st, "gpr_schedule_describe")
     tasks = np.zeros((nt.value, 5), dtype=np.int32)
-    launches = np.zeros((nl.value, 3), dtype=np.int32)
+    launches = np.zeros((nl.value, 5), dtype=np.int32)
     _check(lib.gpr_schedule_describe(M, Mhat, mode,
                                      tasks.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                                      nt.value, ctypes.byref(nt),

@@ -307,3 +307,50 @@ def test_full_size_properties(ctx):
         say(f"  rel(cov[:, {j}]) = {e:.3e}")
         assert e <= TOL
     K.free()
+
+
+# --------------------------------------------------------------------------
+# mixed precision: FP32 / BF16 tile updates, FP64 POTRF / TRSM / solves,
+# FP64 iterative refinement of alpha (spec bar for the mean: 1e-8)
+# --------------------------------------------------------------------------
+
+MEAN_TOL_MIXED = 1e-8
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("n,ns,tile", [(1024, 256, 128), (4096, 1024, 256)])
+def test_mixed_fit_predict(ctx, prec, n, ns, tile):
+    say(f"mixed {prec} fit_predict n={n} n_test={ns} tile={tile}")
+    X, y, Xs = nfir_train_test(n, ns)
+    ref = oracle.predict(X, y, Xs, DEFAULT_HYPER, want=("L", "mean", "cov"))
+    Xd, yd, Xsd = dev(X), dev(y), dev(Xs)
+    mean, cov, K, st = ctx.fit_predict(Xd, yd, Xsd, DEFAULT_HYPER, tile, precision=prec,
+                                       ir_stats=True)
+    m, c = host(mean), host(cov)
+    L = host(ctx.to_dense(K))
+    em = oracle.rel_err(m, ref["mean"])
+    ec = oracle.rel_err(c, ref["cov"])
+    el = oracle.rel_err_lower(L, ref["L"])
+    say(f"  IR steps {st['iters']}, ||r||/||y|| {st['rel_residual']:.2e}, precision used "
+        f"{st['precision']}; rel(mean) {em:.2e}  rel(L) {el:.2e}  rel(cov) {ec:.2e}")
+    assert em <= MEAN_TOL_MIXED
+    np.testing.assert_array_equal(c, c.T)
+    if st["precision"] != 0:
+        assert st["rel_residual"] <= 1e-10
+        assert el <= (1e-4 if prec == "fp32" else 1e-1)   # stated, not pinned
+    K.free()
+
+
+def test_mixed_cholesky_then_predict(ctx):
+    n, ns, tile = 1024, 128, 128
+    say(f"mixed fp32 cholesky + predict n={n} n_test={ns} tile={tile}")
+    X, y, Xs = nfir_train_test(n, ns)
+    Xd, yd, Xsd = dev(X), dev(y), dev(Xs)
+    K = ctx.assemble(Xd, DEFAULT_HYPER, tile)
+    ctx.cholesky(K, "fp32")
+    mean, cov, st = ctx.predict(K, Xd, yd, Xsd, DEFAULT_HYPER, ir_stats=True)
+    ref = oracle.predict(X, y, Xs, DEFAULT_HYPER, want=("mean",))
+    em = oracle.rel_err(host(mean), ref["mean"])
+    say(f"  IR steps {st['iters']}, ||r||/||y|| {st['rel_residual']:.2e}, rel(mean) {em:.2e}")
+    assert st["iters"] >= 1 and em <= MEAN_TOL_MIXED
+    K.free()

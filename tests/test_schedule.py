@@ -60,12 +60,14 @@ def accesses(task, M, mode):
 def happens_before(launches):
     n = len(launches)
     pred = [set() for _ in range(n)]
-    last = {0: -1, 1: -1}
-    for i, (st, wait, _) in enumerate(launches):
+    last = {0: -1, 1: -1, 2: -1}
+    launches = [tuple(int(v) for v in l) for l in launches]
+    for i, (st, w0, w1, w2, _) in enumerate(launches):
         if last[st] >= 0:
             pred[i].add(last[st])
-        if wait >= 0:
-            pred[i].add(wait)
+        for w in (w0, w1, w2):
+            if w >= 0:
+                pred[i].add(w)
         last[st] = i
     reach = [0] * n  # bitset of launches that happen before i
     for i in range(n):
@@ -120,8 +122,9 @@ def test_memory_fraction_of_lower_tiles():
     assert (32 * 33 // 2) * 512 * 512 * 8 == 1107296256  # bytes of K at n = 16384, m = 512
 
 
-@pytest.mark.parametrize("M,Mhat,mode", [(1, 0, 0), (2, 0, 0), (5, 0, 0), (9, 0, 0),
-                                         (4, 3, 1), (7, 2, 1), (1, 2, 1), (5, 3, 2), (6, 1, 2)])
+@pytest.mark.parametrize("M,Mhat,mode", [(1, 0, 0), (2, 0, 0), (3, 0, 0), (5, 0, 0), (9, 0, 0),
+                                         (4, 3, 1), (7, 2, 1), (1, 2, 1), (5, 3, 2), (6, 1, 2),
+                                         (2, 2, 2), (1, 3, 2), (3, 1, 2)])
 def test_schedule_has_no_races(M, Mhat, mode):
     tasks, launches = schedule_describe(M, Mhat, mode)
     prog = fig1_program(M, Mhat, mode)
@@ -129,9 +132,10 @@ def test_schedule_has_no_races(M, Mhat, mode):
     assert got == sorted(prog), "schedule task multiset differs from Fig. 1"
     where = {tuple(t[:4]): int(t[4]) for t in tasks}
     reach, _ = happens_before([tuple(l) for l in launches])
-    # launches only wait on earlier launches of the other stream
-    for i, (st, wait, _) in enumerate(launches):
-        assert wait < i and (wait < 0 or launches[wait][0] != st)
+    # launches only wait on earlier launches of other streams
+    for i, (st, w0, w1, w2, _) in enumerate(launches):
+        for w in (w0, w1, w2):
+            assert w < i and (w < 0 or launches[w][0] != st)
 
     def ordered(a, b):
         la, lb = where[a], where[b]
@@ -181,7 +185,8 @@ def run_schedule_on_host(tiles, tinv, tasks, launches, rng):
         done.add(li)
 
 
-@pytest.mark.parametrize("M,Mhat,mode,m", [(4, 0, 0, 8), (5, 3, 2, 6), (3, 2, 1, 7)])
+@pytest.mark.parametrize("M,Mhat,mode,m", [(4, 0, 0, 8), (5, 3, 2, 6), (3, 2, 1, 7), (2, 2, 2, 5),
+                                           (6, 1, 2, 4)])
 def test_host_execution_matches_oracle(M, Mhat, mode, m):
     n, ns = M * m, Mhat * m
     h = (1.0, 1.0, 0.1)
