@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define GPR_ABI_VERSION 1
+#define GPR_ABI_VERSION 2
 
 /* Status codes. */
 enum {
@@ -183,13 +183,29 @@ int gpr_solve(gpr_ctx* ctx, gpr_tiled* L, const double* b, double* x, void* stre
 
 /* Negative log marginal likelihood
  *   NLML = 1/2 y^T K^{-1} y + 1/2 log det K + n/2 log(2 pi)
- * and its gradient with respect to (l, v, sigma^2), from a Cholesky adjoint
- * (reverse sweep over the tile tasks) and the solve adjoint.
- * out_nlml: device, 1 double. out_grad3: device, 3 doubles (may be NULL to
- * skip the gradient). Returns GPR_ENOTSUP until the adjoint kernels exist. */
+ *        = 1/2 beta^T beta + sum_i log L_ii + n/2 log(2 pi),  beta = L^{-1} y,
+ * with K = K(X, X) + sigma^2 I of eq. (1) factored by the tiled Cholesky
+ * (Sec. 4.2), and its gradient with respect to (l, v, sigma^2). The gradient
+ * runs reverse-mode through the computation: the solve adjoint gives the
+ * adjoint of the factor, Lbar = -tril(alpha beta^T) + diag(1 / L_ii), and a
+ * reverse sweep over the tile tasks of Fig. 1 (the Cholesky adjoint) turns it
+ * into Kbar = 1/2 (K^{-1} - alpha alpha^T); then
+ *   dNLML/dtheta = sum_ij Kbar_ij dK_ij/dtheta,
+ *   dK/dl = v e s / (2 l^2), dK/dv = e, dK/dsigma^2 = I   (e = exp(-s / (2 l))).
+ * X: device n x D row-major; y: device n. tile: as gpr_assemble.
+ * prec: GPR_FP64 (the mixed precisions return GPR_ENOTSUP: the log
+ * determinant is taken from the FP64 factor).
+ * out_nlml: device, 1 double. out_grad3: device, 3 doubles in the order
+ * (l, v, sigma^2), or NULL. out_Kbar: device n x n row-major, receives the
+ * symmetric Kbar (gradient with respect to K for any kernel), or NULL. With
+ * both NULL only the NLML is computed (no reverse sweep).
+ * Asynchronous on `stream`. A failed pivot writes NaN to every output and is
+ * reported by gpr_sync (GPR_ENOTPD). Workspace (two lower-tiled n x n arrays
+ * plus a few tiles) is kept in the context for the next call. */
 int gpr_nlml_grad(gpr_ctx* ctx, const double* X, const double* y, int64_t n,
                   int32_t D, gpr_hyper h, int32_t tile, gpr_precision prec,
-                  double* out_nlml, double* out_grad3, void* stream);
+                  double* out_nlml, double* out_grad3, double* out_Kbar,
+                  void* stream);
 
 /* ---- handles and utilities ----------------------------------------------- */
 
@@ -218,14 +234,16 @@ int gpr_sync(gpr_ctx* ctx, void* stream, int64_t* column);
  * launch the context issues is bracketed by HIP timing events on the stream
  * it runs on. Kinds: 0 POTRF, 1 inverse of the diagonal tiles, 2 TRSM,
  * 3 tile update (GEMM / SYRK), 4 assembly, 5 triangular-solve GEMV,
- * 6 kernel matvec (mean / residual), 7 export to dense. */
+ * 6 kernel matvec (mean / residual), 7 export to dense, 8 adjoint tile
+ * products of the reverse sweep, 9 adjoint seed and gradient reduction. */
 int gpr_profile_enable(gpr_ctx* ctx, int on);
 
 /* Totals for one kind over the launches recorded since the last reset:
  * number of launches, summed device time in ms, and summed algorithmic
  * flops (GEMM tile 2 m^3, SYRK / TRSM tile m^3, POTRF and inverse m^3 / 3 each,
- * GEMV tile 2 m^2, kernel matvec 2 per entry) and bytes (assembly and export:
- * bytes written). Blocks until the recorded work is done. reset != 0 clears
+ * GEMV tile 2 m^2, kernel matvec 2 per entry, adjoint tile product 2 m^3
+ * per term) and bytes (assembly and export: bytes written; adjoint seed and
+ * reduction: bytes of the lower tiles). Blocks until the recorded work is done. reset != 0 clears
  * all kinds after reading. Any out pointer may be NULL. */
 int gpr_profile_read(gpr_ctx* ctx, int kind, int64_t* launches, double* total_ms,
                      double* flops, double* bytes, int reset);
@@ -253,6 +271,30 @@ int gpr_schedule_describe(int32_t M, int32_t Mhat, int32_t mode,
                           int32_t* tasks, int64_t task_cap, int64_t* n_tasks,
                           int32_t* launches, int64_t launch_cap,
                           int64_t* n_launches);
+
+/* The reverse sweep of gpr_nlml_grad as a list of batched tile-product
+ * launches, for M tile rows and a split of the long row sums into chunks of
+ * G terms, without running anything (host only).
+ * Operands are symbolic (matrix, I, J): matrix 0 L (factor tile (I, J)),
+ * 1 Lbar, 2 Abar (tile (I, J) of the lower-tiled adjoint arrays), 3 inverse
+ * of diagonal tile I, 4 partial tile I, 5 / 6 / 7 single scratch tiles Q, G, X;
+ * -1 none. Each task computes
+ *   out = [cin] + sum_terms alpha op(A) op(B) + sum of partial tiles
+ *         part0 .. part0 + npart - 1,
+ * then its epilogue (0 none, 1 lower triangle with the diagonal halved,
+ * 2 mirror the lower triangle into the upper one).
+ * tasks: 12 int32 per task: out (3), cin (3), part0, npart, first_term,
+ * nterm, epilogue, 0. terms: 8 int32 per term: A (3), B (3), alpha (+1 or -1),
+ * flags (1 A transposed, 2 B transposed, 4 A lower-triangular, 8 B
+ * lower-triangular). launches: 4 int32 per launch: kind (0 TRSM adjoint,
+ * 1 partial sums, 2 diagonal sum, 3 POTRF adjoint, 4 push), step, first task,
+ * task count; launches run in list order, tasks of one launch in parallel.
+ * Capacities in records; counts always written; GPR_EINVAL if one is too
+ * small. */
+int gpr_adjoint_describe(int32_t M, int32_t G, int32_t* tasks, int64_t task_cap,
+                         int64_t* n_tasks, int32_t* terms, int64_t term_cap,
+                         int64_t* n_terms, int32_t* launches, int64_t launch_cap,
+                         int64_t* n_launches);
 
 /* ABI version of the loaded library (GPR_ABI_VERSION it was built with). */
 int gpr_abi_version(void);

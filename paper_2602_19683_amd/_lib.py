@@ -47,7 +47,7 @@ SIGNATURES = {
                                        ctypes.POINTER(IRStats), _vp]),
     "gpr_solve": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "gpr_nlml_grad": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, Hyper, _i32, ctypes.c_int, _vp,
-                                     _vp, _vp]),
+                                     _vp, _vp, _vp]),
     "gpr_profile_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
     "gpr_profile_read": (ctypes.c_int, [_vp, ctypes.c_int, _i64p, ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_double),
@@ -58,6 +58,8 @@ SIGNATURES = {
     "gpr_sync": (ctypes.c_int, [_vp, _vp, _i64p]),
     "gpr_schedule_describe": (ctypes.c_int, [_i32, _i32, _i32, _i32p, _i64, _i64p, _i32p, _i64,
                                              _i64p]),
+    "gpr_adjoint_describe": (ctypes.c_int, [_i32, _i32, _i32p, _i64, _i64p, _i32p, _i64, _i64p,
+                                            _i32p, _i64, _i64p]),
 }
 
 _LIB = None

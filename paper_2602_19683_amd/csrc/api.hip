@@ -42,6 +42,9 @@ struct gpr_ctx {
     char* d_ws = nullptr;         // prediction workspace
     size_t ws_cap = 0;
     gpr_tiled* scratch = nullptr; // for gpr_cholesky_dense
+    gpr_tiled* nlml_K = nullptr;  // factor kept by gpr_nlml_grad
+    char* d_adj = nullptr;        // adjoint workspace (Lbar, Abar, partial tiles)
+    size_t adj_cap = 0;
     // instrumentation
     bool prof_on = false;
     std::vector<hipEvent_t> tpool;  // timing events, reused after each read
@@ -52,8 +55,8 @@ struct gpr_ctx {
         double flops, bytes;
     };
     std::vector<ProfRec> pending;
-    int64_t p_launches[8] = {};
-    double p_ms[8] = {}, p_flops[8] = {}, p_bytes[8] = {};
+    int64_t p_launches[10] = {};
+    double p_ms[10] = {}, p_flops[10] = {}, p_bytes[10] = {};
 };
 
 struct gpr_tiled {
@@ -160,7 +163,8 @@ int ensure_events(gpr_ctx* ctx, size_t n)
 }
 
 enum ProfKind { PK_POTRF = 0, PK_TRTRI = 1, PK_TRSM = 2, PK_UPDATE = 3, PK_ASSEMBLE = 4,
-                PK_GEMV = 5, PK_MATVEC = 6, PK_EXPORT = 7, PK_COUNT = 8 };
+                PK_GEMV = 5, PK_MATVEC = 6, PK_EXPORT = 7, PK_ADJOINT = 8, PK_REDUCE = 9,
+                PK_COUNT = 10 };
 
 hipEvent_t timing_event(gpr_ctx* ctx)
 {
@@ -386,6 +390,7 @@ bool valid_prec(int prec, int m)
 struct SolvePlan {
     std::vector<size_t> off;  // per launch
     std::vector<int> count;
+    int nfwd = 0;             // launches of the forward substitution
 };
 
 SolvePlan plan_solves(const gpr_tiled* L, double* r, double* beta, double* alpha, DescBuffer& db)
@@ -404,6 +409,7 @@ SolvePlan plan_solves(const gpr_tiled* L, double* r, double* beta, double* alpha
             up.push_back({tile_ptr(Km, K, J), beta + (size_t)J * m, r + (size_t)K * m, m, 0, 0, 0});
         if (!up.empty()) add(up);
     }
+    P.nfwd = (int)P.off.size();
     for (int J = M - 1; J >= 0; --J) {  // backward, in place on beta
         add({GemvTask{L->tinv + (size_t)J * m * m, beta + (size_t)J * m, alpha + (size_t)J * m, m, 1, 1, 0}});
         std::vector<GemvTask> up;
@@ -414,16 +420,101 @@ SolvePlan plan_solves(const gpr_tiled* L, double* r, double* beta, double* alpha
     return P;
 }
 
+// Runs launches [begin, end) of the plan (end < 0: to the last).
 int run_solves(gpr_ctx* ctx, const gpr_tiled* L, const SolvePlan& P, const DescBuffer& db,
-               hipStream_t s)
+               hipStream_t s, int begin = 0, int end = -1)
 {
     const double m2 = (double)L->m * L->m;
-    for (size_t i = 0; i < P.off.size(); ++i) {
+    if (end < 0) end = (int)P.off.size();
+    for (int i = begin; i < end; ++i) {
         ProfScope ps(ctx, s, PK_GEMV, 2.0 * m2 * P.count[i], 0.0);
         HIP_TRY(launch_gemv_f64(db.dev<GemvTask>(ctx, P.off[i]), P.count[i], L->m, s));
     }
     return GPR_OK;
 }
+
+// Buffers of the reverse sweep (symbolic operands of an AdjPlan resolve here).
+struct AdjBufs {
+    TileMat L, Lbar, Abar;
+    double* tinv;
+    double* part;
+    double *q, *g, *x;
+    int m;
+    double* at(const AdjRef& r) const
+    {
+        const size_t m2 = (size_t)m * m;
+        switch (r.mat) {
+        case AM_L: return tile_ptr(L, r.I, r.J);
+        case AM_LBAR: return tile_ptr(Lbar, r.I, r.J);
+        case AM_ABAR: return tile_ptr(Abar, r.I, r.J);
+        case AM_TINV: return tinv + (size_t)r.I * m2;
+        case AM_PART: return part + (size_t)r.I * m2;
+        case AM_Q: return q;
+        case AM_G: return g;
+        case AM_X: return x;
+        default: return nullptr;
+        }
+    }
+};
+
+struct AdjExec {
+    std::vector<size_t> task_off, term_off;
+    std::vector<int> bm;
+    std::vector<double> flops;
+};
+
+AdjExec plan_adjoint_exec(const AdjPlan& P, const AdjBufs& B, DescBuffer& db)
+{
+    AdjExec E;
+    const int m = B.m;
+    const double m3 = (double)m * m * m;
+    for (const AdjLaunch& L : P.launches) {
+        std::vector<TGemmTask> tv;
+        std::vector<TGemmTerm> rv;
+        const int term0 = L.count ? P.tasks[L.first].first_term : 0;
+        double f = 0.0;
+        for (int t = L.first; t < L.first + L.count; ++t) {
+            const AdjTask& a = P.tasks[t];
+            TGemmTask k;
+            k.C = B.at(a.out);
+            k.Cin = a.cin.mat == AM_NONE ? nullptr : B.at(a.cin);
+            k.beta = a.cin.mat == AM_NONE ? 0.0 : 1.0;
+            k.part = a.npart ? B.part + (size_t)a.part0 * m * m : nullptr;
+            k.part_stride = (long long)m * m;
+            k.ldc = k.ldcin = m;
+            k.npart = a.npart;
+            k.first_term = a.first_term - term0;
+            k.nterm = a.nterm;
+            k.epi = a.epi;
+            tv.push_back(k);
+            for (int q = a.first_term; q < a.first_term + a.nterm; ++q) {
+                const AdjTerm& x = P.terms[q];
+                rv.push_back({B.at(x.A), B.at(x.B), (double)x.alpha, m, m, x.flags, 0});
+                f += (a.epi == TG_EPI_SYM ? 1.0 : 2.0) * m3;
+            }
+        }
+        E.task_off.push_back(db.add(tv.data(), tv.size() * sizeof(TGemmTask)));
+        E.term_off.push_back(db.add(rv.data(), rv.size() * sizeof(TGemmTerm)));
+        E.bm.push_back(tgemm_block(L.count, m));
+        E.flops.push_back(f);
+    }
+    return E;
+}
+
+int run_adjoint(gpr_ctx* ctx, const AdjPlan& P, const AdjExec& E, int m, const DescBuffer& db,
+                hipStream_t s)
+{
+    for (size_t i = 0; i < P.launches.size(); ++i) {
+        ProfScope ps(ctx, s, PK_ADJOINT, E.flops[i], 0.0);
+        HIP_TRY(launch_tgemm_f64(db.dev<TGemmTask>(ctx, E.task_off[i]), P.launches[i].count,
+                                 db.dev<TGemmTerm>(ctx, E.term_off[i]), m, E.bm[i], s));
+    }
+    return GPR_OK;
+}
+
+// Split of the row sums of the reverse sweep into partial tiles: chunks of
+// this many terms.
+constexpr int ADJ_CHUNK = 2;
 
 int finish_info(gpr_ctx* ctx, int32_t* info_dev, hipStream_t s);
 
@@ -500,6 +591,8 @@ int gpr_ctx_destroy(gpr_ctx* c)
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
     if (c->scratch) gpr_tiled_free(c->scratch);
+    if (c->nlml_K) gpr_tiled_free(c->nlml_K);
+    if (c->d_adj) (void)hipFree(c->d_adj);
     for (auto e : c->evpool) (void)hipEventDestroy(e);
     for (auto e : c->tpool) (void)hipEventDestroy(e);
     if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
@@ -840,14 +933,116 @@ int gpr_solve(gpr_ctx* ctx, gpr_tiled* L, const double* b, double* x, void* stre
 
 int gpr_nlml_grad(gpr_ctx* ctx, const double* X, const double* y, int64_t n, int32_t D,
                   gpr_hyper h, int32_t tile, gpr_precision prec, double* out_nlml,
-                  double* out_grad3, void* stream)
+                  double* out_grad3, double* out_Kbar, void* stream)
 {
     if (!ctx || !X || !y || n < 1 || D < 1 || !valid_tile(tile) || !valid_hyper(h) || !out_nlml)
         return GPR_EINVAL;
-    (void)prec;
-    (void)out_grad3;
-    (void)stream;
-    return GPR_ENOTSUP;
+    if (!valid_prec(prec, tile)) return GPR_EINVAL;
+    if (prec != GPR_FP64) return GPR_ENOTSUP;  // log det needs the FP64 factor
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int rc = begin_call(ctx, s);
+    if (rc) return rc;
+    gpr_tiled* K = ctx->nlml_K;
+    if (K && (K->n != n || K->m != tile)) {
+        gpr_tiled_free(K);
+        K = ctx->nlml_K = nullptr;
+    }
+    if (!K) {
+        rc = alloc_tiled(ctx, n, tile, &K);
+        if (rc) return rc;
+        ctx->nlml_K = K;
+    }
+    const int m = K->m, M = K->M;
+    if (!K->tinv) {
+        if (hipMalloc(reinterpret_cast<void**>(&K->tinv), (size_t)M * m * m * sizeof(double)) !=
+            hipSuccess) {
+            (void)hipGetLastError();
+            return GPR_ENOMEM;
+        }
+    }
+    const bool grad = out_grad3 || out_Kbar;
+    const size_t npad = (size_t)M * m;
+    const int nparts = grad ? grad_reduce_parts(M, m) : 0;
+    rc = ensure_device_bytes(&ctx->d_ws, &ctx->ws_cap,
+                             (4 * npad + 3 * (size_t)(nparts + 1)) * sizeof(double) + 256);
+    if (rc) return rc;
+    double* r = reinterpret_cast<double*>(ctx->d_ws);
+    double* beta = r + npad;
+    double* alpha = beta + npad;
+    double* bsave = alpha + npad;
+    double* parts = bsave + npad;
+
+    DescBuffer db;
+    SweepMats SM{kmat(K), K->tinv, TileMat{nullptr, m, 1, M}, TileMat{nullptr, m, 0, 0}, M, 0, m,
+                 GPR_FP64};
+    SweepPlan PP = plan_sweep(SM, SWEEP_CHOLESKY, db);
+    SolvePlan SP = plan_solves(K, r, beta, alpha, db);
+    AdjPlan AP;
+    AdjExec AE;
+    AdjBufs AB{};
+    if (grad) {
+        AP = build_adjoint(M, ADJ_CHUNK);
+        const size_t tb = tiled_bytes(K);
+        const size_t m2b = (size_t)m * m * sizeof(double);
+        rc = ensure_device_bytes(&ctx->d_adj, &ctx->adj_cap,
+                                 2 * tb + (size_t)(AP.max_part + 3) * m2b);
+        if (rc) return rc;
+        double* base = reinterpret_cast<double*>(ctx->d_adj);
+        AB.L = kmat(K);
+        AB.Lbar = TileMat{base, m, 0, 0};
+        AB.Abar = TileMat{base + tb / sizeof(double), m, 0, 0};
+        AB.part = base + 2 * tb / sizeof(double);
+        AB.q = AB.part + (size_t)AP.max_part * m * m;
+        AB.g = AB.q + (size_t)m * m;
+        AB.x = AB.g + (size_t)m * m;
+        AB.tinv = K->tinv;
+        AB.m = m;
+        AE = plan_adjoint_exec(AP, AB, db);
+    }
+    rc = db.upload(ctx, s);
+    if (rc) return rc;
+
+    // K (with noise), its factor, and the diagonal-tile inverses
+    {
+        ProfScope ps(ctx, s, PK_ASSEMBLE, 0.0, (double)tiled_bytes(K));
+        HIP_TRY(launch_assemble(kmat(K), M, X, n, X, n, D, h.lengthscale, h.vertical_variance,
+                                h.noise_variance, true, true, s));
+    }
+    K->state = GPR_STATE_K;
+    HIP_TRY(launch_set_int(ctx->d_info, 0, s));
+    rc = run_sweep(ctx, SM, PP, db, s);
+    if (rc) return rc;
+    {
+        ProfScope ps(ctx, s, PK_TRTRI, M * (double)m * m * m / 3.0, 0.0);
+        HIP_TRY(launch_trtri_f64(kmat(K), M, K->tinv, s));
+    }
+    K->state = GPR_STATE_L;
+    K->prec = GPR_FP64;
+    rc = finish_info(ctx, nullptr, s);
+    if (rc) return rc;
+    // beta = L^{-1} y (kept), alpha = L^{-T} beta
+    HIP_TRY(launch_copy_f64(y, r, n, (int64_t)npad, s));
+    rc = run_solves(ctx, K, SP, db, s, 0, SP.nfwd);
+    if (rc) return rc;
+    HIP_TRY(launch_copy_f64(beta, bsave, (int64_t)npad, (int64_t)npad, s));
+    rc = run_solves(ctx, K, SP, db, s, SP.nfwd, -1);
+    if (rc) return rc;
+    if (grad) {
+        {
+            ProfScope ps(ctx, s, PK_REDUCE, 0.0, (double)tiled_bytes(K));
+            HIP_TRY(launch_lbar_init(AB.Lbar, AB.L, M, alpha, bsave, s));
+        }
+        rc = run_adjoint(ctx, AP, AE, m, db, s);
+        if (rc) return rc;
+        {
+            ProfScope ps(ctx, s, PK_REDUCE, 0.0, (double)tiled_bytes(K));
+            HIP_TRY(launch_grad_reduce(AB.Abar, M, X, n, D, h.lengthscale, parts, s));
+        }
+        if (out_Kbar) HIP_TRY(launch_kbar_export(AB.Abar, n, out_Kbar, s));
+    }
+    HIP_TRY(launch_nlml_finish(kmat(K), bsave, n, parts, out_grad3 ? nparts : 0, h.lengthscale,
+                               h.vertical_variance, ctx->d_info, out_nlml, out_grad3, s));
+    return end_call(ctx, s);
 }
 
 int gpr_profile_enable(gpr_ctx* ctx, int on)

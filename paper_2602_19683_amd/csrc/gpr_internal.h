@@ -72,6 +72,30 @@ struct GemvTask {
     int ld, trans, set, pad;
 };
 
+// Tile product task of the adjoint sweep (k_tgemm.hip):
+//   C = beta Cin + sum_t alpha_t op(A_t) op(B_t) + sum_p part[p * part_stride],
+// then the epilogue. All tiles m x m; partial tiles have leading dimension m.
+enum : int { TG_TRANS_A = 1, TG_TRANS_B = 2, TG_TRI_A = 4, TG_TRI_B = 8 };
+// TG_EPI_PHI: keep the lower triangle, halve the diagonal, zero the upper.
+// TG_EPI_SYM: write the lower triangle and mirror it into the upper one.
+enum : int { TG_EPI_NONE = 0, TG_EPI_PHI = 1, TG_EPI_SYM = 2 };
+
+struct TGemmTerm {
+    const double* A;
+    const double* B;
+    double alpha;
+    int lda, ldb, flags, pad;
+};
+
+struct TGemmTask {
+    double* C;
+    const double* Cin;
+    const double* part;
+    long long part_stride;
+    double beta;
+    int ldc, ldcin, npart, first_term, nterm, epi;
+};
+
 // ---------------------------------------------------------------------------
 // Kernel launchers (defined in the k_*.hip files). All return hipError_t of
 // the launch; grid sizes are derived from the arguments.
@@ -128,6 +152,30 @@ hipError_t launch_axpy(double* y, const double* x, int64_t n, hipStream_t s);
 hipError_t launch_symv_tiled(const TileMat& K, int M, const double* x, const double* base,
                              double* out, int64_t n, hipStream_t s);
 
+// Adjoint sweep tile products; bm in {32, 64, 128} divides m.
+int tgemm_block(int ntask, int m);
+hipError_t launch_tgemm_f64(const TGemmTask* d_tasks, int ntask, const TGemmTerm* d_terms, int m,
+                            int bm, hipStream_t s);
+// NLML seed of the adjoint: W (lower tiles) = -tril(alpha beta^T) + diag(1 / L_ii),
+// zero above the diagonal of the diagonal tiles.
+hipError_t launch_lbar_init(const TileMat& W, const TileMat& L, int M, const double* alpha,
+                            const double* beta, hipStream_t s);
+// Per-workgroup partial sums (3 per workgroup) of
+//   sum_{i >= j, i, j < n} A_ij (e_ij s_ij, e_ij, delta_ij),  e_ij = exp(-s_ij / (2 l)),
+// over the lower tiles of A; returns the number of partial triples written.
+int grad_reduce_parts(int M, int m);
+hipError_t launch_grad_reduce(const TileMat& A, int M, const double* X, int64_t n, int D,
+                              double l, double* parts, hipStream_t s);
+// Dense symmetric adjoint from the lower-convention Abar: out_ij = Abar_ii on the
+// diagonal, Abar_{max(i,j), min(i,j)} / 2 elsewhere (n x n, row-major).
+hipError_t launch_kbar_export(const TileMat& A, int64_t n, double* out, hipStream_t s);
+// out_nlml = 1/2 beta^T beta + sum log L_ii + n/2 log(2 pi); out_grad3 (if not
+// null) from the partial triples. NaN if info[0] > 0.
+hipError_t launch_nlml_finish(const TileMat& L, const double* beta, int64_t n,
+                              const double* parts, int nparts, double l, double v,
+                              const int* info, double* out_nlml, double* out_grad3,
+                              hipStream_t s);
+
 hipError_t launch_set_int(int* p, int value, hipStream_t s);
 hipError_t launch_copy_f64(const double* src, double* dst, int64_t n, int64_t n_pad,
                            hipStream_t s);
@@ -157,6 +205,37 @@ struct Schedule {
     std::vector<SchedTask> tasks;
     std::vector<SchedLaunch> launches;
 };
+
+// Reverse sweep of the tiled Cholesky (adjoint.cpp). Operands are symbolic:
+// matrix id and tile coordinates, resolved to pointers by the executor.
+enum AdjMat : int { AM_NONE = -1, AM_L = 0, AM_LBAR = 1, AM_ABAR = 2, AM_TINV = 3, AM_PART = 4,
+                    AM_Q = 5, AM_G = 6, AM_X = 7 };
+enum AdjLaunchKind : int { AK_TRSM = 0, AK_PART = 1, AK_DIAG_SUM = 2, AK_POTRF = 3, AK_PUSH = 4 };
+
+struct AdjRef {
+    int mat, I, J;  // AM_TINV: tile I; AM_PART: partial tile I; AM_Q/G/X: single tiles
+};
+struct AdjTerm {
+    AdjRef A, B;
+    int alpha;  // +1 or -1
+    int flags;  // TG_*
+};
+struct AdjTask {
+    AdjRef out, cin;  // cin.mat == AM_NONE: beta = 0
+    int part0, npart;
+    int first_term, nterm;
+    int epi;
+};
+struct AdjLaunch {
+    int kind, step, first, count;
+};
+struct AdjPlan {
+    std::vector<AdjTask> tasks;
+    std::vector<AdjTerm> terms;
+    std::vector<AdjLaunch> launches;
+    int max_part = 0;  // partial tiles needed
+};
+AdjPlan build_adjoint(int M, int G);
 
 // Tile sweep over M training tile rows and Mhat test tile rows (see gpr.h,
 // gpr_schedule_describe).

@@ -212,23 +212,32 @@ class Context:
                                    _stream(stream)), "gpr_solve")
         return x
 
-    def nlml_grad(self, X, y, hyper, tile, precision="fp64", out_nlml=None, out_grad=None,
-                  stream=None):
+    def nlml_grad(self, X, y, hyper, tile, precision="fp64", grad=True, kbar=False,
+                  out_nlml=None, out_grad=None, out_kbar=None, stream=None):
+        """NLML and (if grad) its gradient in the order (l, v, sigma^2), as
+        device tensors; with kbar also the dense symmetric adjoint
+        1/2 (K^{-1} - alpha alpha^T). Returns (nlml[1], grad[3] or None,
+        kbar[n, n] or None)."""
         import torch
         n, D = X.shape
         if out_nlml is None:
             out_nlml = torch.empty(1, dtype=torch.float64, device=X.device)
-        if out_grad is None:
+        if grad and out_grad is None:
             out_grad = torch.empty(3, dtype=torch.float64, device=X.device)
+        if kbar and out_kbar is None:
+            out_kbar = torch.empty(n, n, dtype=torch.float64, device=X.device)
         _check(self._lib.gpr_nlml_grad(self._h, _dev_ptr(X, "X"), _dev_ptr(y, "y", n), n, D,
                                        _hyper(hyper), int(tile), _prec(precision),
                                        _dev_ptr(out_nlml, "out_nlml", 1),
-                                       _dev_ptr(out_grad, "out_grad", 3), _stream(stream)),
+                                       _dev_ptr(out_grad, "out_grad", 3) if grad else None,
+                                       _dev_ptr(out_kbar, "out_kbar", n * n) if kbar else None,
+                                       _stream(stream)),
                "gpr_nlml_grad")
-        return out_nlml, out_grad
+        return out_nlml, (out_grad if grad else None), (out_kbar if kbar else None)
 
     # ---- instrumentation --------------------------------------------------
-    PROFILE_KINDS = ("potrf", "trtri", "trsm", "update", "assemble", "gemv", "matvec", "export")
+    PROFILE_KINDS = ("potrf", "trtri", "trsm", "update", "assemble", "gemv", "matvec", "export",
+                     "adjoint", "reduce")
 
     def profile(self, on=True):
         _check(self._lib.gpr_profile_enable(self._h, int(bool(on))), "gpr_profile_enable")
@@ -291,3 +300,61 @@ def schedule_describe(M, Mhat, mode):
                                      launches.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
                                      nl.value, ctypes.byref(nl)), "gpr_schedule_describe")
     return tasks, launches
+
+
+def adjoint_describe(M, G):
+    """Host-only: the launch list of the reverse sweep of gpr_nlml_grad (see
+    gpr.h). Returns ``(tasks, terms, launches)``: int32 arrays of shape
+    (T, 12), (R, 8) and (L, 4)."""
+    lib = _lib.load()
+    nt, nr, nl = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    st = lib.gpr_adjoint_describe(M, G, None, 0, ctypes.byref(nt), None, 0, ctypes.byref(nr),
+                                  None, 0, ctypes.byref(nl))
+    if st not in (GPR_OK, _lib.GPR_EINVAL) or nt.value < 0:
+        raise GPRError(st, "gpr_adjoint_describe")
+    tasks = np.zeros((nt.value, 12), dtype=np.int32)
+    terms = np.zeros((nr.value, 8), dtype=np.int32)
+    launches = np.zeros((nl.value, 4), dtype=np.int32)
+    ip = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))  # noqa: E731
+    _check(lib.gpr_adjoint_describe(M, G, ip(tasks), nt.value, ctypes.byref(nt), ip(terms),
+                                    nr.value, ctypes.byref(nr), ip(launches), nl.value,
+                                    ctypes.byref(nl)), "gpr_adjoint_describe")
+    return tasks, terms, launches
+
+
+class NLML:
+    """Differentiable NLML of the exact GP with the squared-exponential kernel:
+    ``NLML.apply(theta, X, y, ctx, tile)`` with ``theta = (l, v, sigma^2)`` a
+    float64 tensor of 3 entries. The forward pass runs gpr_nlml_grad on the
+    GPU, with the reverse sweep when theta requires a gradient; the backward
+    pass scales that gradient (no further device work). Returns a 0-d tensor
+    on theta's device."""
+
+    _fn = None
+
+    @classmethod
+    def apply(cls, theta, X, y, ctx, tile):
+        if cls._fn is None:
+            cls._fn = _make_nlml_function()
+        return cls._fn.apply(theta, X, y, ctx, tile)
+
+
+def _make_nlml_function():
+    import torch
+
+    class _NLMLFunction(torch.autograd.Function):
+        @staticmethod
+        def forward(fctx, theta, X, y, ctx, tile):
+            th = [float(t) for t in theta.detach().cpu().tolist()]
+            want = theta.requires_grad
+            nl, g, _ = ctx.nlml_grad(X, y, th, tile, grad=want)
+            ctx.sync()
+            fctx.save_for_backward(g.to(theta.device) if want else theta.new_zeros(3))
+            return nl.reshape(()).to(theta.device)
+
+        @staticmethod
+        def backward(fctx, gout):
+            (g,) = fctx.saved_tensors
+            return gout * g, None, None, None, None
+
+    return _NLMLFunction

@@ -29,7 +29,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_abi_version_and_strerror():
     lib = _lib.load()
-    assert lib.gpr_abi_version() == 1
+    assert lib.gpr_abi_version() == 2
     for code in [0, 1, -1, -2, -3, -4, -5]:
         assert lib.gpr_strerror(code)
     assert b"unknown" in lib.gpr_strerror(12345)
@@ -64,7 +64,8 @@ def test_host_argument_validation():
     assert lib.gpr_cholesky_dense(None, None, 10, 32, 0, None, None) == _lib.GPR_EINVAL
     assert lib.gpr_predict(None, None, None, None, 10, None, 5, 8, H, None, None, None,
                            None) == _lib.GPR_EINVAL
-    assert lib.gpr_nlml_grad(None, None, None, 10, 8, H, 32, 0, None, None, None) == _lib.GPR_EINVAL
+    assert lib.gpr_nlml_grad(None, None, None, 10, 8, H, 32, 0, None, None, None,
+                             None) == _lib.GPR_EINVAL
     assert lib.gpr_solve(None, None, None, None, None) == _lib.GPR_EINVAL
     assert lib.gpr_fit_predict(None, None, None, 10, None, 5, 8, H, 32, 0, None, None, None,
                                None, None, None) == _lib.GPR_EINVAL
@@ -88,3 +89,16 @@ def test_schedule_describe_argument_errors():
     assert lib.gpr_schedule_describe(4, 0, 0, None, 0, ctypes.byref(nt), None, 0,
                                      ctypes.byref(nl)) == _lib.GPR_EINVAL
     assert nt.value == 4 + 6 + 6 + 4
+
+
+def test_adjoint_describe_argument_errors():
+    lib = _lib.load()
+    nt, nr, nl = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+    assert lib.gpr_adjoint_describe(0, 2, None, 0, ctypes.byref(nt), None, 0, ctypes.byref(nr),
+                                    None, 0, ctypes.byref(nl)) == _lib.GPR_EINVAL
+    assert lib.gpr_adjoint_describe(4, 0, None, 0, ctypes.byref(nt), None, 0, ctypes.byref(nr),
+                                    None, 0, ctypes.byref(nl)) == _lib.GPR_EINVAL
+    # too-small capacity: counts are still reported
+    assert lib.gpr_adjoint_describe(1, 2, None, 0, ctypes.byref(nt), None, 0, ctypes.byref(nr),
+                                    None, 0, ctypes.byref(nl)) == _lib.GPR_EINVAL
+    assert (nt.value, nr.value, nl.value) == (3, 3, 3)  # M = 1: the three POTRF-adjoint products
