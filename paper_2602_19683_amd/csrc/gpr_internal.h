@@ -122,8 +122,9 @@ hipError_t launch_tiled_to_dense(const TileMat& T, int64_t n, double* out, int64
 hipError_t launch_update_f64(const UpdateTask* d_tasks, int ntask, int m, hipStream_t s);
 hipError_t launch_trsm_f64(const TrsmTask* d_tasks, int ntask, int m, hipStream_t s);
 // POTRF of one diagonal tile, m / 32 cooperating workgroups ordered by
-// flags[0 .. m/32) (set to `epoch` when a row panel is done; epoch must differ
-// from every value the flags hold). *err is set if a wait hits its limit.
+// flags[0 .. 2 m/32) (set to `epoch` as parts of a row panel are done; epoch
+// must differ from every value the flags hold). *err is set if a wait hits
+// its limit.
 hipError_t launch_potrf_f64(double* A, int lda, int m, double* Tinv, int ldt, int* info,
                             int64_t col_base, unsigned* flags, unsigned epoch, int* err,
                             hipStream_t s);

@@ -7,13 +7,17 @@
 // column order q = 0 .. w:
 //     acc = K[w, q] - L[w, 0:32q] L[q, 0:32q]^T      (FP64 MFMA, LDS-staged)
 //     L[w, q] = acc Dinv_q^T                          (q < w)
-//     L[w, w] = chol(acc), Dinv_w = L[w, w]^{-1}      (q = w, one wave)
-// Block (w, q) needs row panel q to be complete (rows of L and Dinv_q): that
-// is signalled by workgroup q through flag[q] (release / acquire at device
-// scope, so it holds across XCDs). A workgroup only ever waits for
-// lower-numbered workgroups, which the hardware dispatches first, so every
-// wait ends; a spin limit turns a broken invariant into an error report
-// instead of a hang.
+//     L[w, w] = chol(K[w, w] - sum_q L[w, q] L[w, q]^T), Dinv_w = L[w, w]^{-1}
+// The diagonal block's sum is accumulated as each L[w, q] is formed, so no
+// long product sits between the last handoff and the 32 x 32 factorisation.
+// Workgroup q publishes two flags (release / acquire at device scope, so they
+// hold across XCDs): its off-diagonal blocks L[q, 0:q] are stored (before its
+// diagonal factorisation), and its diagonal block and Dinv_q are stored.
+// The long product for block (w, q) needs only the first, so it overlaps the
+// factorisation of panel q; only the 32 x 32 product with Dinv_q waits for
+// the second. A workgroup only ever waits for lower-numbered workgroups,
+// which the hardware dispatches first, so every wait ends; a spin limit
+// turns a broken invariant into an error report instead of a hang.
 //
 // TRTRI: block column c of Tinv = L^{-1} is X_c = Dinv_c and
 //     X_r = -Dinv_r sum_{s=c}^{r-1} L[r, s] X_s,   r > c,
@@ -178,18 +182,26 @@ __global__ __launch_bounds__(256) void k_potrf_f64(double* __restrict__ A, int l
     __shared__ double Si[NB][NB + 1];
     __shared__ double dv[NB];
     const int w = blockIdx.x;
+    const int P = m / NB;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int lr = lane & 15, lk = lane >> 4;
     const int qi = wave >> 1, qj = wave & 1;
     const int row0 = NB * w;
     double* Aw = A + (size_t)row0 * lda;  // row panel w
+    // flags[q]: off-diagonal blocks L[q, 0:q] stored; flags[P + q]: L[q, q]
+    // and its inverse stored (row panel q complete)
+    unsigned* off_done = flags;
+    unsigned* diag_done = flags + P;
 
-    for (int q = 0; q <= w; ++q) {
-        if (q < w) {
-            if (tid == 0 && !wait_flag(flags + q, epoch)) *err = 1;
-            __syncthreads();
-        }
+    // running sum of L[w, p] L[w, p]^T over the finished blocks p < q, this
+    // wave's 16 x 16 quadrant of the diagonal block
+    dbl4 dacc = {0.0, 0.0, 0.0, 0.0};
+    for (int q = 0; q < w; ++q) {
+        // acc = K[w, q] - L[w, 0:q] L[q, 0:q]^T needs the off-diagonal blocks of
+        // row panel q; the product with Dinv_q then needs its diagonal block
+        if (tid == 0 && !wait_flag(off_done + q, epoch)) *err = 1;
+        __syncthreads();
         dbl4 acc;
 #pragma unroll
         for (int v = 0; v < 4; ++v)
@@ -197,41 +209,56 @@ __global__ __launch_bounds__(256) void k_potrf_f64(double* __restrict__ A, int l
         acc = accum32<true>(Aw, lda, A + (size_t)NB * q * lda, lda, NB * q, acc, -1.0, As, Bs);
 #pragma unroll
         for (int v = 0; v < 4; ++v) Sacc[16 * qi + drow(lk, v)][16 * qj + lr] = acc[v];
+        if (tid == 0 && !wait_flag(diag_done + q, epoch)) *err = 1;
         __syncthreads();
-        if (q < w) {
-            // L[w, q] = acc Dinv_q^T; Dinv_q is the diagonal block q of Tinv
-            const double* dq = Tinv + (size_t)(NB * q + 16 * qj + lr) * ldt + NB * q + lk;
-            dbl4 o = {0.0, 0.0, 0.0, 0.0};
+        // L[w, q] = acc Dinv_q^T; Dinv_q is the diagonal block q of Tinv
+        const double* dq = Tinv + (size_t)(NB * q + 16 * qj + lr) * ldt + NB * q + lk;
+        dbl4 o = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int k = 0; k < NB; k += 4) o = mfma16(Sacc[16 * qi + lr][k + lk], dq[k], o);
+        for (int k = 0; k < NB; k += 4) o = mfma16(Sacc[16 * qi + lr][k + lk], dq[k], o);
+        __syncthreads();  // every read of Sacc done
 #pragma unroll
-            for (int v = 0; v < 4; ++v)
-                Aw[(size_t)(16 * qi + drow(lk, v)) * lda + NB * q + 16 * qj + lr] = o[v];
-            __syncthreads();  // Sacc reuse; L[w, q] visible to the workgroup
-        } else {
-            int bad = -1;
-            if (wave == 0) bad = factor_diag32(Sacc, Si, dv, lane);
-            __syncthreads();
-            for (int e = tid; e < NB * NB; e += 256) {
-                const int r = e / NB, c = e % NB;
-                Aw[(size_t)r * lda + row0 + c] = Sacc[r][c];
-                Tinv[(size_t)(row0 + r) * ldt + row0 + c] = Si[r][c];
-            }
-            // strict upper triangle of the tile in this row panel
-            const int rest = m - row0 - NB;
-            for (int e = tid; e < NB * rest; e += 256) {
-                const int r = e / rest, c = e % rest;
-                Aw[(size_t)r * lda + row0 + NB + c] = 0.0;
-            }
-            // every earlier panel is complete (flags acquired), so the first
-            // failure seen here in column order is the first overall
-            if (tid == 0 && bad >= 0 && info != nullptr && *info == 0)
-                *info = (int)(col_base + row0 + bad + 1);
-            __syncthreads();
-            if (tid == 0)
-                __hip_atomic_store(flags + w, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        for (int v = 0; v < 4; ++v) {
+            const int r = 16 * qi + drow(lk, v), c = 16 * qj + lr;
+            Aw[(size_t)r * lda + NB * q + c] = o[v];
+            Sacc[r][c] = o[v];
         }
+        __syncthreads();
+        // dacc += L[w, q] L[w, q]^T
+#pragma unroll
+        for (int k = 0; k < NB; k += 4)
+            dacc = mfma16(Sacc[16 * qi + lr][k + lk], Sacc[16 * qj + lr][k + lk], dacc);
     }
+    __syncthreads();  // Sacc reads done; L[w, 0:w] stored by every wave
+    // row panel w's off-diagonal blocks are final: published by the last wave,
+    // so that the release does not delay the factorisation in wave 0
+    if (tid == 192) __hip_atomic_store(off_done + w, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int r = 16 * qi + drow(lk, v), c = 16 * qj + lr;
+        Sacc[r][c] = Aw[(size_t)r * lda + row0 + c] - dacc[v];
+    }
+    __syncthreads();
+    int bad = -1;
+    if (wave == 0) bad = factor_diag32(Sacc, Si, dv, lane);
+    __syncthreads();
+    for (int e = tid; e < NB * NB; e += 256) {
+        const int r = e / NB, c = e % NB;
+        Aw[(size_t)r * lda + row0 + c] = Sacc[r][c];
+        Tinv[(size_t)(row0 + r) * ldt + row0 + c] = Si[r][c];
+    }
+    // strict upper triangle of the tile in this row panel
+    const int rest = m - row0 - NB;
+    for (int e = tid; e < NB * rest; e += 256) {
+        const int r = e / rest, c = e % rest;
+        Aw[(size_t)r * lda + row0 + NB + c] = 0.0;
+    }
+    // every earlier panel is complete (flags acquired), so the first failure
+    // seen here in column order is the first overall
+    if (tid == 0 && bad >= 0 && info != nullptr && *info == 0)
+        *info = (int)(col_base + row0 + bad + 1);
+    __syncthreads();
+    if (tid == 0) __hip_atomic_store(diag_done + w, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __global__ __launch_bounds__(256) void k_trtri_f64(TileMat K, double* __restrict__ Tall)
