@@ -1,0 +1,83 @@
+// k_accum.h -- the 32 x 32 block product used by the diagonal-tile kernels
+// (POTRF, the tile inverse, TRSM): a 256-thread workgroup accumulates
+//     acc += sign * sum_{k < K} A[i][k] B(k, j),   i, j < 32,
+// each wave holding one 16 x 16 quadrant (qi, qj) = (wave / 2, wave % 2) in the
+// FP64 MFMA 16x16x4 layout. A: 32 rows, row-major (lda). NT: B(k, j) =
+// B[j * ldb + k] (32 rows of B); otherwise B(k, j) = B[k * ldb + j]. K is a
+// multiple of KC. Chunks of KC columns go through LDS k-major (the 16 lanes
+// sharing a k read consecutive words), double-buffered. All 256 threads must
+// call it; As and Bs are LDS arrays [2][KC][32 + 4].
+#pragma once
+
+#include "k_common.h"
+
+namespace gpr {
+
+template <bool NT, int KC>
+__device__ inline dbl4 accum32(const double* __restrict__ A, int lda, const double* __restrict__ B,
+                               int ldb, int K, dbl4 acc, double sign, double (*As)[KC][36],
+                               double (*Bs)[KC][36])
+{
+    static_assert(KC % 16 == 0, "chunk must hold whole double2 loads");
+    constexpr int NL = KC / 16;       // double2 loads per thread per operand
+    constexpr int CPR = KC / 2;       // double2 per 32-row operand row (KC columns)
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int qi = wave >> 1, qj = wave & 1;
+    double2 ra[NL], rb[NL];
+    auto gload = [&](int k0) {
+#pragma unroll
+        for (int u = 0; u < NL; ++u) {
+            const int e = tid + 256 * u;
+            const int r = e / CPR, c = (e % CPR) * 2;  // row r (< 32), columns c, c + 1
+            ra[u] = *reinterpret_cast<const double2*>(A + (size_t)r * lda + k0 + c);
+            if (NT) {
+                rb[u] = *reinterpret_cast<const double2*>(B + (size_t)r * ldb + k0 + c);
+            } else {
+                const int kr = e >> 4, jc = (e & 15) * 2;  // k row (< KC), columns jc, jc + 1
+                rb[u] = *reinterpret_cast<const double2*>(B + (size_t)(k0 + kr) * ldb + jc);
+            }
+        }
+    };
+    auto swrite = [&](int buf) {
+#pragma unroll
+        for (int u = 0; u < NL; ++u) {
+            const int e = tid + 256 * u;
+            const int r = e / CPR, c = (e % CPR) * 2;
+            As[buf][c][r] = sign * ra[u].x;
+            As[buf][c + 1][r] = sign * ra[u].y;
+            if (NT) {
+                Bs[buf][c][r] = rb[u].x;
+                Bs[buf][c + 1][r] = rb[u].y;
+            } else {
+                const int kr = e >> 4, jc = (e & 15) * 2;
+                Bs[buf][kr][jc] = rb[u].x;
+                Bs[buf][kr][jc + 1] = rb[u].y;
+            }
+        }
+    };
+    const int nk = K / KC;
+    if (nk == 0) return acc;
+    __syncthreads();  // LDS buffers free
+    gload(0);
+    swrite(0);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        const int cur = kt & 1;
+        if (kt + 1 < nk) gload((kt + 1) * KC);
+        dbl4 acc2 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kk = 0; kk < KC; kk += 8) {
+            acc = mfma16(As[cur][kk + lk][16 * qi + lr], Bs[cur][kk + lk][16 * qj + lr], acc);
+            acc2 = mfma16(As[cur][kk + 4 + lk][16 * qi + lr], Bs[cur][kk + 4 + lk][16 * qj + lr],
+                          acc2);
+        }
+        acc += acc2;
+        if (kt + 1 < nk) swrite(cur ^ 1);
+        __syncthreads();
+    }
+    return acc;
+}
+
+}  // namespace gpr

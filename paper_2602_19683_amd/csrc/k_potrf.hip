@@ -25,6 +25,7 @@
 // diagonal tiles at once (it is off the critical path: TRSM uses only the
 // 32 x 32 block inverses).
 #include "gpr_internal.h"
+#include "k_accum.h"
 #include "k_common.h"
 
 namespace gpr {
@@ -94,72 +95,6 @@ __device__ static int factor_diag32(double (*S)[NB + 1], double (*Si)[NB + 1], d
     return bad;
 }
 
-// acc += sign * sum_{k < K} A[i][k] * B(k, j) for this wave's 16 x 16 quadrant
-// (qi, qj) of a 32 x 32 block; A is 32 rows row-major (lda). NT: B(k, j) =
-// B[j * ldb + k] (32 rows of B); otherwise B(k, j) = B[k * ldb + j]. K is a
-// multiple of KC. Chunks of KC columns go through LDS (k-major, so the 16
-// lanes sharing a k read consecutive words), double-buffered. All 256
-// threads of the workgroup must call it.
-template <bool NT>
-__device__ static dbl4 accum32(const double* __restrict__ A, int lda, const double* __restrict__ B,
-                               int ldb, int K, dbl4 acc, double sign, double (*As)[KC][SP],
-                               double (*Bs)[KC][SP])
-{
-    const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
-    const int lr = lane & 15, lk = lane >> 4;
-    const int qi = wave >> 1, qj = wave & 1;
-    // 32 x KC doubles per operand = 512 double2 -> 2 per thread
-    double2 ra[2], rb[2];
-    auto gload = [&](int k0) {
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            const int e = tid + 256 * u;
-            const int r = e >> 4, c = (e & 15) * 2;  // row r, columns c and c + 1
-            ra[u] = *reinterpret_cast<const double2*>(A + (size_t)r * lda + k0 + c);
-            if (NT) rb[u] = *reinterpret_cast<const double2*>(B + (size_t)r * ldb + k0 + c);
-            else rb[u] = *reinterpret_cast<const double2*>(B + (size_t)(k0 + r) * ldb + c);
-        }
-    };
-    auto swrite = [&](int buf) {
-#pragma unroll
-        for (int u = 0; u < 2; ++u) {
-            const int e = tid + 256 * u;
-            const int r = e >> 4, c = (e & 15) * 2;
-            As[buf][c][r] = sign * ra[u].x;
-            As[buf][c + 1][r] = sign * ra[u].y;
-            if (NT) {
-                Bs[buf][c][r] = rb[u].x;
-                Bs[buf][c + 1][r] = rb[u].y;
-            } else {
-                Bs[buf][r][c] = rb[u].x;
-                Bs[buf][r][c + 1] = rb[u].y;
-            }
-        }
-    };
-    const int nk = K / KC;
-    if (nk == 0) return acc;
-    __syncthreads();  // LDS buffers free
-    gload(0);
-    swrite(0);
-    __syncthreads();
-    for (int kt = 0; kt < nk; ++kt) {
-        const int cur = kt & 1;
-        if (kt + 1 < nk) gload((kt + 1) * KC);
-        dbl4 acc2 = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int kk = 0; kk < KC; kk += 8) {
-            acc = mfma16(As[cur][kk + lk][16 * qi + lr], Bs[cur][kk + lk][16 * qj + lr], acc);
-            acc2 = mfma16(As[cur][kk + 4 + lk][16 * qi + lr], Bs[cur][kk + 4 + lk][16 * qj + lr],
-                          acc2);
-        }
-        acc += acc2;
-        if (kt + 1 < nk) swrite(cur ^ 1);
-        __syncthreads();
-    }
-    return acc;
-}
-
 __device__ static bool wait_flag(const unsigned* f, unsigned epoch)
 {
     unsigned it = 0;
@@ -206,7 +141,7 @@ __global__ __launch_bounds__(256) void k_potrf_f64(double* __restrict__ A, int l
 #pragma unroll
         for (int v = 0; v < 4; ++v)
             acc[v] = Aw[(size_t)(16 * qi + drow(lk, v)) * lda + NB * q + 16 * qj + lr];
-        acc = accum32<true>(Aw, lda, A + (size_t)NB * q * lda, lda, NB * q, acc, -1.0, As, Bs);
+        acc = accum32<true, KC>(Aw, lda, A + (size_t)NB * q * lda, lda, NB * q, acc, -1.0, As, Bs);
 #pragma unroll
         for (int v = 0; v < 4; ++v) Sacc[16 * qi + drow(lk, v)][16 * qj + lr] = acc[v];
         if (tid == 0 && !wait_flag(diag_done + q, epoch)) *err = 1;
@@ -285,7 +220,7 @@ __global__ __launch_bounds__(256) void k_trtri_f64(TileMat K, double* __restrict
     for (int r = c + 1; r < P; ++r) {
         // acc = sum_{s=c}^{r-1} L[r, s] X_s  (X_s = Tinv block (s, c))
         dbl4 acc = {0.0, 0.0, 0.0, 0.0};
-        acc = accum32<false>(L + (size_t)r * NB * lda + c * NB, lda,
+        acc = accum32<false, KC>(L + (size_t)r * NB * lda + c * NB, lda,
                              Tinv + (size_t)c * NB * ldt + c * NB, ldt, NB * (r - c), acc, 1.0,
                              As, Bs);
 #pragma unroll
