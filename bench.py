@@ -26,7 +26,7 @@ FP64_PEAK_TFLOPS = 78.6     # MI355X dense FP64 (vector = matrix)
 # HBM bytes per dispatch of the tile-update kernel from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs scaled by a 1 GiB copy (profiles/fp64_c3_hbm_traffic.md); only
 # valid for the kernel source they were taken on.
-UPDATE_TRAFFIC = {"k_update_sha256_16": "5f340a6b621493c1", "bytes_per_launch": 681831762}
+UPDATE_TRAFFIC = {"k_update_sha256_16": "13f50f13ba42832e", "bytes_per_launch": 738656651}
 
 
 def update_traffic():
@@ -128,6 +128,42 @@ def mixed_runs(ctx, K, step, mean64, cov64, ms64, flops, args, log):
     return out
 
 
+def nlml_run(ctx, args, log):
+    """The gradient workload: NLML and its gradient in (l, v, sigma^2) at
+    n = 8192, D = 8, tile 256, from (0.3, 2.0, 0.5): time per evaluation
+    (forward factorisation + reverse sweep + reduction) and per NLML-only
+    evaluation, with GFLOP/s over n^3/3 (forward) + 2 n^3/3 (adjoint)."""
+    import torch
+    from gpr_inputs import nfir
+    n, tile, h = 8192, 256, (0.3, 2.0, 0.5)
+    X, y = nfir(n)
+    Xd, yd = torch.from_numpy(X).to("cuda:0"), torch.from_numpy(y).to("cuda:0")
+    out = {}
+    for grad in (True, False):
+        ctx.nlml_grad(Xd, yd, h, tile, grad=grad)
+        ctx.sync()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(args.steps):
+            nl, g, _ = ctx.nlml_grad(Xd, yd, h, tile, grad=grad)
+        e1.record()
+        torch.cuda.synchronize()
+        ctx.sync()
+        ms = e0.elapsed_time(e1) / args.steps
+        if grad:
+            out["ms_nlml_and_grad"] = round(ms, 4)
+            out["gflops_nlml_and_grad"] = round(n ** 3 / ms * 1e-6, 2)  # (1/3 + 2/3) n^3
+            out["nlml"] = float(nl.cpu()[0])
+            out["grad"] = [float(v) for v in g.cpu()]
+        else:
+            out["ms_nlml_only"] = round(ms, 4)
+    out["config"] = f"n={n}, D=8, tile {tile}, (l, v, sigma^2) = {h}, fp64"
+    log(f"nlml: {out}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -144,6 +180,8 @@ def main():
     ap.add_argument("--streams", type=int, default=3,
                     help="1 = no overlap between launches (isolated kernel timings)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-nlml", action="store_true",
+                    help="skip the NLML-gradient timing (n = 8192, tile 256) after the line")
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run one device-to-device copy of MIB MiB (for HBM counter scaling)")
@@ -230,6 +268,9 @@ def main():
     mixed = None
     if not args.no_mixed and args.precision == "fp64":
         mixed = mixed_runs(ctx, K, step, mean, cov, ms, flops, args, log)
+    nlml = None
+    if not args.no_nlml:
+        nlml = nlml_run(ctx, args, log)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(h)
@@ -251,6 +292,7 @@ def main():
         "cpu_baseline": cpu,
         "errors": errors,
         "mixed": mixed,
+        "nlml_grad": nlml,
         "phases_ms_per_step": {k: round(v[1] / args.steps, 4) for k, v in prof.items()},
     }
     print(json.dumps(out), flush=True)

@@ -8,19 +8,22 @@
 // registers (FP64 MFMA 16x16x4), so each output block is written once by one
 // workgroup: deterministic, no atomics. Operands are staged through LDS in
 // k-major slices of 16, double buffered across the (term, slice) sequence.
+// The 128 x 128 block uses 8 waves of 64 x 32 (four waves per SIMD at two
+// workgroups per compute unit, without register spills).
 #include "gpr_internal.h"
 #include "k_common.h"
 
 namespace gpr {
 
-template <int BM>
-__global__ __launch_bounds__(256, 2) void k_tgemm_f64(const TGemmTask* __restrict__ tasks,
-                                                      const TGemmTerm* __restrict__ terms, int m)
+template <int BM, int WR, int WC>
+__global__ __launch_bounds__(WR * WC * 64, WR * WC / 2) void k_tgemm_f64(
+    const TGemmTask* __restrict__ tasks, const TGemmTerm* __restrict__ terms, int m)
 {
+    constexpr int NT = WR * WC * 64;
     constexpr int KB = 16;
-    constexpr int WM = BM / 2, TM = WM / 16;
+    constexpr int TR = BM / WR / 16, TC = BM / WC / 16;
     constexpr int LD = BM + 4;
-    constexpr int NLD = BM * KB / 2 / 256;
+    constexpr int NLD = BM * KB / 2 / NT;
     __shared__ double As[2][KB][LD];
     __shared__ double Bs[2][KB][LD];
 
@@ -33,14 +36,14 @@ __global__ __launch_bounds__(256, 2) void k_tgemm_f64(const TGemmTask* __restric
     if (tk.epi == TG_EPI_SYM && bj > bi) return;  // mirrored from block (bj, bi)
     const int i0 = bi * BM, j0 = bj * BM;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wr = (wave >> 1) * WM, wc = (wave & 1) * WM;
+    const int wr = (wave / WC) * (BM / WR), wc = (wave % WC) * (BM / WC);
     const int lr = lane & 15, lk = lane >> 4;
 
-    dbl4 acc[TM][TM];
+    dbl4 acc[TR][TC];
 #pragma unroll
-    for (int i = 0; i < TM; ++i)
+    for (int i = 0; i < TR; ++i)
 #pragma unroll
-        for (int j = 0; j < TM; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+        for (int j = 0; j < TC; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
 
     const int nks = m / KB;
     const int total = tk.nterm * nks;
@@ -58,7 +61,7 @@ __global__ __launch_bounds__(256, 2) void k_tgemm_f64(const TGemmTask* __restric
         flags = tm.flags;
 #pragma unroll
         for (int u = 0; u < NLD; ++u) {
-            const int e = tid + 256 * u;
+            const int e = tid + NT * u;
             int srow, scol;
             if (!(tm.flags & TG_TRANS_A)) {
                 const int r = e / (KB / 2), kk = (e % (KB / 2)) * 2;
@@ -104,7 +107,7 @@ __global__ __launch_bounds__(256, 2) void k_tgemm_f64(const TGemmTask* __restric
     auto swrite = [&](int buf) {
 #pragma unroll
         for (int u = 0; u < NLD; ++u) {
-            const int e = tid + 256 * u;
+            const int e = tid + NT * u;
             if (!(flags & TG_TRANS_A)) {
                 const int r = e / (KB / 2), kk = (e % (KB / 2)) * 2;
                 As[buf][kk][r] = alpha * ra[u].x;
@@ -135,15 +138,15 @@ __global__ __launch_bounds__(256, 2) void k_tgemm_f64(const TGemmTask* __restric
             if (s + 1 < total) gload(s + 1);
 #pragma unroll
             for (int kk = 0; kk < KB; kk += 4) {
-                double a[TM], b[TM];
+                double a[TR], b[TC];
 #pragma unroll
-                for (int i = 0; i < TM; ++i) a[i] = As[cur][kk + lk][wr + 16 * i + lr];
+                for (int i = 0; i < TR; ++i) a[i] = As[cur][kk + lk][wr + 16 * i + lr];
 #pragma unroll
-                for (int j = 0; j < TM; ++j) b[j] = Bs[cur][kk + lk][wc + 16 * j + lr];
+                for (int j = 0; j < TC; ++j) b[j] = Bs[cur][kk + lk][wc + 16 * j + lr];
 #pragma unroll
-                for (int i = 0; i < TM; ++i)
+                for (int i = 0; i < TR; ++i)
 #pragma unroll
-                    for (int j = 0; j < TM; ++j) acc[i][j] = mfma16(a[i], b[j], acc[i][j]);
+                    for (int j = 0; j < TC; ++j) acc[i][j] = mfma16(a[i], b[j], acc[i][j]);
             }
             if (s + 1 < total) swrite(cur ^ 1);
             __syncthreads();
@@ -151,9 +154,9 @@ __global__ __launch_bounds__(256, 2) void k_tgemm_f64(const TGemmTask* __restric
     }
 
 #pragma unroll
-    for (int i = 0; i < TM; ++i)
+    for (int i = 0; i < TR; ++i)
 #pragma unroll
-        for (int j = 0; j < TM; ++j)
+        for (int j = 0; j < TC; ++j)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int gi = i0 + wr + 16 * i + drow(lk, v);
@@ -188,11 +191,11 @@ hipError_t launch_tgemm_f64(const TGemmTask* d_tasks, int ntask, const TGemmTerm
     const int nb = m / bm;
     const dim3 grid(ntask * nb * nb);
     if (bm == 128)
-        hipLaunchKernelGGL(k_tgemm_f64<128>, grid, dim3(256), 0, s, d_tasks, d_terms, m);
+        hipLaunchKernelGGL((k_tgemm_f64<128, 2, 4>), grid, dim3(512), 0, s, d_tasks, d_terms, m);
     else if (bm == 64)
-        hipLaunchKernelGGL(k_tgemm_f64<64>, grid, dim3(256), 0, s, d_tasks, d_terms, m);
+        hipLaunchKernelGGL((k_tgemm_f64<64, 2, 2>), grid, dim3(256), 0, s, d_tasks, d_terms, m);
     else
-        hipLaunchKernelGGL(k_tgemm_f64<32>, grid, dim3(256), 0, s, d_tasks, d_terms, m);
+        hipLaunchKernelGGL((k_tgemm_f64<32, 2, 2>), grid, dim3(256), 0, s, d_tasks, d_terms, m);
     return hipGetLastError();
 }
 

@@ -5,9 +5,9 @@
 // accumulator is subtracted from the FP64 tile. POTRF, TRSM and every solve
 // stay FP64.
 //
-// Same blocking as the FP64 kernel: one workgroup per 128 x 128 (or 64 x 64)
-// block of a tile, 4 waves in 2 x 2, XCD-aware block order, LDS double
-// buffering. FP32: v_mfma_f32_16x16x4_f32, k-slices of 16, LDS k-major.
+// Same blocking as the FP64 kernel: one workgroup per 128 x 128 block of a
+// tile with 16 waves of 32 x 32 (a 64 x 64 block: 4 waves), XCD-aware block
+// order, LDS double buffering. FP32: v_mfma_f32_16x16x4_f32, k-slices of 16, LDS k-major.
 // BF16: v_mfma_f32_16x16x32_bf16, k-slices of 32, LDS row-major (each lane
 // reads 8 consecutive bf16 of one row). Both FP32-accumulator layouts put
 // element v of lane l at row 4 (l / 16) + v, column l % 16.
@@ -22,13 +22,15 @@ typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 
 __device__ constexpr int frow(int lk, int v) { return 4 * lk + v; }
 
-template <int BM>
-__global__ __launch_bounds__(256, 2) void k_update_f32(const UpdateTask* __restrict__ tasks, int m)
+template <int BM, int WR, int WC>
+__global__ __launch_bounds__(WR * WC * 64, WR * WC / 2) void k_update_f32(
+    const UpdateTask* __restrict__ tasks, int m)
 {
+    constexpr int NT = WR * WC * 64;
     constexpr int KB = 16;
-    constexpr int WM = BM / 2, TM = WM / 16;
+    constexpr int TR = BM / WR / 16, TC = BM / WC / 16;
     constexpr int LD = BM + 4;
-    constexpr int NLD = BM * KB / 2 / 256;
+    constexpr int NLD = BM * KB / 2 / NT;
     __shared__ float As[2][KB][LD];
     __shared__ float Bs[2][KB][LD];
 
@@ -44,14 +46,14 @@ __global__ __launch_bounds__(256, 2) void k_update_f32(const UpdateTask* __restr
     double* __restrict__ C = tk.C + (size_t)bi * BM * tk.ldc + (size_t)bj * BM;
     const int lda = tk.lda, ldb = tk.ldb, ldc = tk.ldc;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wr = (wave >> 1) * WM, wc = (wave & 1) * WM;
+    const int wr = (wave / WC) * (BM / WR), wc = (wave % WC) * (BM / WC);
     const int lr = lane & 15, lk = lane >> 4;
 
     double2 ra[NLD], rb[NLD];
     auto gload = [&](int k0) {
 #pragma unroll
         for (int q = 0; q < NLD; ++q) {
-            const int e = tid + 256 * q;
+            const int e = tid + NT * q;
             const int r = e / (KB / 2), kk = (e % (KB / 2)) * 2;
             ra[q] = *reinterpret_cast<const double2*>(A + (size_t)r * lda + k0 + kk);
             rb[q] = *reinterpret_cast<const double2*>(B + (size_t)r * ldb + k0 + kk);
@@ -60,7 +62,7 @@ __global__ __launch_bounds__(256, 2) void k_update_f32(const UpdateTask* __restr
     auto swrite = [&](int buf) {
 #pragma unroll
         for (int q = 0; q < NLD; ++q) {
-            const int e = tid + 256 * q;
+            const int e = tid + NT * q;
             const int r = e / (KB / 2), kk = (e % (KB / 2)) * 2;
             As[buf][kk][r] = (float)ra[q].x;
             As[buf][kk + 1][r] = (float)ra[q].y;
@@ -68,11 +70,11 @@ __global__ __launch_bounds__(256, 2) void k_update_f32(const UpdateTask* __restr
             Bs[buf][kk + 1][r] = (float)rb[q].y;
         }
     };
-    flt4 acc[TM][TM];
+    flt4 acc[TR][TC];
 #pragma unroll
-    for (int i = 0; i < TM; ++i)
+    for (int i = 0; i < TR; ++i)
 #pragma unroll
-        for (int j = 0; j < TM; ++j) acc[i][j] = flt4{0.f, 0.f, 0.f, 0.f};
+        for (int j = 0; j < TC; ++j) acc[i][j] = flt4{0.f, 0.f, 0.f, 0.f};
 
     gload(0);
     swrite(0);
@@ -83,24 +85,24 @@ __global__ __launch_bounds__(256, 2) void k_update_f32(const UpdateTask* __restr
         if (kt + 1 < nk) gload((kt + 1) * KB);
 #pragma unroll
         for (int kk = 0; kk < KB; kk += 4) {
-            float a[TM], b[TM];
+            float a[TR], b[TC];
 #pragma unroll
-            for (int i = 0; i < TM; ++i) a[i] = As[cur][kk + lk][wr + 16 * i + lr];
+            for (int i = 0; i < TR; ++i) a[i] = As[cur][kk + lk][wr + 16 * i + lr];
 #pragma unroll
-            for (int j = 0; j < TM; ++j) b[j] = Bs[cur][kk + lk][wc + 16 * j + lr];
+            for (int j = 0; j < TC; ++j) b[j] = Bs[cur][kk + lk][wc + 16 * j + lr];
 #pragma unroll
-            for (int i = 0; i < TM; ++i)
+            for (int i = 0; i < TR; ++i)
 #pragma unroll
-                for (int j = 0; j < TM; ++j)
+                for (int j = 0; j < TC; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
         }
         if (kt + 1 < nk) swrite(cur ^ 1);
         __syncthreads();
     }
 #pragma unroll
-    for (int i = 0; i < TM; ++i)
+    for (int i = 0; i < TR; ++i)
 #pragma unroll
-        for (int j = 0; j < TM; ++j)
+        for (int j = 0; j < TC; ++j)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int row = wr + 16 * i + frow(lk, v);
@@ -109,13 +111,15 @@ __global__ __launch_bounds__(256, 2) void k_update_f32(const UpdateTask* __restr
             }
 }
 
-template <int BM>
-__global__ __launch_bounds__(256, 2) void k_update_bf16(const UpdateTask* __restrict__ tasks, int m)
+template <int BM, int WR, int WC>
+__global__ __launch_bounds__(WR * WC * 64, WR * WC / 2) void k_update_bf16(
+    const UpdateTask* __restrict__ tasks, int m)
 {
+    constexpr int NT = WR * WC * 64;
     constexpr int KB = 32;
-    constexpr int WM = BM / 2, TM = WM / 16;
+    constexpr int TR = BM / WR / 16, TC = BM / WC / 16;
     constexpr int LD = KB + 8;                      // bf16 per LDS row (padded)
-    constexpr int NLD = BM * KB / 2 / 256;          // double2 loads per thread per operand
+    constexpr int NLD = BM * KB / 2 / NT;           // double2 loads per thread per operand
     __shared__ __bf16 As[2][BM][LD];
     __shared__ __bf16 Bs[2][BM][LD];
 
@@ -131,14 +135,14 @@ __global__ __launch_bounds__(256, 2) void k_update_bf16(const UpdateTask* __rest
     double* __restrict__ C = tk.C + (size_t)bi * BM * tk.ldc + (size_t)bj * BM;
     const int lda = tk.lda, ldb = tk.ldb, ldc = tk.ldc;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wr = (wave >> 1) * WM, wc = (wave & 1) * WM;
+    const int wr = (wave / WC) * (BM / WR), wc = (wave % WC) * (BM / WC);
     const int lr = lane & 15, lk = lane >> 4;
 
     double2 ra[NLD], rb[NLD];
     auto gload = [&](int k0) {
 #pragma unroll
         for (int q = 0; q < NLD; ++q) {
-            const int e = tid + 256 * q;
+            const int e = tid + NT * q;
             const int r = e / (KB / 2), kk = (e % (KB / 2)) * 2;
             ra[q] = *reinterpret_cast<const double2*>(A + (size_t)r * lda + k0 + kk);
             rb[q] = *reinterpret_cast<const double2*>(B + (size_t)r * ldb + k0 + kk);
@@ -147,7 +151,7 @@ __global__ __launch_bounds__(256, 2) void k_update_bf16(const UpdateTask* __rest
     auto swrite = [&](int buf) {
 #pragma unroll
         for (int q = 0; q < NLD; ++q) {
-            const int e = tid + 256 * q;
+            const int e = tid + NT * q;
             const int r = e / (KB / 2), kk = (e % (KB / 2)) * 2;
             bf16x2 pa, pb;
             pa[0] = (__bf16)(float)ra[q].x;
@@ -158,11 +162,11 @@ __global__ __launch_bounds__(256, 2) void k_update_bf16(const UpdateTask* __rest
             *reinterpret_cast<bf16x2*>(&Bs[buf][r][kk]) = pb;
         }
     };
-    flt4 acc[TM][TM];
+    flt4 acc[TR][TC];
 #pragma unroll
-    for (int i = 0; i < TM; ++i)
+    for (int i = 0; i < TR; ++i)
 #pragma unroll
-        for (int j = 0; j < TM; ++j) acc[i][j] = flt4{0.f, 0.f, 0.f, 0.f};
+        for (int j = 0; j < TC; ++j) acc[i][j] = flt4{0.f, 0.f, 0.f, 0.f};
 
     gload(0);
     swrite(0);
@@ -171,25 +175,25 @@ __global__ __launch_bounds__(256, 2) void k_update_bf16(const UpdateTask* __rest
     for (int kt = 0; kt < nk; ++kt) {
         const int cur = kt & 1;
         if (kt + 1 < nk) gload((kt + 1) * KB);
-        bf16x8 a[TM], b[TM];
+        bf16x8 a[TR], b[TC];
 #pragma unroll
-        for (int i = 0; i < TM; ++i)
+        for (int i = 0; i < TR; ++i)
             a[i] = *reinterpret_cast<const bf16x8*>(&As[cur][wr + 16 * i + lr][8 * lk]);
 #pragma unroll
-        for (int j = 0; j < TM; ++j)
+        for (int j = 0; j < TC; ++j)
             b[j] = *reinterpret_cast<const bf16x8*>(&Bs[cur][wc + 16 * j + lr][8 * lk]);
 #pragma unroll
-        for (int i = 0; i < TM; ++i)
+        for (int i = 0; i < TR; ++i)
 #pragma unroll
-            for (int j = 0; j < TM; ++j)
+            for (int j = 0; j < TC; ++j)
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
         if (kt + 1 < nk) swrite(cur ^ 1);
         __syncthreads();
     }
 #pragma unroll
-    for (int i = 0; i < TM; ++i)
+    for (int i = 0; i < TR; ++i)
 #pragma unroll
-        for (int j = 0; j < TM; ++j)
+        for (int j = 0; j < TC; ++j)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int row = wr + 16 * i + frow(lk, v);
@@ -207,11 +211,11 @@ hipError_t launch_update_mixed(const UpdateTask* d_tasks, int ntask, int m, int 
     const int nb = m / BM;
     const dim3 grid(ntask * nb * nb);
     if (prec == GPR_MIXED_FP32) {
-        if (big) hipLaunchKernelGGL(k_update_f32<128>, grid, dim3(256), 0, s, d_tasks, m);
-        else hipLaunchKernelGGL(k_update_f32<64>, grid, dim3(256), 0, s, d_tasks, m);
+        if (big) hipLaunchKernelGGL((k_update_f32<128, 4, 4>), grid, dim3(1024), 0, s, d_tasks, m);
+        else hipLaunchKernelGGL((k_update_f32<64, 2, 2>), grid, dim3(256), 0, s, d_tasks, m);
     } else {
-        if (big) hipLaunchKernelGGL(k_update_bf16<128>, grid, dim3(256), 0, s, d_tasks, m);
-        else hipLaunchKernelGGL(k_update_bf16<64>, grid, dim3(256), 0, s, d_tasks, m);
+        if (big) hipLaunchKernelGGL((k_update_bf16<128, 4, 4>), grid, dim3(1024), 0, s, d_tasks, m);
+        else hipLaunchKernelGGL((k_update_bf16<64, 2, 2>), grid, dim3(256), 0, s, d_tasks, m);
     }
     return hipGetLastError();
 }

@@ -170,7 +170,7 @@ def test_adam_fit_through_autograd_matches_oracle(ctx):
         theta = torch.exp(z)
         f = NLML.apply(theta, Xd, yd, ctx, tile)
         f.backward()
-        gpu_trace.append((theta.detach().numpy().copy(), float(f)))
+        gpu_trace.append((theta.detach().numpy().copy(), float(f.detach())))
         opt.step()
     ref_trace, ref_final = oracle.adam_fit(X, y, C4_HYPER, steps=20)
     worst = 0.0
