@@ -736,7 +736,9 @@ int predict_impl(gpr_ctx* ctx, gpr_tiled* L, const double* X, const double* y, i
     const size_t vec_bytes = 5 * npad * sizeof(double) + 256;
     const size_t v_bytes = cov ? (size_t)Mhat * M * m * m * sizeof(double) : 0;
     const size_t s_bytes = cov ? (size_t)Mhat * (Mhat + 1) / 2 * m * m * sizeof(double) : 0;
-    int rc = ensure_device_bytes(&ctx->d_ws, &ctx->ws_cap, vec_bytes + v_bytes + s_bytes);
+    const size_t mv_bytes = (size_t)matvec_chunks(n_test, n) * n_test * sizeof(double);
+    int rc = ensure_device_bytes(&ctx->d_ws, &ctx->ws_cap,
+                                 vec_bytes + v_bytes + s_bytes + mv_bytes);
     if (rc) return rc;
     if (fused && !L->tinv) {
         if (hipMalloc(reinterpret_cast<void**>(&L->tinv), (size_t)M * m * m * sizeof(double)) !=
@@ -752,6 +754,7 @@ int predict_impl(gpr_ctx* ctx, gpr_tiled* L, const double* X, const double* y, i
     double* scal = acc + npad;      // small scalars (norms)
     double* Vb = scal + npad;
     double* Sb = reinterpret_cast<double*>(reinterpret_cast<char*>(Vb) + v_bytes);
+    double* mvw = reinterpret_cast<double*>(reinterpret_cast<char*>(Sb) + s_bytes);
     const int fprec = fused ? prec : L->prec;
 
     DescBuffer db;
@@ -848,7 +851,8 @@ int predict_impl(gpr_ctx* ctx, gpr_tiled* L, const double* X, const double* y, i
     {
         ProfScope ps(ctx, s, PK_MATVEC, 2.0 * (double)n_test * (double)n, 0.0);
         HIP_TRY(launch_kernel_matvec(Xs, n_test, X, n, D, h.lengthscale, h.vertical_variance,
-                                     h.noise_variance, false, alpha_used, nullptr, mean, s));
+                                     h.noise_variance, false, alpha_used, nullptr, mean, mvw,
+                                     s));
     }
     if (cov) {
         ProfScope ps(ctx, s, PK_EXPORT, 0.0, (double)n_test * n_test * sizeof(double));

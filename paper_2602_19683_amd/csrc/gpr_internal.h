@@ -136,10 +136,12 @@ hipError_t launch_gemv_f64(const GemvTask* d_tasks, int ntask, int m, hipStream_
 
 // out_i = base_i - k(A_i, B) x  (subtract) or out_i = k(A_i, B) x  (base == nullptr),
 // where k(A_i, B) x = sum_j k(a_i, b_j) x_j + (noise ? s2 x_i : 0) over j < nb.
+// work: device scratch of matvec_chunks(na, nb) * na doubles.
+int matvec_chunks(int64_t na, int64_t nb);
 hipError_t launch_kernel_matvec(const double* A, int64_t na, const double* B, int64_t nb,
                                 int D, double l, double v, double s2, bool noise,
                                 const double* x, const double* base, double* out,
-                                hipStream_t s);
+                                double* work, hipStream_t s);
 
 // Mixed-precision tile updates (prec GPR_MIXED_FP32 or GPR_MIXED_BF16); m % 64 == 0.
 hipError_t launch_update_mixed(const UpdateTask* d_tasks, int ntask, int m, int prec,

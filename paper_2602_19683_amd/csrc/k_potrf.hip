@@ -37,61 +37,127 @@ constexpr int SP = NB + 4;   // padded LDS row
 constexpr unsigned SPIN_LIMIT = 1u << 22;
 }  // namespace
 
-// Unblocked Cholesky of the 32 x 32 block in S (lower triangle read), by one
-// wave; lane i < 32 owns row i in registers and the entries of column j are
-// fetched from their owners with readlane (right-looking). One reciprocal per
-// pivot scales the column. The inverse is formed column per lane by forward
-// substitution, multiplying by the stored pivot reciprocals, with four
-// independent partial sums per entry. On return S holds L (zeros above the
-// diagonal) and Si holds L^{-1} (zeros above). Returns the first failing
-// local column or -1. dv: 32 doubles of LDS scratch.
-__device__ static int factor_diag32(double (*S)[NB + 1], double (*Si)[NB + 1], double* dv,
-                                    int lane)
+// 1 / sqrt(d) to about one ulp: the hardware estimate and two Newton steps
+// y <- y (3/2 - d y^2 / 2). A pivot d <= 0 gives NaN or infinity, and the
+// caller reports it.
+__device__ inline double rsqrt_refined(double d)
 {
-    const int i = lane & 31;
-    double a[NB];
+    double y = __builtin_amdgcn_rsq(d);
+    const double h = 0.5 * d;
+    y = y * fma(-h * y, y, 1.5);
+    y = y * fma(-h * y, y, 1.5);
+    return y;
+}
+
+// Cholesky factor and inverse of the 16 x 16 block S[r0.., r0..] (lower
+// triangle read), by one wave: lane i < 16 owns row i in registers and the
+// entries of column j come from their owners by readlane (right-looking); one
+// reciprocal square root per pivot. The inverse is formed one column per lane
+// by forward substitution with the stored pivot reciprocals. On return the
+// block of S holds L (zeros above the diagonal) and the block of Si holds
+// L^{-1}. Returns the first failing local column or -1.
+__device__ static int chol_inv16(double (*S)[NB + 1], double (*Si)[NB + 1], int r0, double* dv,
+                                 int lane)
+{
+    const int i = lane & 15;
+    double a[16];
 #pragma unroll
-    for (int k = 0; k < NB; ++k) a[k] = S[i][k];
+    for (int k = 0; k < 16; ++k) a[k] = S[r0 + i][r0 + k];
     int bad = -1;
 #pragma unroll
-    for (int j = 0; j < NB; ++j) {
+    for (int j = 0; j < 16; ++j) {
         const double d = lane_bcast(a[j], j);
         if (!(d > 0.0) && bad < 0) bad = j;
-        const double ljj = sqrt(d);
-        const double inv = 1.0 / ljj;
+        const double inv = rsqrt_refined(d);
+        const double ljj = d * inv;
         a[j] = (i == j) ? ljj : (i > j ? a[j] * inv : 0.0);
         if (lane == 0) dv[j] = inv;
 #pragma unroll
-        for (int k = j + 1; k < NB; ++k) {
+        for (int k = j + 1; k < 16; ++k) {
             const double lkj = lane_bcast(a[j], k);
             if (i >= k) a[k] -= a[j] * lkj;
         }
     }
     wave_lds_sync();
-    if (lane < 32) {
+    if (lane < 16) {
 #pragma unroll
-        for (int k = 0; k < NB; ++k) S[i][k] = (k <= i) ? a[k] : 0.0;
+        for (int k = 0; k < 16; ++k) S[r0 + i][r0 + k] = (k <= i) ? a[k] : 0.0;
     }
     wave_lds_sync();
-    // column c = lane of L^{-1}: forward substitution of L x = e_c
-    double x[NB];
+    double x[16];
 #pragma unroll
-    for (int r = 0; r < NB; ++r) {
-        double s0 = (r == i) ? 1.0 : 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    for (int r = 0; r < 16; ++r) {
+        double s0 = (r == i) ? 1.0 : 0.0, s1 = 0.0;
 #pragma unroll
         for (int k = 0; k < r; ++k) {
-            const double t = S[r][k] * x[k];
-            if ((k & 3) == 0) s0 -= t;
-            else if ((k & 3) == 1) s1 -= t;
-            else if ((k & 3) == 2) s2 -= t;
-            else s3 -= t;
+            const double t = S[r0 + r][r0 + k] * x[k];
+            if (k & 1) s1 -= t;
+            else s0 -= t;
         }
-        x[r] = ((s0 + s1) + (s2 + s3)) * dv[r];
+        x[r] = (s0 + s1) * dv[r];
     }
-    if (lane < 32) {
+    if (lane < 16) {
 #pragma unroll
-        for (int r = 0; r < NB; ++r) Si[r][i] = x[r];
+        for (int r = 0; r < 16; ++r) Si[r0 + r][r0 + i] = x[r];
     }
+    wave_lds_sync();
+    return bad;
+}
+
+// Cholesky factor and inverse of the 32 x 32 block in S (lower triangle read),
+// by one wave, as a 2 x 2 block recursion over 16 x 16 blocks:
+//     L11 = chol(A11), Y11 = L11^{-1}
+//     L21 = A21 Y11^T,  S22 = A22 - L21 L21^T                (FP64 MFMA)
+//     L22 = chol(S22),  Y22 = L22^{-1}
+//     Y21 = -Y22 (L21 Y11)                                  (FP64 MFMA)
+// which halves the sequential depth of the 32-column factorisation and its
+// inverse. On return S holds L (zeros above the diagonal) and Si holds L^{-1}
+// (zeros above). Returns the first failing local column or -1. dv: 32 doubles
+// of LDS scratch.
+__device__ static int factor_diag32(double (*S)[NB + 1], double (*Si)[NB + 1], double* dv,
+                                    int lane)
+{
+    const int lr = lane & 15, lk = lane >> 4;
+    int bad = chol_inv16(S, Si, 0, dv, lane);
+    // L21 = A21 Y11^T
+    dbl4 t = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < 16; k += 4) t = mfma16(S[16 + lr][k + lk], Si[lr][k + lk], t);
+    wave_lds_sync();
+#pragma unroll
+    for (int v = 0; v < 4; ++v) S[16 + drow(lk, v)][lr] = t[v];
+    wave_lds_sync();
+    // S22 = A22 - L21 L21^T
+    dbl4 u;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) u[v] = S[16 + drow(lk, v)][16 + lr];
+#pragma unroll
+    for (int k = 0; k < 16; k += 4) u = mfma16(-S[16 + lr][k + lk], S[16 + lr][k + lk], u);
+    wave_lds_sync();
+#pragma unroll
+    for (int v = 0; v < 4; ++v) S[16 + drow(lk, v)][16 + lr] = u[v];
+    wave_lds_sync();
+    const int bad2 = chol_inv16(S, Si, 16, dv + 16, lane);
+    if (bad < 0 && bad2 >= 0) bad = 16 + bad2;
+    // Y21 = -Y22 W, W = L21 Y11 (W held in the Y21 block until it is replaced)
+    dbl4 w = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < 16; k += 4) w = mfma16(S[16 + lr][k + lk], Si[k + lk][lr], w);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Si[16 + drow(lk, v)][lr] = w[v];
+    wave_lds_sync();
+    dbl4 z = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < 16; k += 4)
+        z = mfma16(-Si[16 + lr][16 + k + lk], Si[16 + k + lk][lr], z);
+    wave_lds_sync();
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Si[16 + drow(lk, v)][lr] = z[v];
+    for (int e = lane; e < 256; e += 64) {
+        S[e >> 4][16 + (e & 15)] = 0.0;
+        Si[e >> 4][16 + (e & 15)] = 0.0;
+    }
+    wave_lds_sync();
     return bad;
 }
 

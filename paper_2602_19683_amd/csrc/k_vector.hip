@@ -80,48 +80,63 @@ hipError_t launch_gemv_f64(const GemvTask* d_tasks, int ntask, int m, hipStream_
     return hipGetLastError();
 }
 
-// out_i = [base_i -] (sum_{j < nb} v exp(-|a_i - b_j|^2 / (2 l)) x_j + [noise] s2 x_i)
-// A workgroup owns 64 rows of A; each group of 16 lanes owns 4 of them (kept
-// in registers), and lane t % 16 of the group takes the points j = t % 16
-// (mod 16) of every chunk of 256 points of B staged in LDS with their x_j.
-// The 16 partial sums of a row are combined by a fixed butterfly.
+// Matrix-free kernel matvec out_i = base_i - sum_j k(a_i, b_j) x_j (or without
+// base, the plain sum), for the predictive mean (eq. (2)): the cross
+// covariance is never stored. Workgroup (row block, column chunk) takes 64
+// rows (4 per thread, features in registers) against one chunk of the columns;
+// the points of B are staged in LDS 256 at a time with their x_j, and the 16
+// lanes of a row group take every 16th point. Each workgroup writes its
+// partial sums; a second kernel adds the chunks in order (fixed-order sums:
+// bitwise reproducible), so the launch has enough workgroups for the whole
+// chip even for a few thousand rows.
 namespace {
 constexpr int MV_ROWS = 64;   // rows per workgroup
 constexpr int MV_R = 4;       // rows per thread
 constexpr int MV_CH = 256;    // training points per LDS chunk
-constexpr int MV_MAXD = 16;   // features kept in registers / LDS
 }
 
+int matvec_chunks(int64_t na, int64_t nb)
+{
+    const int64_t rb = (na + MV_ROWS - 1) / MV_ROWS;
+    const int64_t maxc = (nb + MV_CH - 1) / MV_CH;
+    int64_t c = (1024 + rb - 1) / rb;
+    if (c > maxc) c = maxc;
+    if (c > 64) c = 64;
+    return (int)(c < 1 ? 1 : c);
+}
+
+template <int MAXD>
 __global__ __launch_bounds__(256) void k_kernel_matvec(const double* __restrict__ A, int64_t na,
                                                        const double* __restrict__ B, int64_t nb,
-                                                       int D, double l, double v, double s2,
-                                                       int noise, const double* __restrict__ x,
-                                                       const double* __restrict__ base,
-                                                       double* __restrict__ out)
+                                                       int D, double l, double v,
+                                                       const double* __restrict__ x,
+                                                       int64_t cw, double* __restrict__ part)
 {
-    __shared__ double Sb[MV_MAXD][MV_CH + 1];
+    __shared__ double Sb[MAXD][MV_CH + 1];
     __shared__ double Sx[MV_CH];
     const int tid = threadIdx.x;
     const int sub = tid & 15, grp = tid >> 4;  // 16 groups of 16 lanes
     const int64_t i0 = (int64_t)blockIdx.x * MV_ROWS + grp * MV_R;
+    const int64_t jb = (int64_t)blockIdx.y * cw;
+    const int64_t je = jb + cw < nb ? jb + cw : nb;
     const double inv2l = 1.0 / (2.0 * l);
-    double a[MV_R][MV_MAXD];
+    double a[MV_R][MAXD];
 #pragma unroll
     for (int r = 0; r < MV_R; ++r)
 #pragma unroll
-        for (int d = 0; d < MV_MAXD; ++d)
+        for (int d = 0; d < MAXD; ++d)
             a[r][d] = (i0 + r < na && d < D) ? A[(i0 + r) * D + d] : 0.0;
     double acc[MV_R];
 #pragma unroll
     for (int r = 0; r < MV_R; ++r) acc[r] = 0.0;
 
-    for (int64_t j0 = 0; j0 < nb; j0 += MV_CH) {
+    for (int64_t j0 = jb; j0 < je; j0 += MV_CH) {
         __syncthreads();
-        for (int e = tid; e < MV_CH * MV_MAXD; e += 256) {
-            const int jj = e / MV_MAXD, d = e % MV_MAXD;
-            Sb[d][jj] = (j0 + jj < nb && d < D) ? B[(j0 + jj) * D + d] : 0.0;
+        for (int e = tid; e < MV_CH * MAXD; e += 256) {
+            const int jj = e / MAXD, d = e % MAXD;
+            Sb[d][jj] = (j0 + jj < je && d < D) ? B[(j0 + jj) * D + d] : 0.0;
         }
-        if (tid < MV_CH) Sx[tid] = (j0 + tid < nb) ? x[j0 + tid] : 0.0;
+        if (tid < MV_CH) Sx[tid] = (j0 + tid < je) ? x[j0 + tid] : 0.0;
         __syncthreads();
         for (int jj = sub; jj < MV_CH; jj += 16) {
             const double xj = Sx[jj];
@@ -129,7 +144,7 @@ __global__ __launch_bounds__(256) void k_kernel_matvec(const double* __restrict_
 #pragma unroll
             for (int r = 0; r < MV_R; ++r) d2[r] = 0.0;
 #pragma unroll
-            for (int d = 0; d < MV_MAXD; ++d) {
+            for (int d = 0; d < MAXD; ++d) {
                 const double bd = Sb[d][jj];
 #pragma unroll
                 for (int r = 0; r < MV_R; ++r) {
@@ -141,13 +156,13 @@ __global__ __launch_bounds__(256) void k_kernel_matvec(const double* __restrict_
             for (int r = 0; r < MV_R; ++r) acc[r] += v * exp(-d2[r] * inv2l) * xj;
         }
     }
-    // features beyond MV_MAXD (rare): recompute those rows' sums exactly
-    if (D > MV_MAXD) {
+    // features beyond MAXD (rare): recompute those rows' sums exactly
+    if (D > MAXD) {
 #pragma unroll
         for (int r = 0; r < MV_R; ++r) {
             acc[r] = 0.0;
             if (i0 + r >= na) continue;
-            for (int64_t j = sub; j < nb; j += 16) {
+            for (int64_t j = jb + sub; j < je; j += 16) {
                 double d2 = 0.0;
                 for (int d = 0; d < D; ++d) {
                     const double q = A[(i0 + r) * D + d] - B[j * D + d];
@@ -165,21 +180,43 @@ __global__ __launch_bounds__(256) void k_kernel_matvec(const double* __restrict_
         sr += __shfl_xor(sr, 2, 64);
         sr += __shfl_xor(sr, 1, 64);
         const int64_t i = i0 + r;
-        if (sub == 0 && i < na) {
-            if (noise && i < nb) sr += s2 * x[i];
-            out[i] = base ? base[i] - sr : sr;
-        }
+        if (sub == 0 && i < na) part[(int64_t)blockIdx.y * na + i] = sr;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_matvec_finish(const double* __restrict__ part, int nch,
+                                                       int64_t na, int64_t nb, double s2, int noise,
+                                                       const double* __restrict__ x,
+                                                       const double* __restrict__ base,
+                                                       double* __restrict__ out)
+{
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < na;
+         i += (int64_t)gridDim.x * 256) {
+        double sr = 0.0;
+        for (int c = 0; c < nch; ++c) sr += part[(int64_t)c * na + i];
+        if (noise && i < nb) sr += s2 * x[i];
+        out[i] = base ? base[i] - sr : sr;
     }
 }
 
 hipError_t launch_kernel_matvec(const double* A, int64_t na, const double* B, int64_t nb, int D,
                                 double l, double v, double s2, bool noise, const double* x,
-                                const double* base, double* out, hipStream_t s)
+                                const double* base, double* out, double* work, hipStream_t s)
 {
     if (na <= 0) return hipSuccess;
-    const unsigned grid = (unsigned)((na + MV_ROWS - 1) / MV_ROWS);
-    hipLaunchKernelGGL(k_kernel_matvec, dim3(grid), dim3(256), 0, s, A, na, B, nb, D, l, v, s2,
-                       noise ? 1 : 0, x, base, out);
+    const int nch = matvec_chunks(na, nb);
+    const int64_t per = (nb + nch - 1) / nch;
+    const int64_t cw = (per + MV_CH - 1) / MV_CH * MV_CH;
+    const dim3 grid((unsigned)((na + MV_ROWS - 1) / MV_ROWS), (unsigned)nch);
+    if (D <= 8)
+        hipLaunchKernelGGL(k_kernel_matvec<8>, grid, dim3(256), 0, s, A, na, B, nb, D, l, v, x, cw,
+                           work);
+    else
+        hipLaunchKernelGGL(k_kernel_matvec<16>, grid, dim3(256), 0, s, A, na, B, nb, D, l, v, x, cw,
+                           work);
+    const int64_t fb = (na + 255) / 256;
+    hipLaunchKernelGGL(k_matvec_finish, dim3((unsigned)(fb < 1024 ? fb : 1024)), dim3(256), 0, s,
+                       work, nch, na, nb, s2, noise ? 1 : 0, x, base, out);
     return hipGetLastError();
 }
 
