@@ -233,7 +233,7 @@ int gpr_sync(gpr_ctx* ctx, void* stream, int64_t* column);
  * Per-kernel timers (the role APEX plays in Sec. 3.1): while enabled, every
  * launch the context issues is bracketed by HIP timing events on the stream
  * it runs on. Kinds: 0 POTRF, 1 inverse of the diagonal tiles, 2 TRSM,
- * 3 tile update (GEMM / SYRK), 4 assembly, 5 triangular-solve GEMV,
+ * 3 tile update (GEMM / SYRK), 4 assembly, 5 triangular vector solve,
  * 6 kernel matvec (mean / residual), 7 export to dense, 8 adjoint tile
  * products of the reverse sweep, 9 adjoint seed and gradient reduction. */
 int gpr_profile_enable(gpr_ctx* ctx, int on);
@@ -241,7 +241,7 @@ int gpr_profile_enable(gpr_ctx* ctx, int on);
 /* Totals for one kind over the launches recorded since the last reset:
  * number of launches, summed device time in ms, and summed algorithmic
  * flops (GEMM tile 2 m^3, SYRK / TRSM tile m^3, POTRF and inverse m^3 / 3 each,
- * GEMV tile 2 m^2, kernel matvec 2 per entry, adjoint tile product 2 m^3
+ * triangular vector solve 2 m^2 per tile read, kernel matvec 2 per entry, adjoint tile product 2 m^3
  * per term) and bytes (assembly and export: bytes written; adjoint seed and
  * reduction: bytes of the lower tiles). Blocks until the recorded work is done. reset != 0 clears
  * all kinds after reading. Any out pointer may be NULL. */

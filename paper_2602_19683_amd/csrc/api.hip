@@ -163,7 +163,7 @@ int ensure_events(gpr_ctx* ctx, size_t n)
 }
 
 enum ProfKind { PK_POTRF = 0, PK_TRTRI = 1, PK_TRSM = 2, PK_UPDATE = 3, PK_ASSEMBLE = 4,
-                PK_GEMV = 5, PK_MATVEC = 6, PK_EXPORT = 7, PK_ADJOINT = 8, PK_REDUCE = 9,
+                PK_TRSV = 5, PK_MATVEC = 6, PK_EXPORT = 7, PK_ADJOINT = 8, PK_REDUCE = 9,
                 PK_COUNT = 10 };
 
 hipEvent_t timing_event(gpr_ctx* ctx)
@@ -385,50 +385,20 @@ bool valid_prec(int prec, int m)
     return (prec == GPR_MIXED_FP32 || prec == GPR_MIXED_BF16) && m % 64 == 0;
 }
 
-// Vector solves with the factor: beta = L^{-1} r, alpha = L^{-T} beta.
-// r, beta, alpha are device vectors of length M m; r is overwritten.
-struct SolvePlan {
-    std::vector<size_t> off;  // per launch
-    std::vector<int> count;
-    int nfwd = 0;             // launches of the forward substitution
-};
-
-SolvePlan plan_solves(const gpr_tiled* L, double* r, double* beta, double* alpha, DescBuffer& db)
+// Vector solves with the factor: beta = L^{-1} rhs, alpha = L^{-T} beta
+// (k_trsv.hip); tmp is scratch. All vectors have length M m.
+int run_trsv_pair(gpr_ctx* ctx, const gpr_tiled* L, const double* rhs, double* tmp,
+                  double* beta, double* alpha, hipStream_t s)
 {
-    SolvePlan P;
     const int M = L->M, m = L->m;
-    const TileMat Km = kmat(L);
-    auto add = [&](const std::vector<GemvTask>& v) {
-        P.off.push_back(db.add(v.data(), v.size() * sizeof(GemvTask)));
-        P.count.push_back((int)v.size());
-    };
-    for (int J = 0; J < M; ++J) {  // forward
-        add({GemvTask{L->tinv + (size_t)J * m * m, r + (size_t)J * m, beta + (size_t)J * m, m, 0, 1, 0}});
-        std::vector<GemvTask> up;
-        for (int K = J + 1; K < M; ++K)
-            up.push_back({tile_ptr(Km, K, J), beta + (size_t)J * m, r + (size_t)K * m, m, 0, 0, 0});
-        if (!up.empty()) add(up);
+    const double f = 2.0 * (double)m * m * ((double)M * (M - 1) / 2 + M);
+    {
+        ProfScope ps(ctx, s, PK_TRSV, f, 0.0);
+        HIP_TRY(launch_trsv(kmat(L), L->tinv, M, rhs, tmp, beta, false, s));
     }
-    P.nfwd = (int)P.off.size();
-    for (int J = M - 1; J >= 0; --J) {  // backward, in place on beta
-        add({GemvTask{L->tinv + (size_t)J * m * m, beta + (size_t)J * m, alpha + (size_t)J * m, m, 1, 1, 0}});
-        std::vector<GemvTask> up;
-        for (int K = 0; K < J; ++K)
-            up.push_back({tile_ptr(Km, J, K), alpha + (size_t)J * m, beta + (size_t)K * m, m, 1, 0, 0});
-        if (!up.empty()) add(up);
-    }
-    return P;
-}
-
-// Runs launches [begin, end) of the plan (end < 0: to the last).
-int run_solves(gpr_ctx* ctx, const gpr_tiled* L, const SolvePlan& P, const DescBuffer& db,
-               hipStream_t s, int begin = 0, int end = -1)
-{
-    const double m2 = (double)L->m * L->m;
-    if (end < 0) end = (int)P.off.size();
-    for (int i = begin; i < end; ++i) {
-        ProfScope ps(ctx, s, PK_GEMV, 2.0 * m2 * P.count[i], 0.0);
-        HIP_TRY(launch_gemv_f64(db.dev<GemvTask>(ctx, P.off[i]), P.count[i], L->m, s));
+    {
+        ProfScope ps(ctx, s, PK_TRSV, f, 0.0);
+        HIP_TRY(launch_trsv(kmat(L), L->tinv, M, beta, tmp, alpha, true, s));
     }
     return GPR_OK;
 }
@@ -733,7 +703,7 @@ int predict_impl(gpr_ctx* ctx, gpr_tiled* L, const double* X, const double* y, i
     const int m = L->m, M = L->M;
     const int Mhat = (int)((n_test + m - 1) / m);
     const size_t npad = (size_t)M * m;
-    const size_t vec_bytes = 5 * npad * sizeof(double) + 256;
+    const size_t vec_bytes = 6 * npad * sizeof(double) + 256;
     const size_t v_bytes = cov ? (size_t)Mhat * M * m * m * sizeof(double) : 0;
     const size_t s_bytes = cov ? (size_t)Mhat * (Mhat + 1) / 2 * m * m * sizeof(double) : 0;
     const size_t mv_bytes = (size_t)matvec_chunks(n_test, n) * n_test * sizeof(double);
@@ -752,13 +722,13 @@ int predict_impl(gpr_ctx* ctx, gpr_tiled* L, const double* X, const double* y, i
     double* alpha = beta + npad;
     double* acc = alpha + npad;     // refined alpha
     double* scal = acc + npad;      // small scalars (norms)
-    double* Vb = scal + npad;
+    double* tmp = scal + npad;      // scratch of the triangular solves
+    double* Vb = tmp + npad;
     double* Sb = reinterpret_cast<double*>(reinterpret_cast<char*>(Vb) + v_bytes);
     double* mvw = reinterpret_cast<double*>(reinterpret_cast<char*>(Sb) + s_bytes);
     const int fprec = fused ? prec : L->prec;
 
     DescBuffer db;
-    SolvePlan SP = plan_solves(L, r, beta, alpha, db);
     SweepMats SM{kmat(L), L->tinv, TileMat{Vb, m, 1, M}, TileMat{Sb, m, 0, 0}, M,
                  cov ? Mhat : 0, m, fprec};
     SweepPlan PP;
@@ -804,7 +774,7 @@ int predict_impl(gpr_ctx* ctx, gpr_tiled* L, const double* X, const double* y, i
     }
     // alpha = K^{-1} y via the two triangular solves (Sec. 4.1)
     HIP_TRY(launch_copy_f64(y, r, n, (int64_t)npad, s));
-    rc = run_solves(ctx, L, SP, db, s);
+    rc = run_trsv_pair(ctx, L, r, tmp, beta, alpha, s);
     if (rc) return rc;
     const double* alpha_used = alpha;
     if (ir) {
@@ -835,7 +805,7 @@ int predict_impl(gpr_ctx* ctx, gpr_tiled* L, const double* X, const double* y, i
             if (rel <= 1e-14 || it == 50) break;
             if (prev >= 0 && rn > 0.9 * prev) break;   // stagnation
             prev = rn;
-            rc = run_solves(ctx, L, SP, db, s);          // alpha = L^{-T} L^{-1} r
+            rc = run_trsv_pair(ctx, L, r, tmp, beta, alpha, s);  // alpha = L^{-T} L^{-1} r
             if (rc) return rc;
             HIP_TRY(launch_axpy(acc, alpha, (int64_t)npad, s));
         }
@@ -919,17 +889,14 @@ int gpr_solve(gpr_ctx* ctx, gpr_tiled* L, const double* b, double* x, void* stre
     int rc = begin_call(ctx, s);
     if (rc) return rc;
     const size_t npad = (size_t)L->M * L->m;
-    rc = ensure_device_bytes(&ctx->d_ws, &ctx->ws_cap, 3 * npad * sizeof(double) + 256);
+    rc = ensure_device_bytes(&ctx->d_ws, &ctx->ws_cap, 4 * npad * sizeof(double) + 256);
     if (rc) return rc;
     double* r = reinterpret_cast<double*>(ctx->d_ws);
     double* beta = r + npad;
     double* alpha = beta + npad;
-    DescBuffer db;
-    SolvePlan SP = plan_solves(L, r, beta, alpha, db);
-    rc = db.upload(ctx, s);
-    if (rc) return rc;
+    double* tmp = alpha + npad;
     HIP_TRY(launch_copy_f64(b, r, L->n, (int64_t)npad, s));
-    rc = run_solves(ctx, L, SP, db, s);
+    rc = run_trsv_pair(ctx, L, r, tmp, beta, alpha, s);
     if (rc) return rc;
     HIP_TRY(launch_copy_f64(alpha, x, L->n, L->n, s));
     return end_call(ctx, s);
@@ -973,14 +940,13 @@ int gpr_nlml_grad(gpr_ctx* ctx, const double* X, const double* y, int64_t n, int
     double* r = reinterpret_cast<double*>(ctx->d_ws);
     double* beta = r + npad;
     double* alpha = beta + npad;
-    double* bsave = alpha + npad;
-    double* parts = bsave + npad;
+    double* tmp = alpha + npad;     // scratch of the triangular solves
+    double* parts = tmp + npad;
 
     DescBuffer db;
     SweepMats SM{kmat(K), K->tinv, TileMat{nullptr, m, 1, M}, TileMat{nullptr, m, 0, 0}, M, 0, m,
                  GPR_FP64};
     SweepPlan PP = plan_sweep(SM, SWEEP_CHOLESKY, db);
-    SolvePlan SP = plan_solves(K, r, beta, alpha, db);
     AdjPlan AP;
     AdjExec AE;
     AdjBufs AB{};
@@ -1026,15 +992,12 @@ int gpr_nlml_grad(gpr_ctx* ctx, const double* X, const double* y, int64_t n, int
     if (rc) return rc;
     // beta = L^{-1} y (kept), alpha = L^{-T} beta
     HIP_TRY(launch_copy_f64(y, r, n, (int64_t)npad, s));
-    rc = run_solves(ctx, K, SP, db, s, 0, SP.nfwd);
-    if (rc) return rc;
-    HIP_TRY(launch_copy_f64(beta, bsave, (int64_t)npad, (int64_t)npad, s));
-    rc = run_solves(ctx, K, SP, db, s, SP.nfwd, -1);
+    rc = run_trsv_pair(ctx, K, r, tmp, beta, alpha, s);
     if (rc) return rc;
     if (grad) {
         {
             ProfScope ps(ctx, s, PK_REDUCE, 0.0, (double)tiled_bytes(K));
-            HIP_TRY(launch_lbar_init(AB.Lbar, AB.L, M, alpha, bsave, s));
+            HIP_TRY(launch_lbar_init(AB.Lbar, AB.L, M, alpha, beta, s));
         }
         rc = run_adjoint(ctx, AP, AE, m, db, s);
         if (rc) return rc;
@@ -1044,7 +1007,7 @@ int gpr_nlml_grad(gpr_ctx* ctx, const double* X, const double* y, int64_t n, int
         }
         if (out_Kbar) HIP_TRY(launch_kbar_export(AB.Abar, n, out_Kbar, s));
     }
-    HIP_TRY(launch_nlml_finish(kmat(K), bsave, n, parts, out_grad3 ? nparts : 0, h.lengthscale,
+    HIP_TRY(launch_nlml_finish(kmat(K), beta, n, parts, out_grad3 ? nparts : 0, h.lengthscale,
                                h.vertical_variance, ctx->d_info, out_nlml, out_grad3, s));
     return end_call(ctx, s);
 }

@@ -64,14 +64,6 @@ struct TrsmTask {
     int ldb, ldl, ldd, pad;
 };
 
-// y (-)= op(T) x on one m x m tile; op = transpose if trans; set: y = op(T) x.
-struct GemvTask {
-    const double* T;
-    const double* x;
-    double* y;
-    int ld, trans, set, pad;
-};
-
 // Tile product task of the adjoint sweep (k_tgemm.hip):
 //   C = beta Cin + sum_t alpha_t op(A_t) op(B_t) + sum_p part[p * part_stride],
 // then the epilogue. All tiles m x m; partial tiles have leading dimension m.
@@ -132,7 +124,11 @@ hipError_t launch_potrf_f64(double* A, int lda, int m, double* Tinv, int ldt, in
 // the inverse of tile J goes to Tinv + J m^2 (leading dimension m), whose
 // 32 x 32 diagonal blocks must already hold the block inverses.
 hipError_t launch_trtri_f64(const TileMat& K, int M, double* Tinv, hipStream_t s);
-hipError_t launch_gemv_f64(const GemvTask* d_tasks, int ntask, int m, hipStream_t s);
+// x = L^{-1} b (trans: L^{-T} b) over the lower tiles of L with the inverses of
+// its diagonal tiles (Tinv, M tiles), two launches per tile row; r: scratch of
+// length M m (b is copied there first).
+hipError_t launch_trsv(const TileMat& L, const double* Tinv, int M, const double* b, double* r,
+                       double* x, bool trans, hipStream_t s);
 
 // out_i = base_i - k(A_i, B) x  (subtract) or out_i = k(A_i, B) x  (base == nullptr),
 // where k(A_i, B) x = sum_j k(a_i, b_j) x_j + (noise ? s2 x_i : 0) over j < nb.

@@ -161,14 +161,21 @@ __device__ static int factor_diag32(double (*S)[NB + 1], double (*Si)[NB + 1], d
     return bad;
 }
 
+// Polls with relaxed loads (no cache invalidation per poll) and acquires once
+// the flag holds the epoch.
 __device__ static bool wait_flag(const unsigned* f, unsigned epoch)
 {
     unsigned it = 0;
-    while (__hip_atomic_load(f, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
+    bool ok = true;
+    while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
         __builtin_amdgcn_s_sleep(2);
-        if (++it > SPIN_LIMIT) return false;
+        if (++it > SPIN_LIMIT) {
+            ok = false;
+            break;
+        }
     }
-    return true;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return ok;
 }
 
 __global__ __launch_bounds__(256) void k_potrf_f64(double* __restrict__ A, int lda, int m,

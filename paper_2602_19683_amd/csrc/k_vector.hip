@@ -1,6 +1,4 @@
 // k_vector.hip -- vector kernels of the prediction (Sec. 4.1):
-//   * tile GEMVs for the triangular solves L beta = y and L^T alpha = beta,
-//     run tile row by tile row with the inverted diagonal tiles;
 //   * the matrix-free kernel matvec sum_j k(a_i, b_j) x_j that gives the
 //     predictive mean (eq. (2)) from alpha without storing K_{X*,X}, and the
 //     residual y - K alpha of the iterative refinement.
@@ -17,68 +15,6 @@ __device__ inline double wave_sum(double x)
     return x;
 }
 
-// y (-)= op(T) x for each task, in blocks of 32 output entries.
-// Non-transposed: each wave owns 8 rows and walks their columns together
-// (eight independent loads per step), then a fixed butterfly adds the lanes.
-// Transposed: thread (g, c) sums column c over row group g of 8 (unrolled);
-// the groups are added in order.
-__global__ __launch_bounds__(256) void k_gemv_f64(const GemvTask* __restrict__ tasks, int m)
-{
-    __shared__ double part[8][32];
-    const int per = m / 32;
-    const int t = blockIdx.x / per, blk = blockIdx.x - t * per;
-    const GemvTask tk = tasks[t];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    if (!tk.trans) {
-        const int row0 = blk * 32 + wave * 8;
-        const double* Tr = tk.T + (size_t)row0 * tk.ld;
-        double s[8];
-#pragma unroll
-        for (int rr = 0; rr < 8; ++rr) s[rr] = 0.0;
-        for (int c = lane; c < m; c += 64) {
-            const double xc = tk.x[c];
-#pragma unroll
-            for (int rr = 0; rr < 8; ++rr) s[rr] += Tr[(size_t)rr * tk.ld + c] * xc;
-        }
-#pragma unroll
-        for (int rr = 0; rr < 8; ++rr) s[rr] = wave_sum(s[rr]);
-        if (lane < 8) {
-            double v = s[0];
-#pragma unroll
-            for (int rr = 1; rr < 8; ++rr) v = (lane == rr) ? s[rr] : v;
-            const int row = row0 + lane;
-            tk.y[row] = tk.set ? v : tk.y[row] - v;
-        }
-    } else {
-        const int c = tid & 31, g = tid >> 5;
-        const int col = blk * 32 + c;
-        const int rows = m / 8;
-        const double* Tc = tk.T + (size_t)g * rows * tk.ld + col;
-        const double* xg = tk.x + g * rows;
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-        for (int r = 0; r < rows; r += 4) {
-            s0 += Tc[(size_t)r * tk.ld] * xg[r];
-            s1 += Tc[(size_t)(r + 1) * tk.ld] * xg[r + 1];
-            s2 += Tc[(size_t)(r + 2) * tk.ld] * xg[r + 2];
-            s3 += Tc[(size_t)(r + 3) * tk.ld] * xg[r + 3];
-        }
-        part[g][c] = (s0 + s1) + (s2 + s3);
-        __syncthreads();
-        if (tid < 32) {
-            double tot = part[0][c];
-#pragma unroll
-            for (int q = 1; q < 8; ++q) tot += part[q][c];
-            tk.y[col] = tk.set ? tot : tk.y[col] - tot;
-        }
-    }
-}
-
-hipError_t launch_gemv_f64(const GemvTask* d_tasks, int ntask, int m, hipStream_t s)
-{
-    if (ntask <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_gemv_f64, dim3(ntask * (m / 32)), dim3(256), 0, s, d_tasks, m);
-    return hipGetLastError();
-}
 
 // Matrix-free kernel matvec out_i = base_i - sum_j k(a_i, b_j) x_j (or without
 // base, the plain sum), for the predictive mean (eq. (2)): the cross

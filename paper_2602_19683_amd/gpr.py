@@ -236,7 +236,7 @@ class Context:
         return out_nlml, (out_grad if grad else None), (out_kbar if kbar else None)
 
     # ---- instrumentation --------------------------------------------------
-    PROFILE_KINDS = ("potrf", "trtri", "trsm", "update", "assemble", "gemv", "matvec", "export",
+    PROFILE_KINDS = ("potrf", "trtri", "trsm", "update", "assemble", "trsv", "matvec", "export",
                      "adjoint", "reduce")
 
     def profile(self, on=True):
