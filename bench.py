@@ -26,7 +26,7 @@ FP64_PEAK_TFLOPS = 78.6     # MI355X dense FP64 (vector = matrix)
 # HBM bytes per dispatch of the tile-update kernel from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs scaled by a 1 GiB copy (profiles/fp64_c3_hbm_traffic.md); only
 # valid for the kernel source they were taken on.
-UPDATE_TRAFFIC = {"k_update_sha256_16": "13f50f13ba42832e", "bytes_per_launch": 738656651}
+UPDATE_TRAFFIC = {"k_update_sha256_16": "13f50f13ba42832e", "bytes_per_launch": 737647399}
 
 
 def update_traffic():
