@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define GPR_ABI_VERSION 2
+#define GPR_ABI_VERSION 3
 
 /* Status codes. */
 enum {
@@ -81,9 +81,15 @@ typedef enum {
     GPR_MIXED_BF16 = 2
 } gpr_precision;
 
-/* How the tile task graph is executed. GPR_EXEC_STREAMS: batched tile-task
- * launches on three HIP streams with one step of look-ahead.
- * GPR_EXEC_PERSISTENT is reserved (GPR_ENOTSUP in this build). */
+/* How the tile task graph is executed (the task graph of Fig. 1, Sec. 4.2,
+ * with the covariance rows of Sec. 4.1 appended). GPR_EXEC_STREAMS: batched
+ * tile-task launches on three HIP streams with one step of look-ahead.
+ * GPR_EXEC_PERSISTENT: one launch per sweep; resident workgroups take work
+ * items (POTRF row panels, TRSM strips, update blocks) from a ticket list in
+ * a precomputed priority order and wait on per-tile progress counters in
+ * device memory. Both give bitwise-identical FP64 results. The persistent
+ * executor runs the FP64 sweeps; the mixed-precision sweeps of a context
+ * created with it run on the streams. */
 typedef enum {
     GPR_EXEC_STREAMS = 0,
     GPR_EXEC_PERSISTENT = 1
@@ -235,7 +241,8 @@ int gpr_sync(gpr_ctx* ctx, void* stream, int64_t* column);
  * it runs on. Kinds: 0 POTRF, 1 inverse of the diagonal tiles, 2 TRSM,
  * 3 tile update (GEMM / SYRK), 4 assembly, 5 triangular vector solve,
  * 6 kernel matvec (mean / residual), 7 export to dense, 8 adjoint tile
- * products of the reverse sweep, 9 adjoint seed and gradient reduction. */
+ * products of the reverse sweep, 9 adjoint seed and gradient reduction,
+ * 10 persistent sweep (one launch per sweep; flops of all its tile tasks). */
 int gpr_profile_enable(gpr_ctx* ctx, int on);
 
 /* Totals for one kind over the launches recorded since the last reset:
@@ -295,6 +302,20 @@ int gpr_adjoint_describe(int32_t M, int32_t G, int32_t* tasks, int64_t task_cap,
                          int64_t* n_tasks, int32_t* terms, int64_t term_cap,
                          int64_t* n_terms, int32_t* launches, int64_t launch_cap,
                          int64_t* n_launches);
+
+/* The ticket order of the persistent executor for one sweep shape (host
+ * only): M, Mhat, mode as for gpr_schedule_describe, tile m, update block
+ * size `block` (divides m), and `workers` resident workgroups assumed by the
+ * planner. items: 5 int32 per ticket (kind 0 POTRF row panel, 1 TRSM strip,
+ * 2 update block; sub-index; I, K, J as in gpr_schedule_describe). waits:
+ * 8 int64 per ticket: the number of waits (0..3), then (counter, value) x 3
+ * -- the item starts once counter >= value (-1, 0 where unused) -- and the
+ * counter the item increments when done. Counter (I, K) = I (I + 1) / 2 + K
+ * over the tile rows of the extended matrix. Either array may be NULL;
+ * cap in tickets; *n_items always written; GPR_EINVAL if cap is too small. */
+int gpr_persist_describe(int32_t M, int32_t Mhat, int32_t mode, int32_t tile, int32_t block,
+                         int32_t workers, int32_t* items, int64_t* waits, int64_t cap,
+                         int64_t* n_items);
 
 /* ABI version of the loaded library (GPR_ABI_VERSION it was built with). */
 int gpr_abi_version(void);

@@ -60,6 +60,8 @@ SIGNATURES = {
                                              _i64p]),
     "gpr_adjoint_describe": (ctypes.c_int, [_i32, _i32, _i32p, _i64, _i64p, _i32p, _i64, _i64p,
                                             _i32p, _i64, _i64p]),
+    "gpr_persist_describe": (ctypes.c_int, [_i32, _i32, _i32, _i32, _i32, _i32, _i32p, _i64p,
+                                            _i64, _i64p]),
 }
 
 _LIB = None

@@ -13,6 +13,7 @@
 // to the device in one transfer, and the launches index into them.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
@@ -45,6 +46,15 @@ struct gpr_ctx {
     gpr_tiled* nlml_K = nullptr;  // factor kept by gpr_nlml_grad
     char* d_adj = nullptr;        // adjoint workspace (Lbar, Abar, partial tiles)
     size_t adj_cap = 0;
+    // persistent executor: ticket order of the last sweep shape (device copy)
+    int executor = GPR_EXEC_STREAMS;
+    char* d_pitems = nullptr;
+    size_t pitems_cap = 0;
+    int64_t pkey[6] = {-1, -1, -1, -1, -1, -1};
+    int64_t p_nitems = 0;
+    int p_workers = 0, p_bm = 0;
+    char* d_pcnt = nullptr;       // progress counters + ticket
+    size_t pcnt_cap = 0;
     // instrumentation
     bool prof_on = false;
     std::vector<hipEvent_t> tpool;  // timing events, reused after each read
@@ -55,8 +65,8 @@ struct gpr_ctx {
         double flops, bytes;
     };
     std::vector<ProfRec> pending;
-    int64_t p_launches[10] = {};
-    double p_ms[10] = {}, p_flops[10] = {}, p_bytes[10] = {};
+    int64_t p_launches[11] = {};
+    double p_ms[11] = {}, p_flops[11] = {}, p_bytes[11] = {};
 };
 
 struct gpr_tiled {
@@ -164,7 +174,7 @@ int ensure_events(gpr_ctx* ctx, size_t n)
 
 enum ProfKind { PK_POTRF = 0, PK_TRTRI = 1, PK_TRSM = 2, PK_UPDATE = 3, PK_ASSEMBLE = 4,
                 PK_TRSV = 5, PK_MATVEC = 6, PK_EXPORT = 7, PK_ADJOINT = 8, PK_REDUCE = 9,
-                PK_COUNT = 10 };
+                PK_PERSIST = 10, PK_COUNT = 11 };
 
 hipEvent_t timing_event(gpr_ctx* ctx)
 {
@@ -247,14 +257,27 @@ struct SweepMats {
 };
 
 struct SweepPlan {
+    int mode = SWEEP_CHOLESKY;
+    bool persistent = false;  // run by the persistent executor (no descriptors)
     Schedule sched;
     std::vector<size_t> off;  // descriptor offset per launch
 };
 
+// The persistent executor runs FP64 sweeps; a context created for it runs
+// the mixed-precision sweeps (whose updates have no persistent form) on the
+// streams.
+bool use_persistent(const gpr_ctx* ctx, const SweepMats& X)
+{
+    return ctx->executor == GPR_EXEC_PERSISTENT && X.prec == GPR_FP64;
+}
+
 // Builds the descriptors of a sweep into `db`.
-SweepPlan plan_sweep(const SweepMats& X, int mode, DescBuffer& db)
+SweepPlan plan_sweep(const gpr_ctx* ctx, const SweepMats& X, int mode, DescBuffer& db)
 {
     SweepPlan P;
+    P.mode = mode;
+    P.persistent = use_persistent(ctx, X);
+    if (P.persistent) return P;
     P.sched = build_schedule(X.M, X.Mhat, mode);
     P.off.assign(P.sched.launches.size(), 0);
     const int m = X.m;
@@ -281,12 +304,60 @@ SweepPlan plan_sweep(const SweepMats& X, int mode, DescBuffer& db)
     return P;
 }
 
+// The whole sweep as one persistent launch on s (k_persist.hip). The ticket
+// order depends only on the shape and is kept in the context.
+int run_persist(gpr_ctx* ctx, const SweepMats& X, int mode, hipStream_t s)
+{
+    const int m = X.m, M = X.M, bm = persist_block(m);
+    const int Mhat = mode == SWEEP_CHOLESKY ? 0 : X.Mhat;
+    if (ctx->p_workers <= 0 || ctx->p_bm != bm) {
+        ctx->p_workers = persist_workers(bm);
+        ctx->p_bm = bm;
+        if (ctx->p_workers <= 0) return GPR_EHIP;
+    }
+    const int64_t key[6] = {M, Mhat, mode, m, bm, ctx->p_workers};
+    if (!std::equal(key, key + 6, ctx->pkey)) {
+        const std::vector<PItem> order = build_persist_order(M, Mhat, mode, m, bm, ctx->p_workers);
+        const size_t bytes = order.size() * sizeof(PItem);
+        // the previous order may still be read by a running sweep
+        HIP_TRY(hipStreamSynchronize(s));
+        int rc = ensure_device_bytes(&ctx->d_pitems, &ctx->pitems_cap, bytes > 0 ? bytes : 64);
+        if (rc) return rc;
+        if (bytes) HIP_TRY(hipMemcpy(ctx->d_pitems, order.data(), bytes, hipMemcpyHostToDevice));
+        std::copy(key, key + 6, ctx->pkey);
+        ctx->p_nitems = (int64_t)order.size();
+    }
+    const PGeom g = persist_geom(M, Mhat, mode, m, bm);
+    const int64_t ncnt = (int64_t)g.T * (g.T + 1) / 2;
+    int rc = ensure_device_bytes(&ctx->d_pcnt, &ctx->pcnt_cap, (size_t)(ncnt + 1) * sizeof(unsigned));
+    if (rc) return rc;
+    // flops of the tile tasks (Fig. 1 counts: POTRF m^3/3, TRSM m^3, SYRK m^3,
+    // GEMM 2 m^3)
+    double tasks = 0.0;
+    for (int J = 0; J < M; ++J) {
+        const int I0 = g.factor ? J + 1 : M;
+        const double rows = g.T - I0;  // TRSM tasks of column J
+        double upd = 0.0;              // update flops of step J in units of m^3
+        for (int I = I0; I < g.T; ++I) upd += 2.0 * (I - J) - 1.0;  // GEMMs 2, SYRK 1
+        tasks += (g.factor ? 1.0 / 3.0 : 0.0) + rows + upd;
+    }
+    const unsigned epoch0 = ctx->epoch + 1;
+    ctx->epoch += (unsigned)M;
+    ProfScope ps(ctx, s, PK_PERSIST, tasks * (double)m * m * m, 0.0);
+    HIP_TRY(launch_persist(reinterpret_cast<const PItem*>(ctx->d_pitems), ctx->p_nitems, g, m, bm,
+                           ctx->p_workers, X.K, X.tinv, X.V, X.S,
+                           reinterpret_cast<unsigned*>(ctx->d_pcnt), ncnt, ctx->d_flags, epoch0,
+                           ctx->d_info, ctx->d_info + 2, s));
+    return GPR_OK;
+}
+
 // Issues the launches of a planned sweep. Logical streams: 0 critical (the
 // caller's stream s), 1 panel, 2 bulk; with fewer streams in the context
 // they fold onto s. The extra streams fork from s and join back into it.
 int run_sweep(gpr_ctx* ctx, const SweepMats& X, const SweepPlan& P, const DescBuffer& db,
               hipStream_t s)
 {
+    if (P.persistent) return run_persist(ctx, X, P.mode, s);
     const auto& Ls = P.sched.launches;
     int rc = ensure_events(ctx, Ls.size());
     if (rc) return rc;
@@ -531,10 +602,10 @@ int gpr_ctx_create(gpr_ctx** out, int device, int n_streams, gpr_executor ex)
     if (ex != GPR_EXEC_STREAMS && ex != GPR_EXEC_PERSISTENT) return GPR_EINVAL;
     int rc = check_device(device);
     if (rc) return rc;
-    if (ex == GPR_EXEC_PERSISTENT) return GPR_ENOTSUP;
     gpr_ctx* c = new (std::nothrow) gpr_ctx;
     if (!c) return GPR_ENOMEM;
     c->device = device;
+    c->executor = ex;
     c->n_streams = n_streams >= 3 ? 3 : n_streams;
     bool ok = hipStreamCreateWithFlags(&c->bulk, hipStreamNonBlocking) == hipSuccess &&
               hipStreamCreateWithFlags(&c->panel, hipStreamNonBlocking) == hipSuccess &&
@@ -576,6 +647,8 @@ int gpr_ctx_destroy(gpr_ctx* c)
     if (c->d_desc) (void)hipFree(c->d_desc);
     if (c->h_desc) (void)hipHostFree(c->h_desc);
     if (c->d_ws) (void)hipFree(c->d_ws);
+    if (c->d_pitems) (void)hipFree(c->d_pitems);
+    if (c->d_pcnt) (void)hipFree(c->d_pcnt);
     delete c;
     return GPR_OK;
 }
@@ -633,7 +706,7 @@ int gpr_cholesky(gpr_ctx* ctx, gpr_tiled* K, gpr_precision prec, int32_t* info_d
     SweepMats X{kmat(K), K->tinv, TileMat{nullptr, m, 1, M}, TileMat{nullptr, m, 0, 0}, M, 0, m,
                 (int)prec};
     DescBuffer db;
-    SweepPlan P = plan_sweep(X, SWEEP_CHOLESKY, db);
+    SweepPlan P = plan_sweep(ctx, X, SWEEP_CHOLESKY, db);
     rc = db.upload(ctx, s);
     if (rc) return rc;
     HIP_TRY(launch_set_int(ctx->d_info, 0, s));
@@ -733,7 +806,7 @@ int predict_impl(gpr_ctx* ctx, gpr_tiled* L, const double* X, const double* y, i
                  cov ? Mhat : 0, m, fprec};
     SweepPlan PP;
     const int mode = fused ? (cov ? SWEEP_FUSED : SWEEP_CHOLESKY) : SWEEP_PREDICT;
-    if (fused || cov) PP = plan_sweep(SM, mode, db);
+    if (fused || cov) PP = plan_sweep(ctx, SM, mode, db);
     rc = db.upload(ctx, s);
     if (rc) return rc;
 
@@ -946,7 +1019,7 @@ int gpr_nlml_grad(gpr_ctx* ctx, const double* X, const double* y, int64_t n, int
     DescBuffer db;
     SweepMats SM{kmat(K), K->tinv, TileMat{nullptr, m, 1, M}, TileMat{nullptr, m, 0, 0}, M, 0, m,
                  GPR_FP64};
-    SweepPlan PP = plan_sweep(SM, SWEEP_CHOLESKY, db);
+    SweepPlan PP = plan_sweep(ctx, SM, SWEEP_CHOLESKY, db);
     AdjPlan AP;
     AdjExec AE;
     AdjBufs AB{};

@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "gpr.h"
+#include "persist.h"
 
 namespace gpr {
 
@@ -239,5 +240,18 @@ AdjPlan build_adjoint(int M, int G);
 // Tile sweep over M training tile rows and Mhat test tile rows (see gpr.h,
 // gpr_schedule_describe).
 Schedule build_schedule(int M, int Mhat, int mode);
+
+// Persistent executor (persist.cpp, k_persist.hip): geometry, ticket order for
+// `workers` resident workgroups, update block size for a tile size, the
+// number of workgroups that fit at once, and the launch (which first clears
+// the ncnt progress counters and the ticket at d_cnt[ncnt]).
+PGeom persist_geom(int M, int Mhat, int mode, int m, int bm);
+std::vector<PItem> build_persist_order(int M, int Mhat, int mode, int m, int bm, int workers);
+int persist_block(int m);
+int persist_workers(int bm);
+hipError_t launch_persist(const PItem* d_items, int64_t nitems, const PGeom& g, int m, int bm,
+                          int workers, const TileMat& K, double* tinv, const TileMat& V,
+                          const TileMat& S, unsigned* d_cnt, int64_t ncnt, unsigned* flags,
+                          unsigned epoch0, int* info, int* err, hipStream_t s);
 
 }  // namespace gpr

@@ -16,53 +16,17 @@
 #include "gpr_internal.h"
 #include "k_accum.h"
 #include "k_common.h"
+#include "k_trsm_dev.h"
 
 namespace gpr {
 
-namespace {
-constexpr int TK = 16;  // k-chunk of the block product
-}
-
 __global__ __launch_bounds__(256) void k_trsm_f64(const TrsmTask* __restrict__ tasks, int m)
 {
-    __shared__ double As[2][TK][36];
-    __shared__ double Bs[2][TK][36];
-    __shared__ double Sacc[32][33];
+    __shared__ TrsmLds sh;
     const int strips = m / 32;
     const int lid = xcd_remap(blockIdx.x, gridDim.x);
     const int t = lid / strips, s = lid - t * strips;
-    const TrsmTask tk = tasks[t];
-    double* __restrict__ B = tk.B + (size_t)s * 32 * tk.ldb;
-    const int ldb = tk.ldb, ldl = tk.ldl, ldd = tk.ldd;
-    float* __restrict__ B32 = tk.B32 ? tk.B32 + (size_t)s * 32 * m : nullptr;
-    const int tid = threadIdx.x;
-    const int lane = tid & 63, wave = tid >> 6;
-    const int lr = lane & 15, lk = lane >> 4;
-    const int qi = wave >> 1, qj = wave & 1;
-    const int P = m / 32;
-    for (int p = 0; p < P; ++p) {
-        const int c0 = 32 * p;
-        dbl4 acc;
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-            acc[v] = B[(size_t)(16 * qi + drow(lk, v)) * ldb + c0 + 16 * qj + lr];
-        // minus the finished blocks X[:, 0:c0] times rows c0.. of L_JJ (transposed)
-        acc = accum32<true, TK>(B, ldb, tk.L + (size_t)c0 * ldl, ldl, c0, acc, -1.0, As, Bs);
-#pragma unroll
-        for (int v = 0; v < 4; ++v) Sacc[16 * qi + drow(lk, v)][16 * qj + lr] = acc[v];
-        __syncthreads();
-        const double* dq = tk.Dinv + (size_t)(c0 + 16 * qj + lr) * ldd + c0 + lk;
-        dbl4 o = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int k = 0; k < 32; k += 4) o = mfma16(Sacc[16 * qi + lr][k + lk], dq[k], o);
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int row = 16 * qi + drow(lk, v), col = c0 + 16 * qj + lr;
-            B[(size_t)row * ldb + col] = o[v];
-            if (B32) B32[(size_t)row * m + col] = (float)o[v];
-        }
-        __syncthreads();  // X_p stored (read by every wave next), Sacc free
-    }
+    trsm_strip(tasks[t], s, m, sh);
 }
 
 hipError_t launch_trsm_f64(const TrsmTask* d_tasks, int ntask, int m, hipStream_t s)

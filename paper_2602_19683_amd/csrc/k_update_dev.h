@@ -1,0 +1,105 @@
+// k_update_dev.h -- one block of a tile update C -= A B^T (GEMM / SYRK tasks of
+// Fig. 1), shared by the stream kernel and the persistent executor; the
+// blocking is described in k_update.hip.
+#pragma once
+
+#include "gpr_internal.h"
+#include "k_common.h"
+
+namespace gpr {
+
+template <int BM>
+struct UpdLds {
+    double As[2][16][BM + 4];
+    double Bs[2][16][BM + 4];
+};
+
+// Block (bi, bj) of the task, WR x WC waves (WR * WC * 64 threads).
+template <int BM, int WR, int WC>
+__device__ inline void update_block(const UpdateTask& tk, int bi, int bj, int m, UpdLds<BM>& sh)
+{
+    constexpr int NT = WR * WC * 64;  // threads
+    constexpr int KB = 16;
+    constexpr int TR = BM / WR / 16;  // MFMA tiles per wave, rows
+    constexpr int TC = BM / WC / 16;  // MFMA tiles per wave, columns
+    constexpr int LD = BM + 4;        // padded LDS row (k-major slices)
+    constexpr int NLD = BM * KB / 2 / NT;  // double2 loads per thread per operand
+    static_assert(NLD >= 1 && TR >= 1 && TC >= 1, "block too small");
+    double (*As)[KB][LD] = sh.As;
+    double (*Bs)[KB][LD] = sh.Bs;
+
+    const double* __restrict__ A = tk.A + (size_t)bi * BM * tk.lda;
+    const double* __restrict__ B = tk.B + (size_t)bj * BM * tk.ldb;
+    double* __restrict__ C = tk.C + (size_t)bi * BM * tk.ldc + (size_t)bj * BM;
+    const int lda = tk.lda, ldb = tk.ldb, ldc = tk.ldc;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wr = (wave / WC) * (BM / WR), wc = (wave % WC) * (BM / WC);
+    const int lr = lane & 15, lk = lane >> 4;
+
+    double2 ra[NLD], rb[NLD];
+    auto gload = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < NLD; ++q) {
+            const int e = tid + NT * q;
+            const int r = e / (KB / 2), kk = (e % (KB / 2)) * 2;
+            ra[q] = *reinterpret_cast<const double2*>(A + (size_t)r * lda + k0 + kk);
+            rb[q] = *reinterpret_cast<const double2*>(B + (size_t)r * ldb + k0 + kk);
+        }
+    };
+    auto swrite = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < NLD; ++q) {
+            const int e = tid + NT * q;
+            const int r = e / (KB / 2), kk = (e % (KB / 2)) * 2;
+            As[buf][kk][r] = ra[q].x;
+            As[buf][kk + 1][r] = ra[q].y;
+            Bs[buf][kk][r] = rb[q].x;
+            Bs[buf][kk + 1][r] = rb[q].y;
+        }
+    };
+
+    dbl4 acc[TR][TC];
+#pragma unroll
+    for (int i = 0; i < TR; ++i)
+#pragma unroll
+        for (int j = 0; j < TC; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+
+    gload(0);
+    swrite(0);
+    __syncthreads();
+    const int nk = m / KB;
+    for (int kt = 0; kt < nk; ++kt) {
+        const int cur = kt & 1;
+        if (kt + 1 < nk) gload((kt + 1) * KB);
+#pragma unroll
+        for (int kk = 0; kk < KB; kk += 4) {
+            double a[TR], b[TC];
+#pragma unroll
+            for (int i = 0; i < TR; ++i) a[i] = As[cur][kk + lk][wr + 16 * i + lr];
+#pragma unroll
+            for (int j = 0; j < TC; ++j) b[j] = Bs[cur][kk + lk][wc + 16 * j + lr];
+#pragma unroll
+            for (int i = 0; i < TR; ++i)
+#pragma unroll
+                for (int j = 0; j < TC; ++j) acc[i][j] = mfma16(a[i], b[j], acc[i][j]);
+        }
+        if (kt + 1 < nk) swrite(cur ^ 1);
+        __syncthreads();
+    }
+
+#pragma unroll
+    for (int i = 0; i < TR; ++i)
+#pragma unroll
+        for (int j = 0; j < TC; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = wr + 16 * i + drow(lk, v);
+                const int col = wc + 16 * j + lr;
+                C[(size_t)row * ldc + col] -= acc[i][j][v];
+            }
+}
+
+
+}  // namespace gpr

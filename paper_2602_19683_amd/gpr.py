@@ -237,7 +237,7 @@ class Context:
 
     # ---- instrumentation --------------------------------------------------
     PROFILE_KINDS = ("potrf", "trtri", "trsm", "update", "assemble", "trsv", "matvec", "export",
-                     "adjoint", "reduce")
+                     "adjoint", "reduce", "persist")
 
     def profile(self, on=True):
         _check(self._lib.gpr_profile_enable(self._h, int(bool(on))), "gpr_profile_enable")
@@ -320,6 +320,25 @@ def adjoint_describe(M, G):
                                     nr.value, ctypes.byref(nr), ip(launches), nl.value,
                                     ctypes.byref(nl)), "gpr_adjoint_describe")
     return tasks, terms, launches
+
+
+def persist_describe(M, Mhat, mode, tile, block, workers):
+    """Host-only: the ticket order of the persistent executor (see gpr.h).
+    Returns ``(items, waits)``: int32 (N, 5) = (kind, sub, I, K, J) and
+    int64 (N, 8) = (number of waits, (counter, value) x 3, signalled counter)."""
+    lib = _lib.load()
+    n = ctypes.c_int64()
+    st = lib.gpr_persist_describe(M, Mhat, mode, tile, block, workers, None, None, 0,
+                                  ctypes.byref(n))
+    if st not in (GPR_OK, _lib.GPR_EINVAL) or n.value <= 0 and st != GPR_OK:
+        raise GPRError(st, "gpr_persist_describe")
+    items = np.zeros((n.value, 5), dtype=np.int32)
+    waits = np.zeros((n.value, 8), dtype=np.int64)
+    _check(lib.gpr_persist_describe(M, Mhat, mode, tile, block, workers,
+                                    items.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                    waits.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                    n.value, ctypes.byref(n)), "gpr_persist_describe")
+    return items, waits
 
 
 class NLML:
