@@ -25,15 +25,21 @@ FP64_PEAK_TFLOPS = 78.6     # MI355X dense FP64 (vector = matrix)
 
 # HBM bytes per dispatch of the tile-update kernel from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs scaled by a 1 GiB copy (profiles/fp64_c3_hbm_traffic.md); only
-# valid for the kernel source they were taken on.
+# valid for the kernel source they were taken on (k_update.hip + k_update_dev.h).
 UPDATE_TRAFFIC = {"k_update_sha256_16": "13f50f13ba42832e", "bytes_per_launch": 737647399}
 
 
-def update_traffic():
+def update_source_hash():
     import hashlib
-    path = os.path.join(ROOT, "paper_2602_19683_amd", "csrc", "k_update.hip")
-    h = hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
-    return UPDATE_TRAFFIC["bytes_per_launch"] if h == UPDATE_TRAFFIC["k_update_sha256_16"] else None
+    h = hashlib.sha256()
+    for f in ("k_update.hip", "k_update_dev.h"):
+        h.update(open(os.path.join(ROOT, "paper_2602_19683_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def update_traffic():
+    ok = update_source_hash() == UPDATE_TRAFFIC["k_update_sha256_16"]
+    return UPDATE_TRAFFIC["bytes_per_launch"] if ok else None
 
 
 def log(*a):
@@ -128,6 +134,46 @@ def mixed_runs(ctx, K, step, mean64, cov64, ms64, flops, args, log):
     return out
 
 
+def persistent_run(Xd, yd, Xsd, h, tile, mean64, cov64, ms64, flops, args, log):
+    """The same FP64 step with the persistent executor (one launch per sweep):
+    time per step, and whether mean and covariance equal the stream
+    executor's bit for bit."""
+    import torch
+    from paper_2602_19683_amd import GPR_EXEC_PERSISTENT, Context
+    ctx = Context(0, executor=GPR_EXEC_PERSISTENT)
+    mean = torch.empty_like(mean64)
+    cov = torch.empty_like(cov64)
+    K = None
+    for _ in range(max(args.warmup, 1)):
+        _, _, K, _ = ctx.fit_predict(Xd, yd, Xsd, h, tile, "fp64", K=K, mean=mean, cov=cov,
+                                     ir_stats=True)
+        ctx.sync()
+    ctx.profile(True)
+    ctx.profile_read(reset=True)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        ctx.fit_predict(Xd, yd, Xsd, h, tile, "fp64", K=K, mean=mean, cov=cov, ir_stats=True)
+    e1.record()
+    torch.cuda.synchronize()
+    ctx.sync()
+    ms = e0.elapsed_time(e1) / args.steps
+    prof = ctx.profile_read(reset=True)
+    ctx.profile(False)
+    nl, tms, fl, _ = prof["persist"]
+    out = {"ms_per_step": round(ms, 4), "value": round(flops / (ms * 1e-3) / 1e9, 2),
+           "speedup_vs_streams": round(ms64 / ms, 3),
+           "sweep_kernel_ms": round(tms / max(nl, 1), 4),
+           "sweep_kernel_tflops": round(fl / (tms * 1e-3) / 1e12, 3) if tms else None,
+           "bitwise_equal_to_streams": bool(torch.equal(mean, mean64) and torch.equal(cov, cov64))}
+    K.free()
+    ctx.close()
+    log(f"persistent executor: {out}")
+    return out
+
+
 def nlml_run(ctx, args, log):
     """The gradient workload: NLML and its gradient in (l, v, sigma^2) at
     n = 8192, D = 8, tile 256, from (0.3, 2.0, 0.5): time per evaluation
@@ -183,6 +229,8 @@ def main():
     ap.add_argument("--no-nlml", action="store_true",
                     help="skip the NLML-gradient timing (n = 8192, tile 256) after the line")
     ap.add_argument("--no-check", action="store_true")
+    ap.add_argument("--no-persistent", action="store_true",
+                    help="skip the persistent-executor timing of the same FP64 step")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run one device-to-device copy of MIB MiB (for HBM counter scaling)")
     args = ap.parse_args()
@@ -265,6 +313,9 @@ def main():
     if not args.no_check:
         errors = error_check(ctx, K, X, y, Xs, mean, h, Xd, yd)
         log(f"errors: {errors}")
+    persistent = None
+    if not args.no_persistent and args.precision == "fp64" and args.path == "fused":
+        persistent = persistent_run(Xd, yd, Xsd, h, tile, mean, cov, ms, flops, args, log)
     mixed = None
     if not args.no_mixed and args.precision == "fp64":
         mixed = mixed_runs(ctx, K, step, mean, cov, ms, flops, args, log)
@@ -292,6 +343,7 @@ def main():
         "cpu_baseline": cpu,
         "errors": errors,
         "mixed": mixed,
+        "persistent_executor": persistent,
         "nlml_grad": nlml,
         "phases_ms_per_step": {k: round(v[1] / args.steps, 4) for k, v in prof.items()},
     }

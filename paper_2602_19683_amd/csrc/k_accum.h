@@ -6,7 +6,8 @@
 // B[j * ldb + k] (32 rows of B); otherwise B(k, j) = B[k * ldb + j]. K is a
 // multiple of KC. Chunks of KC columns go through LDS k-major (the 16 lanes
 // sharing a k read consecutive words), double-buffered. All 256 threads must
-// call it; As and Bs are LDS arrays [2][KC][32 + 4].
+// call it (tid: the thread's index, 0..255); As and Bs are LDS arrays
+// [2][KC][32 + 4].
 #pragma once
 
 #include "k_common.h"
@@ -16,12 +17,11 @@ namespace gpr {
 template <bool NT, int KC>
 __device__ inline dbl4 accum32(const double* __restrict__ A, int lda, const double* __restrict__ B,
                                int ldb, int K, dbl4 acc, double sign, double (*As)[KC][36],
-                               double (*Bs)[KC][36])
+                               double (*Bs)[KC][36], int tid)
 {
     static_assert(KC % 16 == 0, "chunk must hold whole double2 loads");
     constexpr int NL = KC / 16;       // double2 loads per thread per operand
     constexpr int CPR = KC / 2;       // double2 per 32-row operand row (KC columns)
-    const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int lr = lane & 15, lk = lane >> 4;
     const int qi = wave >> 1, qj = wave & 1;

@@ -38,7 +38,8 @@ __global__ __launch_bounds__(256) void k_potrf_f64(double* __restrict__ A, int l
                                                    int* __restrict__ err)
 {
     __shared__ PotrfLds sh;
-    potrf_panel(A, lda, m, Tinv, ldt, info, col_base, flags, epoch, err, blockIdx.x, sh);
+    potrf_panel(A, lda, m, Tinv, ldt, info, col_base, flags, epoch, err, blockIdx.x, sh,
+                threadIdx.x);
 }
 
 __global__ __launch_bounds__(256) void k_trtri_f64(TileMat K, double* __restrict__ Tall)
@@ -67,7 +68,7 @@ __global__ __launch_bounds__(256) void k_trtri_f64(TileMat K, double* __restrict
         dbl4 acc = {0.0, 0.0, 0.0, 0.0};
         acc = accum32<false, KC>(L + (size_t)r * NB * lda + c * NB, lda,
                              Tinv + (size_t)c * NB * ldt + c * NB, ldt, NB * (r - c), acc, 1.0,
-                             As, Bs);
+                             As, Bs, tid);
 #pragma unroll
         for (int v = 0; v < 4; ++v) Sacc[16 * qi + drow(lk, v)][16 * qj + lr] = acc[v];
         __syncthreads();

@@ -178,11 +178,12 @@ struct PotrfLds {
     double dv[NB];
 };
 
-// Row panel w of the POTRF of the m x m tile A (see k_potrf.hip). 256 threads.
+// Row panel w of the POTRF of the m x m tile A (see k_potrf.hip). 256 threads;
+// tid is the thread's index (0..255).
 __device__ inline void potrf_panel(double* __restrict__ A, int lda, int m, double* __restrict__ Tinv,
                                    int ldt, int* __restrict__ info, int64_t col_base,
                                    unsigned* __restrict__ flags, unsigned epoch,
-                                   int* __restrict__ err, int w, PotrfLds& sh)
+                                   int* __restrict__ err, int w, PotrfLds& sh, int tid)
 {
     double (*As)[KC][SP] = sh.As;
     double (*Bs)[KC][SP] = sh.Bs;
@@ -190,7 +191,6 @@ __device__ inline void potrf_panel(double* __restrict__ A, int lda, int m, doubl
     double (*Si)[NB + 1] = sh.Si;
     double* dv = sh.dv;
     const int P = m / NB;
-    const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int lr = lane & 15, lk = lane >> 4;
     const int qi = wave >> 1, qj = wave & 1;
@@ -213,7 +213,8 @@ __device__ inline void potrf_panel(double* __restrict__ A, int lda, int m, doubl
 #pragma unroll
         for (int v = 0; v < 4; ++v)
             acc[v] = Aw[(size_t)(16 * qi + drow(lk, v)) * lda + NB * q + 16 * qj + lr];
-        acc = accum32<true, KC>(Aw, lda, A + (size_t)NB * q * lda, lda, NB * q, acc, -1.0, As, Bs);
+        acc = accum32<true, KC>(Aw, lda, A + (size_t)NB * q * lda, lda, NB * q, acc, -1.0, As, Bs,
+                                tid);
 #pragma unroll
         for (int v = 0; v < 4; ++v) Sacc[16 * qi + drow(lk, v)][16 * qj + lr] = acc[v];
         if (tid == 0 && !wait_flag(diag_done + q, epoch, err)) flag_error(err);

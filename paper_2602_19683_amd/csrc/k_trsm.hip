@@ -26,7 +26,7 @@ __global__ __launch_bounds__(256) void k_trsm_f64(const TrsmTask* __restrict__ t
     const int strips = m / 32;
     const int lid = xcd_remap(blockIdx.x, gridDim.x);
     const int t = lid / strips, s = lid - t * strips;
-    trsm_strip(tasks[t], s, m, sh);
+    trsm_strip(tasks[t], s, m, sh, threadIdx.x);
 }
 
 hipError_t launch_trsm_f64(const TrsmTask* d_tasks, int ntask, int m, hipStream_t s)

@@ -20,8 +20,8 @@ struct TrsmLds {
     double Sacc[32][33];
 };
 
-// Strip s (rows 32 s .. 32 s + 31) of the task; 256 threads.
-__device__ inline void trsm_strip(const TrsmTask& tk, int s, int m, TrsmLds& sh)
+// Strip s (rows 32 s .. 32 s + 31) of the task; 256 threads, tid = 0..255.
+__device__ inline void trsm_strip(const TrsmTask& tk, int s, int m, TrsmLds& sh, int tid)
 {
     double (*As)[TK][36] = sh.As;
     double (*Bs)[TK][36] = sh.Bs;
@@ -29,7 +29,6 @@ __device__ inline void trsm_strip(const TrsmTask& tk, int s, int m, TrsmLds& sh)
     double* __restrict__ B = tk.B + (size_t)s * 32 * tk.ldb;
     const int ldb = tk.ldb, ldl = tk.ldl, ldd = tk.ldd;
     float* __restrict__ B32 = tk.B32 ? tk.B32 + (size_t)s * 32 * m : nullptr;
-    const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int lr = lane & 15, lk = lane >> 4;
     const int qi = wave >> 1, qj = wave & 1;
@@ -41,7 +40,7 @@ __device__ inline void trsm_strip(const TrsmTask& tk, int s, int m, TrsmLds& sh)
         for (int v = 0; v < 4; ++v)
             acc[v] = B[(size_t)(16 * qi + drow(lk, v)) * ldb + c0 + 16 * qj + lr];
         // minus the finished blocks X[:, 0:c0] times rows c0.. of L_JJ (transposed)
-        acc = accum32<true, TK>(B, ldb, tk.L + (size_t)c0 * ldl, ldl, c0, acc, -1.0, As, Bs);
+        acc = accum32<true, TK>(B, ldb, tk.L + (size_t)c0 * ldl, ldl, c0, acc, -1.0, As, Bs, tid);
 #pragma unroll
         for (int v = 0; v < 4; ++v) Sacc[16 * qi + drow(lk, v)][16 * qj + lr] = acc[v];
         __syncthreads();

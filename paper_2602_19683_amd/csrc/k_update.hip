@@ -33,7 +33,7 @@ __global__ __launch_bounds__(WR * WC * 64, WR * WC / 2) void k_update_f64(
     const int bi = sub / nb, bj = sub - bi * nb;
     const UpdateTask tk = tasks[t];
     if ((tk.flags & TASK_DIAG) && bj > bi) return;
-    update_block<BM, WR, WC>(tk, bi, bj, m, sh);
+    update_block<BM, WR, WC>(tk, bi, bj, m, sh, threadIdx.x);
 }
 
 hipError_t launch_update_f64(const UpdateTask* d_tasks, int ntask, int m, hipStream_t s)

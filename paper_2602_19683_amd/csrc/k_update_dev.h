@@ -14,9 +14,11 @@ struct UpdLds {
     double Bs[2][16][BM + 4];
 };
 
-// Block (bi, bj) of the task, WR x WC waves (WR * WC * 64 threads).
+// Block (bi, bj) of the task, WR x WC waves (WR * WC * 64 threads, tid the
+// thread's index).
 template <int BM, int WR, int WC>
-__device__ inline void update_block(const UpdateTask& tk, int bi, int bj, int m, UpdLds<BM>& sh)
+__device__ inline void update_block(const UpdateTask& tk, int bi, int bj, int m, UpdLds<BM>& sh,
+                                    int tid)
 {
     constexpr int NT = WR * WC * 64;  // threads
     constexpr int KB = 16;
@@ -33,7 +35,6 @@ __device__ inline void update_block(const UpdateTask& tk, int bi, int bj, int m,
     double* __restrict__ C = tk.C + (size_t)bi * BM * tk.ldc + (size_t)bj * BM;
     const int lda = tk.lda, ldb = tk.ldb, ldc = tk.ldc;
 
-    const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
     const int wr = (wave / WC) * (BM / WR), wc = (wave % WC) * (BM / WC);
     const int lr = lane & 15, lk = lane >> 4;
