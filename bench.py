@@ -26,7 +26,7 @@ FP64_PEAK_TFLOPS = 78.6     # MI355X dense FP64 (vector = matrix)
 # HBM bytes per dispatch of the tile-update kernel from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs scaled by a 1 GiB copy (profiles/fp64_c3_hbm_traffic.md); only
 # valid for the kernel source they were taken on (k_update.hip + k_update_dev.h).
-UPDATE_TRAFFIC = {"k_update_sha256_16": "13f50f13ba42832e", "bytes_per_launch": 737647399}
+UPDATE_TRAFFIC = {"k_update_sha256_16": "a4f0af6b795ae81e", "bytes_per_launch": 728422018}
 
 
 def update_source_hash():
@@ -231,6 +231,8 @@ def main():
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-persistent", action="store_true",
                     help="skip the persistent-executor timing of the same FP64 step")
+    ap.add_argument("--executor", default="streams", choices=["streams", "persistent"],
+                    help="executor of the timed line (persistent: one launch per sweep)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run one device-to-device copy of MIB MiB (for HBM counter scaling)")
     args = ap.parse_args()
@@ -251,7 +253,7 @@ def main():
         log(f"copied {args.calibrate_copy} MiB (read {args.calibrate_copy} MiB, write {args.calibrate_copy} MiB)")
         return
     from gpr_inputs import DEFAULT_HYPER, nfir_train_test
-    from paper_2602_19683_amd import Context
+    from paper_2602_19683_amd import GPR_EXEC_PERSISTENT, GPR_EXEC_STREAMS, Context
 
     n, ns, tile, D = args.n, args.n_test, args.tile, 8
     h = DEFAULT_HYPER
@@ -262,7 +264,9 @@ def main():
     Xd, yd, Xsd = dev(X), dev(y), dev(Xs)
     mean = torch.empty(ns, dtype=torch.float64, device="cuda:0")
     cov = torch.empty(ns, ns, dtype=torch.float64, device="cuda:0")
-    ctx = Context(0, n_streams=args.streams)
+    persistent_line = args.executor == "persistent"
+    ctx = Context(0, n_streams=args.streams,
+                  executor=GPR_EXEC_PERSISTENT if persistent_line else GPR_EXEC_STREAMS)
     K = ctx.assemble(Xd, h, tile)
 
     def step(prec=args.precision, out_mean=mean, out_cov=cov):
@@ -301,11 +305,14 @@ def main():
 
     flops = path_flops(n, ns)
     value = flops / (ms * 1e-3) / 1e9
-    nl, tms, fl, _ = prof["update"]
+    nl, tms, fl, _ = prof["persist" if persistent_line else "update"]
     achieved = fl / (tms * 1e-3) / 1e12 if tms else 0.0
-    roofline = {"bound": "mfma", "kernel": "k_update_f64 (GEMM/SYRK tile updates)",
+    roofline = {"bound": "mfma",
+                "kernel": "k_persist (the whole sweep: POTRF panels, TRSM strips, update blocks)"
+                          if persistent_line else "k_update_f64 (GEMM/SYRK tile updates)",
                 "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": update_traffic(),
+                "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
+                "traffic": None if persistent_line else update_traffic(),
                 "traffic_unit": "bytes per launch",
                 "avg_launch_ms": round(tms / max(nl, 1), 4),
                 "flops_per_launch": round(fl / max(nl, 1), 1)}
@@ -314,7 +321,8 @@ def main():
         errors = error_check(ctx, K, X, y, Xs, mean, h, Xd, yd)
         log(f"errors: {errors}")
     persistent = None
-    if not args.no_persistent and args.precision == "fp64" and args.path == "fused":
+    if (not args.no_persistent and not persistent_line and args.precision == "fp64"
+            and args.path == "fused"):
         persistent = persistent_run(Xd, yd, Xsd, h, tile, mean, cov, ms, flops, args, log)
     mixed = None
     if not args.no_mixed and args.precision == "fp64":
@@ -337,6 +345,7 @@ def main():
                    "n": n, "n_test": ns, "D": D, "tile": tile, "precision": args.precision,
                    "entry": "gpr_fit_predict" if args.path == "fused" else
                             "gpr_assemble + gpr_cholesky + gpr_predict",
+                   "executor": args.executor,
                    "parallelism": "single GPU"},
         "pct_fp64_peak": round(100 * value / (FP64_PEAK_TFLOPS * 1e3), 2),
         "roofline": roofline,
