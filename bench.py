@@ -174,6 +174,38 @@ def persistent_run(Xd, yd, Xsd, h, tile, mean64, cov64, ms64, flops, args, log):
     return out
 
 
+def variants_run(ctx, K, Xd, yd, Xsd, h, tile, args, log):
+    """The prediction variants of the same fit (FP64, one fused call each):
+    mean only (no test rows swept) and mean + predictive variances (V^T
+    formed, the test block skipped), time per call."""
+    import torch
+    ns = Xsd.shape[0]
+    mean = torch.empty(ns, dtype=torch.float64, device="cuda:0")
+    var = torch.empty(ns, dtype=torch.float64, device="cuda:0")
+    calls = {
+        "mean_only": lambda: ctx.fit_predict(Xd, yd, Xsd, h, tile, "fp64", full_cov=False, K=K,
+                                             mean=mean),
+        "mean_and_variance": lambda: ctx.fit_predict_var(Xd, yd, Xsd, h, tile, "fp64", K=K,
+                                                         mean=mean, var=var),
+    }
+    out = {}
+    for name, call in calls.items():
+        call()
+        ctx.sync()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            call()
+        e1.record()
+        torch.cuda.synchronize()
+        ctx.sync()
+        out[name + "_ms"] = round(e0.elapsed_time(e1) / args.steps, 4)
+    log(f"variants: {out}")
+    return out
+
+
 def nlml_run(ctx, args, log):
     """The gradient workload: NLML and its gradient in (l, v, sigma^2) at
     n = 8192, D = 8, tile 256, from (0.3, 2.0, 0.5): time per evaluation
@@ -231,6 +263,8 @@ def main():
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-persistent", action="store_true",
                     help="skip the persistent-executor timing of the same FP64 step")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the mean-only and mean + variance timings")
     ap.add_argument("--executor", default="streams", choices=["streams", "persistent"],
                     help="executor of the timed line (persistent: one launch per sweep)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -324,6 +358,9 @@ def main():
     if (not args.no_persistent and not persistent_line and args.precision == "fp64"
             and args.path == "fused"):
         persistent = persistent_run(Xd, yd, Xsd, h, tile, mean, cov, ms, flops, args, log)
+    variants = None
+    if not args.no_variants and args.path == "fused":
+        variants = variants_run(ctx, K, Xd, yd, Xsd, h, tile, args, log)
     mixed = None
     if not args.no_mixed and args.precision == "fp64":
         mixed = mixed_runs(ctx, K, step, mean, cov, ms, flops, args, log)
@@ -353,6 +390,7 @@ def main():
         "errors": errors,
         "mixed": mixed,
         "persistent_executor": persistent,
+        "prediction_variants": variants,
         "nlml_grad": nlml,
         "phases_ms_per_step": {k: round(v[1] / args.steps, 4) for k, v in prof.items()},
     }

@@ -181,6 +181,24 @@ int gpr_fit_predict(gpr_ctx* ctx, const double* X, const double* y, int64_t n,
                     double* mean, double* cov, int32_t* info_dev,
                     gpr_ir_stats* ir, void* stream);
 
+/* gpr_predict and gpr_fit_predict with the predictive variances as a third
+ * output: var (device, n_test, or NULL) receives diag of the posterior
+ * covariance, k(x*_i, x*_i) - ||V_{:,i}||^2 (Sec. 4.1: its diagonal holds the
+ * predictive variances). With cov == NULL and var != NULL only V^T is formed:
+ * the sweep skips the updates of the test block (the n_test^2 n flops of
+ * eq. (3)) and the variances are row sums of squares of V^T. With both,
+ * var is the diagonal of cov (bitwise). Other arguments and errors as in
+ * gpr_predict / gpr_fit_predict, which are these calls with var == NULL. */
+int gpr_predict_var(gpr_ctx* ctx, gpr_tiled* L, const double* X, const double* y,
+                    int64_t n, const double* Xs, int64_t n_test, int32_t D,
+                    gpr_hyper h, double* mean, double* cov, double* var,
+                    gpr_ir_stats* ir, void* stream);
+int gpr_fit_predict_var(gpr_ctx* ctx, const double* X, const double* y, int64_t n,
+                        const double* Xs, int64_t n_test, int32_t D, gpr_hyper h,
+                        int32_t tile, gpr_precision prec, gpr_tiled** K_inout,
+                        double* mean, double* cov, double* var, int32_t* info_dev,
+                        gpr_ir_stats* ir, void* stream);
+
 /* x = K^{-1} b through the factor: forward substitution L beta = b, then
  * backward substitution L^T x = beta (the solve recipe after eq. (2)).
  * L: handle holding a factor; b, x: device vectors of length n (may alias).
@@ -264,7 +282,8 @@ const char* gpr_strerror(int status);
  * Mhat test tile rows without running anything, so the schedule can be
  * checked on a machine without a GPU.
  * mode: 0 = Cholesky only, 1 = covariance solve with a given factor
- * (rows M..M+Mhat-1 only), 2 = both in one sweep.
+ * (rows M..M+Mhat-1 only), 2 = both in one sweep, 3 and 4 = modes 1 and 2
+ * without the updates of the test block (only V^T: predictive variances).
  * tasks: host array of 5 int32 per task: kind (0 POTRF, 1 TRSM, 2 SYRK,
  * 3 GEMM), I, K, J, launch index. Tile (I, K) is the one written; for POTRF
  * I = K = J, for TRSM K = J. Rows I >= M are test rows.

@@ -45,6 +45,11 @@ SIGNATURES = {
     "gpr_fit_predict": (ctypes.c_int, [_vp, _vp, _vp, _i64, _vp, _i64, _i32, Hyper, _i32,
                                        ctypes.c_int, ctypes.POINTER(_vp), _vp, _vp, _vp,
                                        ctypes.POINTER(IRStats), _vp]),
+    "gpr_predict_var": (ctypes.c_int, [_vp, _vp, _vp, _vp, _i64, _vp, _i64, _i32, Hyper, _vp,
+                                       _vp, _vp, ctypes.POINTER(IRStats), _vp]),
+    "gpr_fit_predict_var": (ctypes.c_int, [_vp, _vp, _vp, _i64, _vp, _i64, _i32, Hyper, _i32,
+                                           ctypes.c_int, ctypes.POINTER(_vp), _vp, _vp, _vp,
+                                           _vp, ctypes.POINTER(IRStats), _vp]),
     "gpr_solve": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "gpr_nlml_grad": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, Hyper, _i32, ctypes.c_int, _vp,
                                      _vp, _vp, _vp]),

@@ -309,7 +309,7 @@ SweepPlan plan_sweep(const gpr_ctx* ctx, const SweepMats& X, int mode, DescBuffe
 int run_persist(gpr_ctx* ctx, const SweepMats& X, int mode, hipStream_t s)
 {
     const int m = X.m, M = X.M, bm = persist_block(m);
-    const int Mhat = mode == SWEEP_CHOLESKY ? 0 : X.Mhat;
+    const int Mhat = sweep_test_rows(mode) ? X.Mhat : 0;
     if (ctx->p_workers <= 0 || ctx->p_bm != bm) {
         ctx->p_workers = persist_workers(bm);
         ctx->p_bm = bm;
@@ -333,12 +333,15 @@ int run_persist(gpr_ctx* ctx, const SweepMats& X, int mode, hipStream_t s)
     if (rc) return rc;
     // flops of the tile tasks (Fig. 1 counts: POTRF m^3/3, TRSM m^3, SYRK m^3,
     // GEMM 2 m^3)
+    const bool block = sweep_test_block(mode);
     double tasks = 0.0;
     for (int J = 0; J < M; ++J) {
         const int I0 = g.factor ? J + 1 : M;
         const double rows = g.T - I0;  // TRSM tasks of column J
         double upd = 0.0;              // update flops of step J in units of m^3
-        for (int I = I0; I < g.T; ++I) upd += 2.0 * (I - J) - 1.0;  // GEMMs 2, SYRK 1
+        for (int I = I0; I < g.T; ++I)
+            for (int K = J + 1; K <= I; ++K)
+                if (block || K < M) upd += K == I ? 1.0 : 2.0;  // SYRK 1, GEMM 2
         tasks += (g.factor ? 1.0 / 3.0 : 0.0) + rows + upd;
     }
     const unsigned epoch0 = ctx->epoch + 1;
@@ -770,14 +773,15 @@ constexpr int RETRY_HIGHER = 100;
 // the stream once per step.
 int predict_impl(gpr_ctx* ctx, gpr_tiled* L, const double* X, const double* y, int64_t n,
                  const double* Xs, int64_t n_test, int32_t D, const gpr_hyper& h, double* mean,
-                 double* cov, int32_t* info_dev, hipStream_t s, bool fused, int prec,
-                 gpr_ir_stats* ir)
+                 double* cov, double* var, int32_t* info_dev, hipStream_t s, bool fused,
+                 int prec, gpr_ir_stats* ir)
 {
     const int m = L->m, M = L->M;
     const int Mhat = (int)((n_test + m - 1) / m);
     const size_t npad = (size_t)M * m;
     const size_t vec_bytes = 6 * npad * sizeof(double) + 256;
-    const size_t v_bytes = cov ? (size_t)Mhat * M * m * m * sizeof(double) : 0;
+    const bool rows = cov || var;  // the test rows V^T are needed
+    const size_t v_bytes = rows ? (size_t)Mhat * M * m * m * sizeof(double) : 0;
     const size_t s_bytes = cov ? (size_t)Mhat * (Mhat + 1) / 2 * m * m * sizeof(double) : 0;
     const size_t mv_bytes = (size_t)matvec_chunks(n_test, n) * n_test * sizeof(double);
     int rc = ensure_device_bytes(&ctx->d_ws, &ctx->ws_cap,
@@ -803,10 +807,12 @@ int predict_impl(gpr_ctx* ctx, gpr_tiled* L, const double* X, const double* y, i
 
     DescBuffer db;
     SweepMats SM{kmat(L), L->tinv, TileMat{Vb, m, 1, M}, TileMat{Sb, m, 0, 0}, M,
-                 cov ? Mhat : 0, m, fprec};
+                 rows ? Mhat : 0, m, fprec};
     SweepPlan PP;
-    const int mode = fused ? (cov ? SWEEP_FUSED : SWEEP_CHOLESKY) : SWEEP_PREDICT;
-    if (fused || cov) PP = plan_sweep(ctx, SM, mode, db);
+    // the full covariance needs the test block; variances alone only V^T
+    const int mode = fused ? (cov ? SWEEP_FUSED : (var ? SWEEP_FUSED_V : SWEEP_CHOLESKY))
+                           : (cov ? SWEEP_PREDICT : SWEEP_PREDICT_V);
+    if (fused || rows) PP = plan_sweep(ctx, SM, mode, db);
     rc = db.upload(ctx, s);
     if (rc) return rc;
 
@@ -814,16 +820,17 @@ int predict_impl(gpr_ctx* ctx, gpr_tiled* L, const double* X, const double* y, i
         rc = save_kcopy(L, s);
         if (rc) return rc;
     }
-    if (cov) {
+    if (rows) {
         // K_{X*,X} tiles (to become V^T) and lower tiles of K_{X*,X*}; no noise
         ProfScope ps(ctx, s, PK_ASSEMBLE, 0.0, (double)(v_bytes + s_bytes));
         HIP_TRY(launch_assemble(SM.V, Mhat, Xs, n_test, X, n, D, h.lengthscale,
                                 h.vertical_variance, h.noise_variance, false, false, s));
-        HIP_TRY(launch_assemble(SM.S, Mhat, Xs, n_test, Xs, n_test, D, h.lengthscale,
-                                h.vertical_variance, h.noise_variance, false, false, s));
+        if (cov)
+            HIP_TRY(launch_assemble(SM.S, Mhat, Xs, n_test, Xs, n_test, D, h.lengthscale,
+                                    h.vertical_variance, h.noise_variance, false, false, s));
     }
     if (fused) HIP_TRY(launch_set_int(ctx->d_info, 0, s));
-    if (fused || cov) {
+    if (fused || rows) {
         rc = run_sweep(ctx, SM, PP, db, s);
         if (rc) return rc;
     }
@@ -901,6 +908,15 @@ int predict_impl(gpr_ctx* ctx, gpr_tiled* L, const double* X, const double* y, i
         ProfScope ps(ctx, s, PK_EXPORT, 0.0, (double)n_test * n_test * sizeof(double));
         HIP_TRY(launch_tiled_to_dense(SM.S, n_test, cov, n_test, true, s));
     }
+    if (var) {
+        // the diagonal of the covariance when it was formed, else from V^T
+        ProfScope ps(ctx, s, PK_EXPORT, 0.0,
+                     cov ? 16.0 * n_test : (double)n_test * M * m * sizeof(double));
+        if (cov)
+            HIP_TRY(launch_tile_diag(SM.S, n_test, var, s));
+        else
+            HIP_TRY(launch_rowsq_var(SM.V, M, n_test, h.vertical_variance, var, s));
+    }
     return GPR_OK;
 }
 
@@ -908,9 +924,9 @@ int predict_impl(gpr_ctx* ctx, gpr_tiled* L, const double* X, const double* y, i
 
 extern "C" {
 
-int gpr_predict(gpr_ctx* ctx, gpr_tiled* L, const double* X, const double* y, int64_t n,
-                const double* Xs, int64_t n_test, int32_t D, gpr_hyper h, double* mean,
-                double* cov, gpr_ir_stats* ir, void* stream)
+int gpr_predict_var(gpr_ctx* ctx, gpr_tiled* L, const double* X, const double* y, int64_t n,
+                    const double* Xs, int64_t n_test, int32_t D, gpr_hyper h, double* mean,
+                    double* cov, double* var, gpr_ir_stats* ir, void* stream)
 {
     if (!ctx || !L || !X || !y || n < 1 || D < 1 || n_test < 0 || !valid_hyper(h))
         return GPR_EINVAL;
@@ -920,15 +936,23 @@ int gpr_predict(gpr_ctx* ctx, gpr_tiled* L, const double* X, const double* y, in
     hipStream_t s = static_cast<hipStream_t>(stream);
     int rc = begin_call(ctx, s);
     if (rc) return rc;
-    rc = predict_impl(ctx, L, X, y, n, Xs, n_test, D, h, mean, cov, nullptr, s, false, L->prec, ir);
+    rc = predict_impl(ctx, L, X, y, n, Xs, n_test, D, h, mean, cov, var, nullptr, s, false,
+                      L->prec, ir);
     if (rc) return rc;
     return end_call(ctx, s);
 }
 
-int gpr_fit_predict(gpr_ctx* ctx, const double* X, const double* y, int64_t n, const double* Xs,
-                    int64_t n_test, int32_t D, gpr_hyper h, int32_t tile, gpr_precision prec,
-                    gpr_tiled** K_inout, double* mean, double* cov, int32_t* info_dev,
-                    gpr_ir_stats* ir, void* stream)
+int gpr_predict(gpr_ctx* ctx, gpr_tiled* L, const double* X, const double* y, int64_t n,
+                const double* Xs, int64_t n_test, int32_t D, gpr_hyper h, double* mean,
+                double* cov, gpr_ir_stats* ir, void* stream)
+{
+    return gpr_predict_var(ctx, L, X, y, n, Xs, n_test, D, h, mean, cov, nullptr, ir, stream);
+}
+
+int gpr_fit_predict_var(gpr_ctx* ctx, const double* X, const double* y, int64_t n,
+                        const double* Xs, int64_t n_test, int32_t D, gpr_hyper h, int32_t tile,
+                        gpr_precision prec, gpr_tiled** K_inout, double* mean, double* cov,
+                        double* var, int32_t* info_dev, gpr_ir_stats* ir, void* stream)
 {
     if (!ctx || !X || !y || !K_inout || n < 1 || D < 1 || n_test < 1 || !Xs || !mean ||
         !valid_tile(tile) || !valid_hyper(h) || !valid_prec(prec, tile))
@@ -942,7 +966,8 @@ int gpr_fit_predict(gpr_ctx* ctx, const double* X, const double* y, int64_t n, c
         rc = begin_call(ctx, s);
         if (rc) return rc;
         gpr_tiled* K = *K_inout;
-        rc = predict_impl(ctx, K, X, y, n, Xs, n_test, D, h, mean, cov, info_dev, s, true, p, ir);
+        rc = predict_impl(ctx, K, X, y, n, Xs, n_test, D, h, mean, cov, var, info_dev, s, true, p,
+                          ir);
         if (rc == RETRY_HIGHER && p != GPR_FP64) {
             rc = end_call(ctx, s);
             if (rc) return rc;
@@ -952,6 +977,15 @@ int gpr_fit_predict(gpr_ctx* ctx, const double* X, const double* y, int64_t n, c
         if (ir) ir->fallback_precision = p;
         return end_call(ctx, s);
     }
+}
+
+int gpr_fit_predict(gpr_ctx* ctx, const double* X, const double* y, int64_t n, const double* Xs,
+                    int64_t n_test, int32_t D, gpr_hyper h, int32_t tile, gpr_precision prec,
+                    gpr_tiled** K_inout, double* mean, double* cov, int32_t* info_dev,
+                    gpr_ir_stats* ir, void* stream)
+{
+    return gpr_fit_predict_var(ctx, X, y, n, Xs, n_test, D, h, tile, prec, K_inout, mean, cov,
+                               nullptr, info_dev, ir, stream);
 }
 
 int gpr_solve(gpr_ctx* ctx, gpr_tiled* L, const double* b, double* x, void* stream)

@@ -176,6 +176,12 @@ hipError_t launch_nlml_finish(const TileMat& L, const double* beta, int64_t n,
                               const int* info, double* out_nlml, double* out_grad3,
                               hipStream_t s);
 
+// var_i = v - sum_j V^T_ij^2 over the M tiles of test-tile row i / m of V
+// (layout 1), i < n_test; and out_i = S_ii for the lower-tiled S, i < n.
+hipError_t launch_rowsq_var(const TileMat& V, int M, int64_t n_test, double v, double* var,
+                            hipStream_t s);
+hipError_t launch_tile_diag(const TileMat& S, int64_t n, double* out, hipStream_t s);
+
 hipError_t launch_set_int(int* p, int value, hipStream_t s);
 hipError_t launch_copy_f64(const double* src, double* dst, int64_t n, int64_t n_pad,
                            hipStream_t s);
@@ -186,7 +192,15 @@ hipError_t launch_copy_f64(const double* src, double* dst, int64_t n, int64_t n_
 
 enum TaskKind : int { K_POTRF = 0, K_TRSM = 1, K_SYRK = 2, K_GEMM = 3 };
 enum LaunchKind : int { LK_POTRF = 0, LK_TRSM = 1, LK_UPDATE = 2 };
-enum SweepMode : int { SWEEP_CHOLESKY = 0, SWEEP_PREDICT = 1, SWEEP_FUSED = 2 };
+// SWEEP_PREDICT_V / SWEEP_FUSED_V: as SWEEP_PREDICT / SWEEP_FUSED without the
+// updates of the test block (only V^T is formed: predictive variances).
+enum SweepMode : int { SWEEP_CHOLESKY = 0, SWEEP_PREDICT = 1, SWEEP_FUSED = 2,
+                       SWEEP_PREDICT_V = 3, SWEEP_FUSED_V = 4 };
+
+inline bool sweep_factors(int mode) { return mode == SWEEP_CHOLESKY || mode == SWEEP_FUSED ||
+                                             mode == SWEEP_FUSED_V; }
+inline bool sweep_test_rows(int mode) { return mode != SWEEP_CHOLESKY; }
+inline bool sweep_test_block(int mode) { return mode == SWEEP_PREDICT || mode == SWEEP_FUSED; }
 
 struct SchedTask {
     int kind, I, K, J;

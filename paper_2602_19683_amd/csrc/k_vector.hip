@@ -289,4 +289,52 @@ hipError_t launch_copy_f64(const double* src, double* dst, int64_t n, int64_t n_
     return hipGetLastError();
 }
 
+// Predictive variances without the covariance matrix (eq. (3), diagonal):
+// var_i = k(x*_i, x*_i) - sum_j (V^T)_{ij}^2 with k(x, x) = v (the test block
+// is noise-free). One wave per test row; each lane sums its columns of every
+// tile in order, then a fixed butterfly: bitwise reproducible.
+__global__ __launch_bounds__(256) void k_rowsq_var(TileMat V, int M, int64_t n_test, double v,
+                                                   double* __restrict__ var)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= n_test) return;
+    const int m = V.m;
+    const int I = (int)(i / m), r = (int)(i % m);
+    double acc = 0.0;
+    for (int J = 0; J < M; ++J) {
+        const double* row = tile_ptr(V, I, J) + (size_t)r * m;
+        for (int c = lane; c < m; c += 64) acc = fma(row[c], row[c], acc);
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) var[i] = v - acc;
+}
+
+// The diagonal of a lower-tiled matrix (the predictive variances when the
+// full covariance is formed): out_i = S_ii, i < n.
+__global__ void k_tile_diag(TileMat S, int64_t n, double* __restrict__ out)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int m = S.m;
+    const int I = (int)(i / m), r = (int)(i % m);
+    out[i] = tile_ptr(S, I, I)[(size_t)r * m + r];
+}
+
+hipError_t launch_rowsq_var(const TileMat& V, int M, int64_t n_test, double v, double* var,
+                            hipStream_t s)
+{
+    if (n_test <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rowsq_var, dim3((unsigned)((n_test + 3) / 4)), dim3(256), 0, s, V, M,
+                       n_test, v, var);
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_diag(const TileMat& S, int64_t n, double* out, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_tile_diag, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, S, n, out);
+    return hipGetLastError();
+}
+
 }  // namespace gpr

@@ -39,8 +39,8 @@ PGeom persist_geom(int M, int Mhat, int mode, int m, int bm)
 {
     PGeom g;
     g.M = M;
-    g.factor = (mode == SWEEP_CHOLESKY || mode == SWEEP_FUSED) ? 1 : 0;
-    g.T = M + (mode == SWEEP_CHOLESKY ? 0 : Mhat);
+    g.factor = sweep_factors(mode) ? 1 : 0;
+    g.T = M + (sweep_test_rows(mode) ? Mhat : 0);
     g.P = m / 32;
     g.nb = m / bm;
     return g;
@@ -87,11 +87,13 @@ std::vector<PItem> build_persist_order(int M, int Mhat, int mode, int m, int bm,
     };
     // creation order is topological: step J ascending; in a step POTRF,
     // TRSMs, then updates
+    const bool block = sweep_test_block(mode);  // updates of the test block too
     for (int J = 0; J < M; ++J) {
         if (g.factor) add(PI_POTRF, J, J, J);
         for (int I = (g.factor ? J + 1 : M); I < T; ++I) add(PI_TRSM, I, J, J);
         for (int I = (g.factor ? J + 1 : M); I < T; ++I)
-            for (int K = J + 1; K <= I; ++K) add(PI_UPDATE, I, K, J);
+            for (int K = J + 1; K <= I; ++K)
+                if (block || K < M) add(PI_UPDATE, I, K, J);
     }
     // predecessors (the tasks whose items an item waits for, persist.h)
     auto link = [&](int pred, int succ) {
@@ -180,7 +182,7 @@ extern "C" int gpr_persist_describe(int32_t M, int32_t Mhat, int32_t mode, int32
                                     int32_t block, int32_t workers, int32_t* items,
                                     int64_t* waits, int64_t cap, int64_t* n_items)
 {
-    if (M < 1 || Mhat < 0 || mode < 0 || mode > 2 || !n_items) return GPR_EINVAL;
+    if (M < 1 || Mhat < 0 || mode < 0 || mode > 4 || !n_items) return GPR_EINVAL;
     if (mode != gpr::SWEEP_CHOLESKY && Mhat < 1) return GPR_EINVAL;
     if (tile < 32 || tile % 32 != 0 || block < 32 || tile % block != 0 || workers < 1)
         return GPR_EINVAL;

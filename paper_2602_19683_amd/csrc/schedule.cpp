@@ -31,6 +31,8 @@
 // step J on P; tiles of columns >= J+2 get all their updates on B in step
 // order. The covariance solve with a given factor (mode 1) has no POTRF and
 // uses C (TRSM of the test rows, then the updates of column J+1) and B.
+// Modes 3 and 4 are modes 1 and 2 without the updates of the test block
+// (columns K >= M): only V^T is formed, for the predictive variances.
 #include <algorithm>
 
 #include "gpr_internal.h"
@@ -68,9 +70,12 @@ SchedTask upd(int I, int K, int J) { return SchedTask{I == K ? K_SYRK : K_GEMM, 
 Schedule build_schedule(int M, int Mhat, int mode)
 {
     Builder b;
-    const bool factor = (mode == SWEEP_CHOLESKY || mode == SWEEP_FUSED);
-    const bool predict = (mode == SWEEP_PREDICT || mode == SWEEP_FUSED);
+    const bool factor = sweep_factors(mode);
+    const bool predict = sweep_test_rows(mode);
+    const bool block = sweep_test_block(mode);  // updates of the test block too
     const int T = M + (predict ? Mhat : 0);  // tile rows of the extended matrix
+    // columns K of the updates: all, or only the training columns (V only)
+    auto keep = [&](int K) { return block || K < M; };
     enum { C = 0, P = 1, B = 2 };
 
     if (!factor) {
@@ -82,6 +87,7 @@ Schedule build_schedule(int M, int Mhat, int mode)
             for (int I = M; I < T; ++I) tr.push_back({K_TRSM, I, J, J});
             for (int I = M; I < T; ++I)
                 for (int K = J + 1; K <= I; ++K) {
+                    if (!keep(K)) continue;
                     if (K == J + 1 && K < M) N.push_back(upd(I, K, J));
                     else R.push_back(upd(I, K, J));
                 }
@@ -113,13 +119,14 @@ Schedule build_schedule(int M, int Mhat, int mode)
             if (J + 2 < M) last_G1 = b.add(P, {t1, last_R}, LK_UPDATE, {upd(J + 2, J + 1, J)}, J);
             std::vector<SchedTask> N;
             for (int I = J + 2; I < T; ++I)
-                if (!(I == J + 2 && J + 2 < M)) N.push_back(upd(I, J + 1, J));
+                if (!(I == J + 2 && J + 2 < M) && keep(J + 1)) N.push_back(upd(I, J + 1, J));
             b.add(P, {t1, last_R}, LK_UPDATE, N, J);
         }
         // everything else of step J
         std::vector<SchedTask> R;
         for (int I = J + 1; I < T; ++I)
-            for (int K = (next ? J + 2 : J + 1); K <= I; ++K) R.push_back(upd(I, K, J));
+            for (int K = (next ? J + 2 : J + 1); K <= I; ++K)
+                if (keep(K)) R.push_back(upd(I, K, J));
         const int r = b.add(B, {t1, tr}, LK_UPDATE, R, J);
         if (r >= 0) last_R = r;
     }
@@ -132,7 +139,7 @@ extern "C" int gpr_schedule_describe(int32_t M, int32_t Mhat, int32_t mode, int3
                                      int64_t task_cap, int64_t* n_tasks, int32_t* launches,
                                      int64_t launch_cap, int64_t* n_launches)
 {
-    if (M < 1 || Mhat < 0 || mode < 0 || mode > 2 || !n_tasks || !n_launches) return GPR_EINVAL;
+    if (M < 1 || Mhat < 0 || mode < 0 || mode > 4 || !n_tasks || !n_launches) return GPR_EINVAL;
     if (mode != gpr::SWEEP_CHOLESKY && Mhat < 1) return GPR_EINVAL;
     gpr::Schedule S = gpr::build_schedule(M, Mhat, mode);
     *n_tasks = (int64_t)S.tasks.size();

@@ -202,6 +202,58 @@ class Context:
                            "precision": st.fallback_precision},)
         return out
 
+    def predict_var(self, L, X, y, Xs, hyper, full_cov=False, mean=None, var=None, cov=None,
+                    stream=None, ir_stats=False):
+        """Mean and predictive variances (and the full covariance if asked)
+        with the factor in L. Returns (mean, var, cov or None)."""
+        import torch
+        n, D = X.shape
+        ns = Xs.shape[0]
+        mean = mean if mean is not None else torch.empty(ns, dtype=torch.float64, device=X.device)
+        var = var if var is not None else torch.empty(ns, dtype=torch.float64, device=X.device)
+        if full_cov and cov is None:
+            cov = torch.empty(ns, ns, dtype=torch.float64, device=X.device)
+        st = IRStats()
+        _check(self._lib.gpr_predict_var(self._h, L.handle, _dev_ptr(X, "X"), _dev_ptr(y, "y", n),
+                                         n, _dev_ptr(Xs, "Xs"), ns, D, _hyper(hyper),
+                                         _dev_ptr(mean, "mean", ns),
+                                         _dev_ptr(cov, "cov", ns * ns) if full_cov else None,
+                                         _dev_ptr(var, "var", ns), ctypes.byref(st),
+                                         _stream(stream)), "gpr_predict_var")
+        out = (mean, var, cov if full_cov else None)
+        if ir_stats:
+            return out + ({"iters": st.iters, "rel_residual": st.rel_residual,
+                           "precision": st.fallback_precision},)
+        return out
+
+    def fit_predict_var(self, X, y, Xs, hyper, tile, precision="fp64", full_cov=False, K=None,
+                        mean=None, var=None, cov=None, info=None, stream=None, ir_stats=False):
+        """Assembly, Cholesky, mean and predictive variances (and the full
+        covariance if asked) in one sweep. Returns (mean, var, cov or None, K)."""
+        import torch
+        n, D = X.shape
+        ns = Xs.shape[0]
+        mean = mean if mean is not None else torch.empty(ns, dtype=torch.float64, device=X.device)
+        var = var if var is not None else torch.empty(ns, dtype=torch.float64, device=X.device)
+        if full_cov and cov is None:
+            cov = torch.empty(ns, ns, dtype=torch.float64, device=X.device)
+        h = ctypes.c_void_p(K.handle.value) if K is not None else ctypes.c_void_p()
+        ip = _dev_ptr_int(info) if info is not None else None
+        st = IRStats()
+        _check(self._lib.gpr_fit_predict_var(self._h, _dev_ptr(X, "X"), _dev_ptr(y, "y", n), n,
+                                             _dev_ptr(Xs, "Xs"), ns, D, _hyper(hyper), int(tile),
+                                             _prec(precision), ctypes.byref(h),
+                                             _dev_ptr(mean, "mean", ns),
+                                             _dev_ptr(cov, "cov", ns * ns) if full_cov else None,
+                                             _dev_ptr(var, "var", ns), ip, ctypes.byref(st),
+                                             _stream(stream)), "gpr_fit_predict_var")
+        K = K if K is not None else Tiled(h, self)
+        out = (mean, var, cov if full_cov else None, K)
+        if ir_stats:
+            return out + ({"iters": st.iters, "rel_residual": st.rel_residual,
+                           "precision": st.fallback_precision},)
+        return out
+
     def solve(self, L, b, x=None, stream=None):
         """x = K^{-1} b with the factor held by L."""
         import torch

@@ -48,7 +48,8 @@ def expected_items(M, Mhat, mode, m, bm):
 
 SHAPES = [(1, 0, 0, 64, 32), (3, 0, 0, 64, 32), (5, 0, 0, 96, 32), (4, 0, 0, 128, 64),
           (3, 2, 1, 64, 32), (2, 3, 1, 96, 32), (4, 2, 2, 64, 32), (3, 1, 2, 128, 64),
-          (1, 2, 2, 64, 32), (6, 2, 2, 64, 64)]
+          (1, 2, 2, 64, 32), (6, 2, 2, 64, 64), (3, 2, 3, 64, 32), (4, 2, 4, 64, 32),
+          (1, 2, 4, 64, 32)]
 
 
 @pytest.mark.parametrize("M,Mhat,mode,m,bm", SHAPES)
@@ -98,7 +99,7 @@ class HostSweep:
                   for I in range(T) for J in range(I + 1)}
         self.dinv = {}
         self.step = {}
-        if mode == 1:
+        if mode in (1, 3):
             for J in range(M):
                 L = self.t[(J, J)]
                 self.dinv[J] = scipy.linalg.solve_triangular(L, np.eye(m), lower=True)
@@ -192,7 +193,8 @@ def run_rounds(state, items, waits, sequential_rng=None):
 
 @pytest.mark.parametrize("M,Mhat,mode,m,bm", [(4, 0, 0, 64, 32), (3, 2, 2, 64, 32),
                                               (3, 2, 1, 64, 32), (2, 2, 2, 96, 32),
-                                              (3, 1, 2, 128, 64)])
+                                              (3, 1, 2, 128, 64), (3, 2, 3, 64, 32),
+                                              (3, 2, 4, 64, 32)])
 def test_host_execution_matches_oracle(M, Mhat, mode, m, bm):
     n, ns = M * m, Mhat * m
     h = (1.0, 1.0, 0.1)
@@ -202,7 +204,7 @@ def test_host_execution_matches_oracle(M, Mhat, mode, m, bm):
     assert info == 0
     ref = oracle.predict(X, y, Xs, h) if ns else None
     big = np.zeros((n + ns, n + ns))
-    big[:n, :n] = K if mode != 1 else Lref
+    big[:n, :n] = K if mode not in (1, 3) else Lref
     if ns:
         big[n:, :n] = oracle.kernel_matrix(Xs, X, h)
         big[n:, n:] = oracle.kernel_matrix(Xs, Xs, h)
@@ -217,12 +219,16 @@ def test_host_execution_matches_oracle(M, Mhat, mode, m, bm):
         out = np.zeros_like(big)
         for (I, J), t in st.t.items():
             out[I * m:(I + 1) * m, J * m:(J + 1) * m] = t
-        if mode != 1:
+        if mode not in (1, 3):
             assert oracle.rel_err_lower(np.tril(out[:n, :n]), Lref) <= 1e-12
-        if mode:
+        if mode in (1, 2):
             S = np.tril(out[n:, n:])
             S = S + np.tril(S, -1).T
             assert oracle.rel_err(S, ref["cov"]) <= 1e-11
+        if mode in (3, 4):   # variances only: V^T formed, the test block untouched
+            var = h[1] - (out[n:, :n] ** 2).sum(axis=1)
+            assert oracle.rel_err(var, np.diag(ref["cov"])) <= 1e-11
+            np.testing.assert_array_equal(np.tril(out[n:, n:]), np.tril(big[n:, n:]))
         outs.append(out)
     for o in outs[1:]:
         np.testing.assert_array_equal(o, outs[0])   # the same bits in any valid order

@@ -19,9 +19,11 @@ GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "fig2_first_iteration
 
 def fig1_program(M, Mhat, mode):
     """The loop nest of Fig. 1 as a sequential task list, extended with the
-    test rows M..M+Mhat-1 of the covariance solve (mode 1 and 2)."""
-    factor = mode in (0, 2)
-    predict = mode in (1, 2)
+    test rows M..M+Mhat-1 of the covariance solve (modes 1 to 4; modes 3 and 4
+    leave out the updates of the test block, K >= M)."""
+    factor = mode in (0, 2, 4)
+    predict = mode in (1, 2, 3, 4)
+    block = mode in (1, 2)
     T = M + (Mhat if predict else 0)
     rows = [I for I in range(T) if (I < M and factor) or (I >= M and predict)]
     prog = []
@@ -34,16 +36,16 @@ def fig1_program(M, Mhat, mode):
         for I in rows:
             if I <= J:
                 continue
-            prog.append((SYRK, I, I, J))
+            if I < M or block:
+                prog.append((SYRK, I, I, J))
             for K in range(J + 1, I):
-                if I >= M or factor:
+                if (I >= M or factor) and (K < M or block):
                     prog.append((GEMM, I, K, J))
     return prog
 
 
 def accesses(task, M, mode):
     kind, I, K, J = task
-    fixed = mode == 1  # factor tiles are read-only inputs in mode 1
     def w(t):
         return (t, "w")
     def r(t):
@@ -124,7 +126,8 @@ def test_memory_fraction_of_lower_tiles():
 
 @pytest.mark.parametrize("M,Mhat,mode", [(1, 0, 0), (2, 0, 0), (3, 0, 0), (5, 0, 0), (9, 0, 0),
                                          (4, 3, 1), (7, 2, 1), (1, 2, 1), (5, 3, 2), (6, 1, 2),
-                                         (2, 2, 2), (1, 3, 2), (3, 1, 2)])
+                                         (2, 2, 2), (1, 3, 2), (3, 1, 2), (4, 3, 3), (1, 2, 3),
+                                         (5, 3, 4), (2, 2, 4), (1, 3, 4), (6, 1, 4)])
 def test_schedule_has_no_races(M, Mhat, mode):
     tasks, launches = schedule_describe(M, Mhat, mode)
     prog = fig1_program(M, Mhat, mode)
@@ -186,7 +189,7 @@ def run_schedule_on_host(tiles, tinv, tasks, launches, rng):
 
 
 @pytest.mark.parametrize("M,Mhat,mode,m", [(4, 0, 0, 8), (5, 3, 2, 6), (3, 2, 1, 7), (2, 2, 2, 5),
-                                           (6, 1, 2, 4)])
+                                           (6, 1, 2, 4), (3, 2, 3, 7), (5, 3, 4, 6)])
 def test_host_execution_matches_oracle(M, Mhat, mode, m):
     n, ns = M * m, Mhat * m
     h = (1.0, 1.0, 0.1)
@@ -199,7 +202,7 @@ def test_host_execution_matches_oracle(M, Mhat, mode, m):
         rng = random.Random(seed)
         tiles, tinv = {}, {}
         big = np.zeros((n + ns, n + ns))
-        big[:n, :n] = K if mode != 1 else Lref
+        big[:n, :n] = K if mode not in (1, 3) else Lref
         if ns:
             big[n:, :n] = oracle.kernel_matrix(Xs, X, h)
             big[n:, n:] = oracle.kernel_matrix(Xs, Xs, h)
@@ -207,7 +210,7 @@ def test_host_execution_matches_oracle(M, Mhat, mode, m):
         for I in range(T):
             for J in range(I + 1):
                 tiles[(I, J)] = big[I * m:(I + 1) * m, J * m:(J + 1) * m].copy()
-        if mode == 1:
+        if mode in (1, 3):
             for J in range(M):
                 tinv[J] = scipy.linalg.solve_triangular(tiles[(J, J)], np.eye(m), lower=True)
         tasks, launches = schedule_describe(M, Mhat, mode)
@@ -216,11 +219,16 @@ def test_host_execution_matches_oracle(M, Mhat, mode, m):
         for (I, J), t in tiles.items():
             out[I * m:(I + 1) * m, J * m:(J + 1) * m] = t
         results.append(out)
-        if mode != 1:
+        if mode not in (1, 3):
             assert oracle.rel_err_lower(np.tril(out[:n, :n]), Lref) <= 1e-13
-        if mode:
+        if mode in (1, 2):
             S = np.tril(out[n:, n:])
             S = S + np.tril(S, -1).T
             assert oracle.rel_err(S, ref["cov"]) <= 1e-12
+        if mode in (3, 4):
+            # variances from the rows of V^T; the test block is left as assembled
+            var = h[1] - (out[n:, :n] ** 2).sum(axis=1)
+            assert oracle.rel_err(var, np.diag(ref["cov"])) <= 1e-12
+            np.testing.assert_array_equal(np.tril(out[n:, n:]), np.tril(big[n:, n:]))
     for r in results[1:]:
         np.testing.assert_array_equal(r, results[0])   # order-independent, bitwise
