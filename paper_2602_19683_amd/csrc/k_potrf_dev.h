@@ -255,18 +255,19 @@ __device__ inline void potrf_panel(double* __restrict__ A, int lda, int m, doubl
         Aw[(size_t)r * lda + row0 + c] = Sacc[r][c];
         Tinv[(size_t)(row0 + r) * ldt + row0 + c] = Si[r][c];
     }
-    // strict upper triangle of the tile in this row panel
-    const int rest = m - row0 - NB;
-    for (int e = tid; e < NB * rest; e += 256) {
-        const int r = e / rest, c = e % rest;
-        Aw[(size_t)r * lda + row0 + NB + c] = 0.0;
-    }
     // every earlier panel is complete (flags acquired), so the first failure
     // seen here in column order is the first overall
     if (tid == 0 && bad >= 0 && info != nullptr && *info == 0)
         *info = (int)(col_base + row0 + bad + 1);
     __syncthreads();
     if (tid == 0) __hip_atomic_store(diag_done + w, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    // strict upper triangle of the tile in this row panel: no other panel
+    // reads it, so it is written after the handoff, off the dependency chain
+    const int rest = m - row0 - NB;
+    for (int e = tid; e < NB * rest; e += 256) {
+        const int r = e / rest, c = e % rest;
+        Aw[(size_t)r * lda + row0 + NB + c] = 0.0;
+    }
 }
 
 
