@@ -69,6 +69,10 @@ def test_host_argument_validation():
     assert lib.gpr_solve(None, None, None, None, None) == _lib.GPR_EINVAL
     assert lib.gpr_fit_predict(None, None, None, 10, None, 5, 8, H, 32, 0, None, None, None,
                                None, None, None) == _lib.GPR_EINVAL
+    assert lib.gpr_predict_var(None, None, None, None, 10, None, 5, 8, H, None, None, None, None,
+                               None) == _lib.GPR_EINVAL
+    assert lib.gpr_fit_predict_var(None, None, None, 10, None, 5, 8, H, 32, 0, None, None, None,
+                                   None, None, None, None) == _lib.GPR_EINVAL
     assert lib.gpr_tiled_info(None, None, None, None) == _lib.GPR_EINVAL
     assert lib.gpr_tiled_to_dense(None, None, None, None) == _lib.GPR_EINVAL
     assert lib.gpr_tiled_free(None) == _lib.GPR_EINVAL
