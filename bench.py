@@ -206,6 +206,50 @@ def variants_run(ctx, K, Xd, yd, Xsd, h, tile, args, log):
     return out
 
 
+def library_run(ctx, K, Xd, h, tile, args, log):
+    """The single-tile analogue: the vendor dense Cholesky (torch.linalg.cholesky
+    on the assembled n x n FP64 matrix, rocSOLVER through hipSOLVER) against this
+    library's assembly + tiled Cholesky of the same matrix, and the normwise
+    difference between the two factors."""
+    import torch
+    torch.backends.cuda.preferred_linalg_library("cusolver")
+    ctx.assemble(Xd, h, tile, K=K)
+    A = ctx.to_dense(K)
+    ctx.sync()
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / args.steps
+
+    ms_lib = timed(lambda: torch.linalg.cholesky(A))
+    ms_asm = timed(lambda: ctx.assemble(Xd, h, tile, K=K))
+    ms_ours = timed(lambda: (ctx.assemble(Xd, h, tile, K=K), ctx.cholesky(K)))
+    ctx.sync()
+    L_ours = torch.tril(ctx.to_dense(K))
+    L_lib = torch.linalg.cholesky(A)
+    torch.cuda.synchronize()
+    diff = float(torch.linalg.norm(L_ours - L_lib) / torch.linalg.norm(L_lib))
+    n = A.shape[0]
+    out = {"vendor_cholesky_ms": round(ms_lib, 4),
+           "vendor_gflops": round(n ** 3 / 3 / (ms_lib * 1e-3) / 1e9, 1),
+           "tiled_cholesky_ms": round(ms_ours - ms_asm, 4),
+           "tiled_gflops": round(n ** 3 / 3 / ((ms_ours - ms_asm) * 1e-3) / 1e9, 1),
+           "rel_diff_factor": diff,
+           "vendor": "torch.linalg.cholesky (hipSOLVER / rocSOLVER), one n x n FP64 matrix"}
+    del A, L_ours, L_lib
+    torch.cuda.empty_cache()
+    log(f"library comparator: {out}")
+    return out
+
+
 def nlml_run(ctx, args, log):
     """The gradient workload: NLML and its gradient in (l, v, sigma^2) at
     n = 8192, D = 8, tile 256, from (0.3, 2.0, 0.5): time per evaluation
@@ -263,6 +307,8 @@ def main():
     ap.add_argument("--no-check", action="store_true")
     ap.add_argument("--no-persistent", action="store_true",
                     help="skip the persistent-executor timing of the same FP64 step")
+    ap.add_argument("--no-library", action="store_true",
+                    help="skip the vendor dense-Cholesky comparator")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the mean-only and mean + variance timings")
     ap.add_argument("--executor", default="streams", choices=["streams", "persistent"],
@@ -320,15 +366,21 @@ def main():
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
+    marks = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     t_wall = time.perf_counter()
     e0.record()
-    for _ in range(args.steps):
+    marks[0].record()
+    for i in range(args.steps):
         step()
+        marks[i + 1].record()
     e1.record()
     torch.cuda.synchronize()
     t_wall = time.perf_counter() - t_wall
     ctx.sync()
     ms = e0.elapsed_time(e1) / args.steps
+    per = [marks[i].elapsed_time(marks[i + 1]) for i in range(args.steps)]
+    sd = (sum((x - ms) ** 2 for x in per) / max(len(per) - 1, 1)) ** 0.5
+    ci95 = 1.96 * sd / max(len(per), 1) ** 0.5
     prof = ctx.profile_read(reset=True)
     ctx.profile(False)
     log(f"timed {args.steps} steps: {ms:.3f} ms/step (wall {t_wall / args.steps * 1e3:.3f})")
@@ -358,6 +410,9 @@ def main():
     if (not args.no_persistent and not persistent_line and args.precision == "fp64"
             and args.path == "fused"):
         persistent = persistent_run(Xd, yd, Xsd, h, tile, mean, cov, ms, flops, args, log)
+    library = None
+    if not args.no_library and args.precision == "fp64":
+        library = library_run(ctx, K, Xd, h, tile, args, log)
     variants = None
     if not args.no_variants and args.path == "fused":
         variants = variants_run(ctx, K, Xd, yd, Xsd, h, tile, args, log)
@@ -374,6 +429,7 @@ def main():
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": "GFLOP/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 4),
+        "ms_per_step_ci95": round(ci95, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": f"exact GP, SE kernel: assembly + tiled Cholesky + mean + full "
@@ -391,6 +447,7 @@ def main():
         "mixed": mixed,
         "persistent_executor": persistent,
         "prediction_variants": variants,
+        "library_comparator": library,
         "nlml_grad": nlml,
         "phases_ms_per_step": {k: round(v[1] / args.steps, 4) for k, v in prof.items()},
     }
