@@ -52,7 +52,7 @@ struct gpr_ctx {
     size_t pitems_cap = 0;
     int64_t pkey[6] = {-1, -1, -1, -1, -1, -1};
     int64_t p_nitems = 0;
-    int p_workers = 0, p_bm = 0;
+    int p_workers = 0, p_bm = 0, p_prec = -1;
     char* d_pcnt = nullptr;       // progress counters + ticket
     size_t pcnt_cap = 0;
     // instrumentation
@@ -263,12 +263,13 @@ struct SweepPlan {
     std::vector<size_t> off;  // descriptor offset per launch
 };
 
-// The persistent executor runs FP64 sweeps; a context created for it runs
-// the mixed-precision sweeps (whose updates have no persistent form) on the
+// The persistent executor runs FP64 and FP32-update sweeps; a context created
+// for it runs the BF16 sweeps (whose updates have no persistent form) on the
 // streams.
 bool use_persistent(const gpr_ctx* ctx, const SweepMats& X)
 {
-    return ctx->executor == GPR_EXEC_PERSISTENT && X.prec == GPR_FP64;
+    return ctx->executor == GPR_EXEC_PERSISTENT &&
+           (X.prec == GPR_FP64 || X.prec == GPR_MIXED_FP32);
 }
 
 // Builds the descriptors of a sweep into `db`.
@@ -310,9 +311,10 @@ int run_persist(gpr_ctx* ctx, const SweepMats& X, int mode, hipStream_t s)
 {
     const int m = X.m, M = X.M, bm = persist_block(m);
     const int Mhat = sweep_test_rows(mode) ? X.Mhat : 0;
-    if (ctx->p_workers <= 0 || ctx->p_bm != bm) {
-        ctx->p_workers = persist_workers(bm);
+    if (ctx->p_workers <= 0 || ctx->p_bm != bm || ctx->p_prec != X.prec) {
+        ctx->p_workers = persist_workers(bm, X.prec);
         ctx->p_bm = bm;
+        ctx->p_prec = X.prec;
         if (ctx->p_workers <= 0) return GPR_EHIP;
     }
     const int64_t key[6] = {M, Mhat, mode, m, bm, ctx->p_workers};
@@ -348,7 +350,7 @@ int run_persist(gpr_ctx* ctx, const SweepMats& X, int mode, hipStream_t s)
     ctx->epoch += (unsigned)M;
     ProfScope ps(ctx, s, PK_PERSIST, tasks * (double)m * m * m, 0.0);
     HIP_TRY(launch_persist(reinterpret_cast<const PItem*>(ctx->d_pitems), ctx->p_nitems, g, m, bm,
-                           ctx->p_workers, X.K, X.tinv, X.V, X.S,
+                           X.prec, ctx->p_workers, X.K, X.tinv, X.V, X.S,
                            reinterpret_cast<unsigned*>(ctx->d_pcnt), ncnt, ctx->d_flags, epoch0,
                            ctx->d_info, ctx->d_info + 2, s));
     return GPR_OK;

@@ -258,13 +258,14 @@ Schedule build_schedule(int M, int Mhat, int mode);
 // Persistent executor (persist.cpp, k_persist.hip): geometry, ticket order for
 // `workers` resident workgroups, update block size for a tile size, the
 // number of workgroups that fit at once, and the launch (which first clears
-// the ncnt progress counters and the ticket at d_cnt[ncnt]).
+// the ncnt progress counters and the ticket at d_cnt[ncnt]). prec: GPR_FP64
+// or GPR_MIXED_FP32 (precision of the update items).
 PGeom persist_geom(int M, int Mhat, int mode, int m, int bm);
 std::vector<PItem> build_persist_order(int M, int Mhat, int mode, int m, int bm, int workers);
 int persist_block(int m);
-int persist_workers(int bm);
+int persist_workers(int bm, int prec);
 hipError_t launch_persist(const PItem* d_items, int64_t nitems, const PGeom& g, int m, int bm,
-                          int workers, const TileMat& K, double* tinv, const TileMat& V,
+                          int prec, int workers, const TileMat& K, double* tinv, const TileMat& V,
                           const TileMat& S, unsigned* d_cnt, int64_t ncnt, unsigned* flags,
                           unsigned epoch0, int* info, int* err, hipStream_t s);
 

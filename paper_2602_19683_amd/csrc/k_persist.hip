@@ -18,6 +18,7 @@
 #include "k_potrf_dev.h"
 #include "k_trsm_dev.h"
 #include "k_update_dev.h"
+#include "k_update_mixed_dev.h"
 #include "persist.h"
 
 namespace gpr {
@@ -68,13 +69,16 @@ __device__ inline bool wait_count(const unsigned* c, unsigned v, int* err)
 template <int BM>
 union PersistLds {
     UpdLds<BM> u;
+    UpdLdsF32<BM> uf;
     PotrfLds p;
     TrsmLds t;
 };
 
 }  // namespace
 
-template <int BM>
+// F32: the update items round their operands to FP32 (the mixed-precision
+// sweep); POTRF and TRSM items stay FP64.
+template <int BM, bool F32>
 __global__ __launch_bounds__(256, 2) void k_persist(PersistArgs a)
 {
     __shared__ PersistLds<BM> sh;
@@ -123,7 +127,10 @@ __global__ __launch_bounds__(256, 2) void k_persist(PersistArgs a)
             }
             const UpdateTask tk{ext_tile(a, it.I, it.K), ext_tile(a, it.I, it.J),
                                 ext_tile(a, it.K, it.J), m, m, m, it.I == it.K ? TASK_DIAG : 0};
-            update_block<BM, 2, 2>(tk, bi, bj, m, sh.u, ltid);
+            if (F32)
+                update_block_f32<BM, 2, 2>(tk, bi, bj, m, sh.uf, ltid);
+            else
+                update_block<BM, 2, 2>(tk, bi, bj, m, sh.u, ltid);
         } else if (kind == PI_TRSM) {
             const TrsmTask tk{ext_tile(a, it.I, it.J), ext_tile(a, it.J, it.J),
                               a.tinv + (size_t)it.J * m * m, nullptr, m, m, m, 0};
@@ -155,25 +162,43 @@ __global__ void k_zero_u32(unsigned* p, int64_t n)
 // blocks (measured 1.4x faster for the whole sweep at m = 512).
 int persist_block(int m) { return m % 128 == 0 ? 128 : (m % 64 == 0 ? 64 : 32); }
 
-int persist_workers(int bm)
+namespace {
+
+template <bool F32>
+hipError_t occupancy(int* per, int bm)
+{
+    if (bm == 128) return hipOccupancyMaxActiveBlocksPerMultiprocessor(per, k_persist<128, F32>, 256, 0);
+    if (bm == 64) return hipOccupancyMaxActiveBlocksPerMultiprocessor(per, k_persist<64, F32>, 256, 0);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per, k_persist<32, F32>, 256, 0);
+}
+
+template <bool F32>
+void launch(int bm, dim3 grid, hipStream_t s, const PersistArgs& a)
+{
+    if (bm == 128)
+        hipLaunchKernelGGL((k_persist<128, F32>), grid, dim3(256), 0, s, a);
+    else if (bm == 64)
+        hipLaunchKernelGGL((k_persist<64, F32>), grid, dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_persist<32, F32>), grid, dim3(256), 0, s, a);
+}
+
+}  // namespace
+
+int persist_workers(int bm, int prec)
 {
     int dev = 0, cus = 0, per = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         return 0;
-    hipError_t e;
-    if (bm == 128)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_persist<128>, 256, 0);
-    else if (bm == 64)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_persist<64>, 256, 0);
-    else
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_persist<32>, 256, 0);
+    const hipError_t e = prec == GPR_MIXED_FP32 ? occupancy<true>(&per, bm)
+                                                : occupancy<false>(&per, bm);
     if (e != hipSuccess) return 0;
     return per * cus;
 }
 
 hipError_t launch_persist(const PItem* d_items, int64_t nitems, const PGeom& g, int m, int bm,
-                          int workers, const TileMat& K, double* tinv, const TileMat& V,
+                          int prec, int workers, const TileMat& K, double* tinv, const TileMat& V,
                           const TileMat& S, unsigned* d_cnt, int64_t ncnt, unsigned* flags,
                           unsigned epoch0, int* info, int* err, hipStream_t s)
 {
@@ -184,12 +209,10 @@ hipError_t launch_persist(const PItem* d_items, int64_t nitems, const PGeom& g, 
     PersistArgs a{d_items, nitems, K, tinv, V, S, g, m, d_cnt, d_cnt + ncnt, flags, epoch0,
                   info, err};
     const dim3 grid((unsigned)std::min<int64_t>(workers, nitems));
-    if (bm == 128)
-        hipLaunchKernelGGL(k_persist<128>, grid, dim3(256), 0, s, a);
-    else if (bm == 64)
-        hipLaunchKernelGGL(k_persist<64>, grid, dim3(256), 0, s, a);
+    if (prec == GPR_MIXED_FP32)
+        launch<true>(bm, grid, s, a);
     else
-        hipLaunchKernelGGL(k_persist<32>, grid, dim3(256), 0, s, a);
+        launch<false>(bm, grid, s, a);
     return hipGetLastError();
 }
 

@@ -1,0 +1,109 @@
+// k_update_mixed_dev.h -- one block of a tile update C -= A B^T with the
+// operands rounded to FP32 as they are staged into LDS and an FP32-accumulator
+// MFMA (the mixed-precision GEMM / SYRK tasks of Fig. 1), shared by the stream
+// kernel and the persistent executor; the blocking is described in
+// k_update_mixed.hip.
+#pragma once
+
+#include "gpr_internal.h"
+#include "k_common.h"
+
+namespace gpr {
+
+typedef float flt4 __attribute__((ext_vector_type(4)));
+
+// Row of element v held by a lane of group lk = l / 16 in an FP32-accumulator
+// 16 x 16 MFMA result.
+__device__ constexpr int frow(int lk, int v) { return 4 * lk + v; }
+
+template <int BM>
+struct UpdLdsF32 {
+    float As[2][16][BM + 4];
+    float Bs[2][16][BM + 4];
+};
+
+// Block (bi, bj) of the task, WR x WC waves (WR * WC * 64 threads, tid the
+// thread's index).
+template <int BM, int WR, int WC>
+__device__ inline void update_block_f32(const UpdateTask& tk, int bi, int bj, int m,
+                                        UpdLdsF32<BM>& sh, int tid)
+{
+    constexpr int NT = WR * WC * 64;
+    constexpr int KB = 16;
+    constexpr int TR = BM / WR / 16, TC = BM / WC / 16;
+    constexpr int LD = BM + 4;
+    constexpr int NLD = BM * KB / 2 / NT;
+    float (*As)[KB][LD] = sh.As;
+    float (*Bs)[KB][LD] = sh.Bs;
+    const double* __restrict__ A = tk.A + (size_t)bi * BM * tk.lda;
+    const double* __restrict__ B = tk.B + (size_t)bj * BM * tk.ldb;
+    double* __restrict__ C = tk.C + (size_t)bi * BM * tk.ldc + (size_t)bj * BM;
+    const int lda = tk.lda, ldb = tk.ldb, ldc = tk.ldc;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int wr = (wave / WC) * (BM / WR), wc = (wave % WC) * (BM / WC);
+    const int lr = lane & 15, lk = lane >> 4;
+
+    double2 ra[NLD], rb[NLD];
+    auto gload = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < NLD; ++q) {
+            const int e = tid + NT * q;
+            const int r = e / (KB / 2), kk = (e % (KB / 2)) * 2;
+            ra[q] = *reinterpret_cast<const double2*>(A + (size_t)r * lda + k0 + kk);
+            rb[q] = *reinterpret_cast<const double2*>(B + (size_t)r * ldb + k0 + kk);
+        }
+    };
+    auto swrite = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < NLD; ++q) {
+            const int e = tid + NT * q;
+            const int r = e / (KB / 2), kk = (e % (KB / 2)) * 2;
+            As[buf][kk][r] = (float)ra[q].x;
+            As[buf][kk + 1][r] = (float)ra[q].y;
+            Bs[buf][kk][r] = (float)rb[q].x;
+            Bs[buf][kk + 1][r] = (float)rb[q].y;
+        }
+    };
+    flt4 acc[TR][TC];
+#pragma unroll
+    for (int i = 0; i < TR; ++i)
+#pragma unroll
+        for (int j = 0; j < TC; ++j) acc[i][j] = flt4{0.f, 0.f, 0.f, 0.f};
+
+    gload(0);
+    swrite(0);
+    __syncthreads();
+    const int nk = m / KB;
+    for (int kt = 0; kt < nk; ++kt) {
+        const int cur = kt & 1;
+        if (kt + 1 < nk) gload((kt + 1) * KB);
+#pragma unroll
+        for (int kk = 0; kk < KB; kk += 4) {
+            float a[TR], b[TC];
+#pragma unroll
+            for (int i = 0; i < TR; ++i) a[i] = As[cur][kk + lk][wr + 16 * i + lr];
+#pragma unroll
+            for (int j = 0; j < TC; ++j) b[j] = Bs[cur][kk + lk][wc + 16 * j + lr];
+#pragma unroll
+            for (int i = 0; i < TR; ++i)
+#pragma unroll
+                for (int j = 0; j < TC; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+        if (kt + 1 < nk) swrite(cur ^ 1);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < TR; ++i)
+#pragma unroll
+        for (int j = 0; j < TC; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = wr + 16 * i + frow(lk, v);
+                const int col = wc + 16 * j + lr;
+                C[(size_t)row * ldc + col] -= (double)acc[i][j][v];
+            }
+}
+
+
+}  // namespace gpr

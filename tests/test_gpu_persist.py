@@ -96,6 +96,29 @@ def test_fit_predict_bitwise_equal_to_streams(ctxs, n, ns, tile):
         assert em <= TOL and ec <= TOL
 
 
+@pytest.mark.parametrize("prec,n,ns,tile", [("fp32", 1000, 300, 128), ("fp32", 4096, 1024, 512),
+                                           ("bf16", 1000, 300, 128)])
+def test_mixed_precision_bitwise_equal_to_streams(ctxs, prec, n, ns, tile):
+    """FP32 tile updates run as persistent items (BF16 sweeps of a persistent
+    context run on the streams): factor, mean, covariance and the
+    refinement statistics equal the stream executor's."""
+    say(f"persistent mixed {prec} n={n} n_test={ns} tile={tile}")
+    s, p = ctxs
+    X, y, Xs = nfir_train_test(n, ns)
+    Xd, yd, Xsd = dev(X), dev(y), dev(Xs)
+    out = []
+    for c in (s, p):
+        mean, cov, K, st = c.fit_predict(Xd, yd, Xsd, DEFAULT_HYPER, tile, prec, ir_stats=True)
+        L = host(c.to_dense(K))
+        out.append((host(mean), host(cov), L, st))
+        assert c.sync()[0] == 0
+        K.free()
+    for a, b in zip(out[0][:3], out[1][:3]):
+        np.testing.assert_array_equal(b, a)
+    assert out[0][3] == out[1][3]
+    say(f"  refinement {out[1][3]}")
+
+
 def test_nlml_and_gradient_bitwise_equal_to_streams(ctxs):
     n, tile, h = 1024, 128, (0.3, 2.0, 0.5)
     say(f"persistent nlml_grad n={n} tile={tile}")
