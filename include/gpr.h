@@ -87,8 +87,8 @@ typedef enum {
  * GPR_EXEC_PERSISTENT: one launch per sweep; resident workgroups take work
  * items (POTRF row panels, TRSM strips, update blocks) from a ticket list in
  * a precomputed priority order and wait on per-tile progress counters in
- * device memory. Both give bitwise-identical FP64 results. The persistent
- * executor runs the FP64 sweeps; the mixed-precision sweeps of a context
+ * device memory. Both give bitwise-identical results. The persistent
+ * executor runs the FP64 and FP32-update sweeps; the BF16 sweeps of a context
  * created with it run on the streams. */
 typedef enum {
     GPR_EXEC_STREAMS = 0,
