@@ -313,8 +313,12 @@ int gpr_schedule_describe(int32_t M, int32_t Mhat, int32_t mode,
  * nterm, epilogue, 0. terms: 8 int32 per term: A (3), B (3), alpha (+1 or -1),
  * flags (1 A transposed, 2 B transposed, 4 A lower-triangular, 8 B
  * lower-triangular). launches: 4 int32 per launch: kind (0 TRSM adjoint,
- * 1 partial sums, 2 diagonal sum, 3 POTRF adjoint, 4 push), step, first task,
- * task count; launches run in list order, tasks of one launch in parallel.
+ * 1 partial sums, 2 diagonal sum, 3 POTRF adjoint, 4 sums of the partial
+ * tiles into the column's Lbar tiles), step, first task, task count; launches
+ * run in list order, tasks of one launch in parallel. The sweep is
+ * left-looking: step J collects into column J everything the later steps
+ * contribute to it (M - J tile products per tile), then runs its TRSM and
+ * POTRF adjoints.
  * Capacities in records; counts always written; GPR_EINVAL if one is too
  * small. */
 int gpr_adjoint_describe(int32_t M, int32_t G, int32_t* tasks, int64_t task_cap,

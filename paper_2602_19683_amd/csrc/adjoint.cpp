@@ -21,10 +21,19 @@
 // <Lbar, dL> = <L^{-T} Phi(L^T Lbar) L^{-1}, dK>; summed over the two triangles
 // this is Phi(S + S^T) with S + S^T = Tinv^T G Tinv.)
 //
-// The row-K sums over R are long and feed few output tiles, so they run
-// split-K: chunks of G consecutive R go to separate partial tiles (one task
-// each, many workgroups), and the task that consumes them adds the partials in
-// chunk order (fixed order: the result is deterministic).
+// The sweep is run left-looking ("pull"): no step pushes into later columns.
+// Collecting the pushes that tile (I, J), I > J, receives from the steps
+// K > J gives its final value just before step J needs it:
+//   Lbar_IJ -= sum_{R>I} Abar_RI^T L_RJ + (Abar_II + Abar_II^T) L_IJ
+//              + sum_{J<K<I} Abar_IK L_KJ                        (M - J terms)
+// and the diagonal tile only receives the row sum of its own step:
+//   Q = Lbar_JJ - sum_{R>J} Abar_RJ^T L_RJ.
+// Step J (J = M-1 down to 0) therefore runs: the pulls of column J (deep
+// products, M - J terms each), the TRSM adjoint of column J, the diagonal
+// row sum, and the POTRF adjoint. The long sums run split-K: chunks of G
+// consecutive terms go to separate partial tiles (one task each, many
+// workgroups), and the task that consumes them adds the partials in chunk
+// order (fixed order: the result is deterministic).
 #include <algorithm>
 
 #include "gpr_internal.h"
@@ -67,53 +76,66 @@ AdjPlan build_adjoint(int M, int G)
 {
     PB b;
     if (G < 1) G = 1;
-    for (int K = M - 1; K >= 0; --K) {
-        const int nt = M - K - 1;          // tile rows below the diagonal tile
-        const int C = (nt + G - 1) / G;    // chunks of the row-K sums
+    for (int J = M - 1; J >= 0; --J) {
+        const int nt = M - J - 1;  // tile rows below the diagonal tile
         if (nt > 0) {
-            // TRSM adjoint
-            b.launch_begin(AK_TRSM, K);
-            for (int I = K + 1; I < M; ++I)
-                b.task(R_(AM_ABAR, I, K), NONE, 0, 0, TG_EPI_NONE,
-                       {AdjTerm{R_(AM_LBAR, I, K), R_(AM_TINV, K, K), 1, TG_TRI_B}});
-            // partial sums -sum_{R in chunk} Abar_RK^T L_RJ for J = 0 .. K
-            b.launch_begin(AK_PART, K);
-            for (int J = K; J >= 0; --J)  // the diagonal tile's partials first
-                for (int c = 0; c < C; ++c) {
-                    std::vector<AdjTerm> t;
-                    for (int R = K + 1 + c * G; R < std::min(M, K + 1 + (c + 1) * G); ++R)
-                        t.push_back({R_(AM_ABAR, R, K), R_(AM_L, R, J), -1, TG_TRANS_A});
-                    b.task_terms(R_(AM_PART, J * C + c, 0), NONE, 0, 0, TG_EPI_NONE, t);
+            // pulls into column J, as partial tiles: for each I > J the
+            // M - J terms in chunks of G
+            b.launch_begin(AK_PART, J);
+            std::vector<int> part0(M, 0), npart(M, 0);
+            int p = 0;
+            for (int I = J + 1; I < M; ++I) {
+                std::vector<AdjTerm> all;
+                for (int R = I + 1; R < M; ++R)
+                    all.push_back({R_(AM_ABAR, R, I), R_(AM_L, R, J), -1, TG_TRANS_A});
+                all.push_back({R_(AM_ABAR, I, I), R_(AM_L, I, J), -1, 0});
+                all.push_back({R_(AM_ABAR, I, I), R_(AM_L, I, J), -1, TG_TRANS_A});
+                for (int K = J + 1; K < I; ++K)
+                    all.push_back({R_(AM_ABAR, I, K), R_(AM_L, K, J), -1, 0});
+                part0[I] = p;
+                for (size_t c = 0; c < all.size(); c += (size_t)G) {
+                    const std::vector<AdjTerm> chunk(all.begin() + c,
+                                                     all.begin() + std::min(all.size(), c + G));
+                    b.task_terms(R_(AM_PART, p, 0), NONE, 0, 0, TG_EPI_NONE, chunk);
+                    ++p;
                 }
-            b.P.max_part = std::max(b.P.max_part, (K + 1) * C);
-            // Q = Lbar_KK + sum of its partials
-            b.launch_begin(AK_DIAG_SUM, K);
-            b.task(R_(AM_Q, 0, 0), R_(AM_LBAR, K, K), K * C, C, TG_EPI_NONE, {});
-        }
-        const AdjRef Q = nt > 0 ? R_(AM_Q, 0, 0) : R_(AM_LBAR, K, K);
-        // POTRF adjoint: three products on single tiles
-        b.launch_begin(AK_POTRF, K);
-        b.task(R_(AM_G, 0, 0), NONE, 0, 0, TG_EPI_SYM,
-               {AdjTerm{R_(AM_L, K, K), Q, 1, TG_TRANS_A | TG_TRI_A | TG_TRI_B}});
-        b.launch_begin(AK_POTRF, K);
-        b.task(R_(AM_X, 0, 0), NONE, 0, 0, TG_EPI_NONE,
-               {AdjTerm{R_(AM_G, 0, 0), R_(AM_TINV, K, K), 1, TG_TRI_B}});
-        b.launch_begin(AK_POTRF, K);
-        b.task(R_(AM_ABAR, K, K), NONE, 0, 0, TG_EPI_PHI,
-               {AdjTerm{R_(AM_TINV, K, K), R_(AM_X, 0, 0), 1, TG_TRANS_A | TG_TRI_A}});
-        // push into the columns J < K
-        if (K > 0) {
-            b.launch_begin(AK_PUSH, K);
-            for (int J = K - 1; J >= 0; --J) {  // column K-1 (needed next) first
-                b.task(R_(AM_LBAR, K, J), R_(AM_LBAR, K, J), nt > 0 ? J * C : 0, nt > 0 ? C : 0,
-                       TG_EPI_NONE,
-                       {AdjTerm{R_(AM_ABAR, K, K), R_(AM_L, K, J), -1, 0},
-                        AdjTerm{R_(AM_ABAR, K, K), R_(AM_L, K, J), -1, TG_TRANS_A}});
-                for (int R = K + 1; R < M; ++R)
-                    b.task(R_(AM_LBAR, R, J), R_(AM_LBAR, R, J), 0, 0, TG_EPI_NONE,
-                           {AdjTerm{R_(AM_ABAR, R, K), R_(AM_L, K, J), -1, 0}});
+                npart[I] = p - part0[I];
             }
+            b.P.max_part = std::max(b.P.max_part, p);
+            // Lbar_IJ += its partials (in place)
+            b.launch_begin(AK_PUSH, J);
+            for (int I = J + 1; I < M; ++I)
+                b.task(R_(AM_LBAR, I, J), R_(AM_LBAR, I, J), part0[I], npart[I], TG_EPI_NONE, {});
+            // TRSM adjoint
+            b.launch_begin(AK_TRSM, J);
+            for (int I = J + 1; I < M; ++I)
+                b.task(R_(AM_ABAR, I, J), NONE, 0, 0, TG_EPI_NONE,
+                       {AdjTerm{R_(AM_LBAR, I, J), R_(AM_TINV, J, J), 1, TG_TRI_B}});
+            // the diagonal tile's row sum -sum_{R>J} Abar_RJ^T L_RJ, in chunks
+            b.launch_begin(AK_PART, J);
+            const int C = (nt + G - 1) / G;
+            for (int c = 0; c < C; ++c) {
+                std::vector<AdjTerm> t;
+                for (int R = J + 1 + c * G; R < std::min(M, J + 1 + (c + 1) * G); ++R)
+                    t.push_back({R_(AM_ABAR, R, J), R_(AM_L, R, J), -1, TG_TRANS_A});
+                b.task_terms(R_(AM_PART, c, 0), NONE, 0, 0, TG_EPI_NONE, t);
+            }
+            b.P.max_part = std::max(b.P.max_part, C);
+            // Q = Lbar_JJ + its partials
+            b.launch_begin(AK_DIAG_SUM, J);
+            b.task(R_(AM_Q, 0, 0), R_(AM_LBAR, J, J), 0, C, TG_EPI_NONE, {});
         }
+        const AdjRef Q = nt > 0 ? R_(AM_Q, 0, 0) : R_(AM_LBAR, J, J);
+        // POTRF adjoint: three products on single tiles
+        b.launch_begin(AK_POTRF, J);
+        b.task(R_(AM_G, 0, 0), NONE, 0, 0, TG_EPI_SYM,
+               {AdjTerm{R_(AM_L, J, J), Q, 1, TG_TRANS_A | TG_TRI_A | TG_TRI_B}});
+        b.launch_begin(AK_POTRF, J);
+        b.task(R_(AM_X, 0, 0), NONE, 0, 0, TG_EPI_NONE,
+               {AdjTerm{R_(AM_G, 0, 0), R_(AM_TINV, J, J), 1, TG_TRI_B}});
+        b.launch_begin(AK_POTRF, J);
+        b.task(R_(AM_ABAR, J, J), NONE, 0, 0, TG_EPI_PHI,
+               {AdjTerm{R_(AM_TINV, J, J), R_(AM_X, 0, 0), 1, TG_TRANS_A | TG_TRI_A}});
     }
     return b.P;
 }

@@ -140,12 +140,16 @@ def test_plan_matches_closed_form_adjoint(n, m, G):
 @pytest.mark.parametrize("M,G", [(1, 1), (2, 2), (5, 2), (9, 3), (12, 5)])
 def test_plan_counts(M, G):
     tasks, terms, launches = adjoint_describe(M, G)
-    # tile products: TRSM adjoint M(M-1)/2, POTRF adjoint 3 M, row partials
-    # sum_K (K+1)(M-K-1), push sum_K K (M-K) + K (the two Abar_KK terms)
-    tprod = M * (M - 1) // 2 + 3 * M
-    tprod += sum((K + 1) * (M - K - 1) for K in range(M))
-    tprod += sum(K * (M - K) + K for K in range(M))
+    # tile products: TRSM adjoint M(M-1)/2, POTRF adjoint 3 M, diagonal row
+    # sums M(M-1)/2, pulls: M - J terms for each of the M - J - 1 tiles below
+    # the diagonal of column J
+    tprod = M * (M - 1) // 2 + 3 * M + M * (M - 1) // 2
+    tprod += sum((M - J - 1) * (M - J) for J in range(M))
     assert len(terms) == tprod
+    # no partial chunk holds more than G terms
+    for kind, step, first, count in launches:
+        if kind == 1:
+            assert all(tasks[t][9] <= G for t in range(first, first + count))
     # the reverse steps run from M-1 down to 0
     steps = [int(s) for s in launches[:, 1]]
     assert steps == sorted(steps, reverse=True)
