@@ -312,15 +312,17 @@ int gpr_schedule_describe(int32_t M, int32_t Mhat, int32_t mode,
  * tasks: 12 int32 per task: out (3), cin (3), part0, npart, first_term,
  * nterm, epilogue, 0. terms: 8 int32 per term: A (3), B (3), alpha (+1 or -1),
  * flags (1 A transposed, 2 B transposed, 4 A lower-triangular, 8 B
- * lower-triangular). launches: 4 int32 per launch: kind (0 TRSM adjoint,
+ * lower-triangular). launches: 6 int32 per launch: kind (0 TRSM adjoint,
  * 1 partial sums, 2 diagonal sum, 3 POTRF adjoint, 4 sums of the partial
- * tiles into the column's Lbar tiles), step, first task, task count; launches
+ * tiles into the column's Lbar tiles), step, first task, task count, stream
+ * (0 the caller's, 1 a second stream), and the index of a launch on the
+ * other stream that must finish first (-1 if none). Launches on one stream
  * run in list order, tasks of one launch in parallel. The sweep is
  * left-looking: step J collects into column J everything the later steps
  * contribute to it (M - J tile products per tile), then runs its TRSM and
- * POTRF adjoints.
- * Capacities in records; counts always written; GPR_EINVAL if one is too
- * small. */
+ * POTRF adjoints; the contributions that do not involve column J + 1 run on
+ * the second stream during step J + 1. Capacities in records; counts always
+ * written; GPR_EINVAL if one is too small. */
 int gpr_adjoint_describe(int32_t M, int32_t G, int32_t* tasks, int64_t task_cap,
                          int64_t* n_tasks, int32_t* terms, int64_t term_cap,
                          int64_t* n_terms, int32_t* launches, int64_t launch_cap,

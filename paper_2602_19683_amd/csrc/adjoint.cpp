@@ -34,6 +34,14 @@
 // consecutive terms go to separate partial tiles (one task each, many
 // workgroups), and the task that consumes them adds the partials in chunk
 // order (fixed order: the result is deterministic).
+//
+// Look-ahead on two streams: the pull terms of column J that involve only
+// the columns >= J + 2 ("early": all but the terms with column J + 1) are
+// final once step J + 2 is done, so they run on a second stream while step
+// J + 1 runs its chain (TRSM adjoint, row sum, POTRF adjoint) on the caller's
+// stream; the terms with column J + 1 ("late") follow on the caller's stream.
+// Partial tiles alternate between two sets by the parity of J, so the early
+// pulls of one step never overwrite partials another step still reads.
 #include <algorithm>
 
 #include "gpr_internal.h"
@@ -44,9 +52,9 @@ namespace {
 
 struct PB {
     AdjPlan P;
-    int launch_begin(int kind, int step)
+    int launch_begin(int kind, int step, int stream = 0, int wait = -1)
     {
-        P.launches.push_back({kind, step, (int)P.tasks.size(), 0});
+        P.launches.push_back({kind, step, (int)P.tasks.size(), 0, stream, wait});
         return (int)P.launches.size() - 1;
     }
     void task(AdjRef out, AdjRef cin, int part0, int npart, int epi,
@@ -65,6 +73,11 @@ struct PB {
         P.tasks.push_back(t);
         P.launches.back().count += 1;
     }
+    // drops an empty launch just begun (no tasks)
+    void drop_if_empty()
+    {
+        if (!P.launches.empty() && P.launches.back().count == 0) P.launches.pop_back();
+    }
 };
 
 constexpr AdjRef NONE{AM_NONE, 0, 0};
@@ -72,40 +85,98 @@ AdjRef R_(int mat, int I, int J) { return AdjRef{mat, I, J}; }
 
 }  // namespace
 
+namespace {
+
+// The pull terms of tile (I, J), I > J, split by whether they involve column
+// J + 1 (late) or only columns >= J + 2 (early).
+void pull_terms(int M, int I, int J, std::vector<AdjTerm>& early, std::vector<AdjTerm>& late)
+{
+    early.clear();
+    late.clear();
+    std::vector<AdjTerm>& colI = (I == J + 1) ? late : early;
+    for (int R = I + 1; R < M; ++R)
+        colI.push_back({R_(AM_ABAR, R, I), R_(AM_L, R, J), -1, TG_TRANS_A});
+    colI.push_back({R_(AM_ABAR, I, I), R_(AM_L, I, J), -1, 0});
+    colI.push_back({R_(AM_ABAR, I, I), R_(AM_L, I, J), -1, TG_TRANS_A});
+    for (int K = J + 1; K < I; ++K)
+        (K == J + 1 ? late : early).push_back({R_(AM_ABAR, I, K), R_(AM_L, K, J), -1, 0});
+}
+
+int chunks(size_t n, int G) { return (int)((n + (size_t)G - 1) / (size_t)G); }
+
+}  // namespace
+
 AdjPlan build_adjoint(int M, int G)
 {
     PB b;
     if (G < 1) G = 1;
+    // partial tiles per step: the pulls (early chunks, then late chunks, tile
+    // by tile), or the diagonal row sum; two sets, by the parity of the step
+    std::vector<AdjTerm> e, l;
+    int per_step = 1;
+    for (int J = 0; J < M; ++J) {
+        int p = 0;
+        for (int I = J + 1; I < M; ++I) {
+            pull_terms(M, I, J, e, l);
+            p += chunks(e.size(), G) + chunks(l.size(), G);
+        }
+        per_step = std::max({per_step, p, chunks((size_t)(M - J - 1), G)});
+    }
+    b.P.max_part = 2 * per_step;
+    auto set0 = [&](int J) { return (J & 1) * per_step; };
+    // partial-tile layout of step J: tile I's early chunks at early0[I], its
+    // late chunks right after them
+    auto layout = [&](int J, std::vector<int>& early0, std::vector<int>& ne, std::vector<int>& nl) {
+        early0.assign(M, 0);
+        ne.assign(M, 0);
+        nl.assign(M, 0);
+        int p = set0(J);
+        for (int I = J + 1; I < M; ++I) {
+            pull_terms(M, I, J, e, l);
+            early0[I] = p;
+            ne[I] = chunks(e.size(), G);
+            nl[I] = chunks(l.size(), G);
+            p += ne[I] + nl[I];
+        }
+    };
+    auto emit_chunks = [&](const std::vector<AdjTerm>& t, int p0) {
+        for (size_t c = 0; c < t.size(); c += (size_t)G) {
+            const std::vector<AdjTerm> chunk(t.begin() + c, t.begin() + std::min(t.size(), c + G));
+            b.task_terms(R_(AM_PART, p0++, 0), NONE, 0, 0, TG_EPI_NONE, chunk);
+        }
+    };
+    // the early pulls of column J, on the second stream after `after`
+    std::vector<int> early_launch(M, -1);
+    auto emit_early = [&](int J, int after) {
+        if (J < 0) return;
+        std::vector<int> e0, ne, nl;
+        layout(J, e0, ne, nl);
+        b.launch_begin(AK_PART, J, 1, after);
+        for (int I = J + 1; I < M; ++I) {
+            pull_terms(M, I, J, e, l);
+            emit_chunks(e, e0[I]);
+        }
+        if (b.P.launches.back().count == 0) b.drop_if_empty();
+        else early_launch[J] = (int)b.P.launches.size() - 1;
+    };
+    // column M - 2 has no early terms (its only tile row is M - 1 = J + 1)
     for (int J = M - 1; J >= 0; --J) {
         const int nt = M - J - 1;  // tile rows below the diagonal tile
         if (nt > 0) {
-            // pulls into column J, as partial tiles: for each I > J the
-            // M - J terms in chunks of G
+            std::vector<int> e0, ne, nl;
+            layout(J, e0, ne, nl);
+            // late pulls (the terms with column J + 1)
             b.launch_begin(AK_PART, J);
-            std::vector<int> part0(M, 0), npart(M, 0);
-            int p = 0;
             for (int I = J + 1; I < M; ++I) {
-                std::vector<AdjTerm> all;
-                for (int R = I + 1; R < M; ++R)
-                    all.push_back({R_(AM_ABAR, R, I), R_(AM_L, R, J), -1, TG_TRANS_A});
-                all.push_back({R_(AM_ABAR, I, I), R_(AM_L, I, J), -1, 0});
-                all.push_back({R_(AM_ABAR, I, I), R_(AM_L, I, J), -1, TG_TRANS_A});
-                for (int K = J + 1; K < I; ++K)
-                    all.push_back({R_(AM_ABAR, I, K), R_(AM_L, K, J), -1, 0});
-                part0[I] = p;
-                for (size_t c = 0; c < all.size(); c += (size_t)G) {
-                    const std::vector<AdjTerm> chunk(all.begin() + c,
-                                                     all.begin() + std::min(all.size(), c + G));
-                    b.task_terms(R_(AM_PART, p, 0), NONE, 0, 0, TG_EPI_NONE, chunk);
-                    ++p;
-                }
-                npart[I] = p - part0[I];
+                pull_terms(M, I, J, e, l);
+                emit_chunks(l, e0[I] + ne[I]);
             }
-            b.P.max_part = std::max(b.P.max_part, p);
-            // Lbar_IJ += its partials (in place)
-            b.launch_begin(AK_PUSH, J);
+            b.drop_if_empty();
+            // Lbar_IJ += its partials (early, then late), in place
+            b.launch_begin(AK_PUSH, J, 0, early_launch[J]);
             for (int I = J + 1; I < M; ++I)
-                b.task(R_(AM_LBAR, I, J), R_(AM_LBAR, I, J), part0[I], npart[I], TG_EPI_NONE, {});
+                b.task(R_(AM_LBAR, I, J), R_(AM_LBAR, I, J), e0[I], ne[I] + nl[I], TG_EPI_NONE,
+                       {});
             // TRSM adjoint
             b.launch_begin(AK_TRSM, J);
             for (int I = J + 1; I < M; ++I)
@@ -113,17 +184,16 @@ AdjPlan build_adjoint(int M, int G)
                        {AdjTerm{R_(AM_LBAR, I, J), R_(AM_TINV, J, J), 1, TG_TRI_B}});
             // the diagonal tile's row sum -sum_{R>J} Abar_RJ^T L_RJ, in chunks
             b.launch_begin(AK_PART, J);
-            const int C = (nt + G - 1) / G;
+            const int C = chunks((size_t)nt, G);
             for (int c = 0; c < C; ++c) {
                 std::vector<AdjTerm> t;
                 for (int R = J + 1 + c * G; R < std::min(M, J + 1 + (c + 1) * G); ++R)
                     t.push_back({R_(AM_ABAR, R, J), R_(AM_L, R, J), -1, TG_TRANS_A});
-                b.task_terms(R_(AM_PART, c, 0), NONE, 0, 0, TG_EPI_NONE, t);
+                b.task_terms(R_(AM_PART, set0(J) + c, 0), NONE, 0, 0, TG_EPI_NONE, t);
             }
-            b.P.max_part = std::max(b.P.max_part, C);
             // Q = Lbar_JJ + its partials
             b.launch_begin(AK_DIAG_SUM, J);
-            b.task(R_(AM_Q, 0, 0), R_(AM_LBAR, J, J), 0, C, TG_EPI_NONE, {});
+            b.task(R_(AM_Q, 0, 0), R_(AM_LBAR, J, J), set0(J), C, TG_EPI_NONE, {});
         }
         const AdjRef Q = nt > 0 ? R_(AM_Q, 0, 0) : R_(AM_LBAR, J, J);
         // POTRF adjoint: three products on single tiles
@@ -133,9 +203,11 @@ AdjPlan build_adjoint(int M, int G)
         b.launch_begin(AK_POTRF, J);
         b.task(R_(AM_X, 0, 0), NONE, 0, 0, TG_EPI_NONE,
                {AdjTerm{R_(AM_G, 0, 0), R_(AM_TINV, J, J), 1, TG_TRI_B}});
-        b.launch_begin(AK_POTRF, J);
+        const int potrf3 = b.launch_begin(AK_POTRF, J);
         b.task(R_(AM_ABAR, J, J), NONE, 0, 0, TG_EPI_PHI,
                {AdjTerm{R_(AM_TINV, J, J), R_(AM_X, 0, 0), 1, TG_TRANS_A | TG_TRI_A}});
+        // column J - 2's early pulls need the columns >= J: now final
+        emit_early(J - 2, potrf3);
     }
     return b.P;
 }
@@ -174,8 +246,9 @@ extern "C" int gpr_adjoint_describe(int32_t M, int32_t G, int32_t* tasks, int64_
     if (launches)
         for (size_t i = 0; i < P.launches.size(); ++i) {
             const auto& L = P.launches[i];
-            int32_t* o = launches + 4 * i;
+            int32_t* o = launches + 6 * i;
             o[0] = L.kind; o[1] = L.step; o[2] = L.first; o[3] = L.count;
+            o[4] = L.stream; o[5] = L.wait;
         }
     return GPR_OK;
 }

@@ -547,13 +547,40 @@ AdjExec plan_adjoint_exec(const AdjPlan& P, const AdjBufs& B, DescBuffer& db)
     return E;
 }
 
+// The reverse sweep on two streams: the chain of each step on the caller's
+// stream s, the early pulls on a second stream (the bulk stream of the
+// context; with one stream everything runs on s in list order, which the
+// plan also allows). Waits across the streams are events.
 int run_adjoint(gpr_ctx* ctx, const AdjPlan& P, const AdjExec& E, int m, const DescBuffer& db,
                 hipStream_t s)
 {
-    for (size_t i = 0; i < P.launches.size(); ++i) {
-        ProfScope ps(ctx, s, PK_ADJOINT, E.flops[i], 0.0);
-        HIP_TRY(launch_tgemm_f64(db.dev<TGemmTask>(ctx, E.task_off[i]), P.launches[i].count,
-                                 db.dev<TGemmTerm>(ctx, E.term_off[i]), m, E.bm[i], s));
+    const auto& Ls = P.launches;
+    int rc = ensure_events(ctx, Ls.size());
+    if (rc) return rc;
+    const hipStream_t phys[2] = {s, ctx->n_streams >= 2 ? ctx->bulk : s};
+    const bool two = phys[1] != s;
+    std::vector<char> waited(Ls.size(), 0);
+    for (const auto& L : Ls)
+        if (L.wait >= 0 && phys[Ls[L.wait].stream] != phys[L.stream]) waited[L.wait] = 1;
+    if (two) {
+        HIP_TRY(hipEventRecord(ctx->ev_fork, s));
+        HIP_TRY(hipStreamWaitEvent(phys[1], ctx->ev_fork, 0));
+    }
+    for (size_t i = 0; i < Ls.size(); ++i) {
+        const AdjLaunch& L = Ls[i];
+        hipStream_t st = phys[L.stream];
+        if (L.wait >= 0 && phys[Ls[L.wait].stream] != st)
+            HIP_TRY(hipStreamWaitEvent(st, ctx->evpool[L.wait], 0));
+        {
+            ProfScope ps(ctx, st, PK_ADJOINT, E.flops[i], 0.0);
+            HIP_TRY(launch_tgemm_f64(db.dev<TGemmTask>(ctx, E.task_off[i]), L.count,
+                                     db.dev<TGemmTerm>(ctx, E.term_off[i]), m, E.bm[i], st));
+        }
+        if (waited[i]) HIP_TRY(hipEventRecord(ctx->evpool[i], st));
+    }
+    if (two) {
+        HIP_TRY(hipEventRecord(ctx->ev_join, phys[1]));
+        HIP_TRY(hipStreamWaitEvent(s, ctx->ev_join, 0));
     }
     return GPR_OK;
 }

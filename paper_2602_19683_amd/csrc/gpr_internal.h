@@ -242,6 +242,8 @@ struct AdjTask {
 };
 struct AdjLaunch {
     int kind, step, first, count;
+    int stream;  // 0: the caller's stream (the chain of each step), 1: a second stream
+    int wait;    // launch on the other stream to wait for, or -1
 };
 struct AdjPlan {
     std::vector<AdjTask> tasks;

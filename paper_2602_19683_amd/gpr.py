@@ -357,7 +357,7 @@ def schedule_describe(M, Mhat, mode):
 def adjoint_describe(M, G):
     """Host-only: the launch list of the reverse sweep of gpr_nlml_grad (see
     gpr.h). Returns ``(tasks, terms, launches)``: int32 arrays of shape
-    (T, 12), (R, 8) and (L, 4)."""
+    (T, 12), (R, 8) and (L, 6)."""
     lib = _lib.load()
     nt, nr, nl = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
     st = lib.gpr_adjoint_describe(M, G, None, 0, ctypes.byref(nt), None, 0, ctypes.byref(nr),
@@ -366,7 +366,7 @@ def adjoint_describe(M, G):
         raise GPRError(st, "gpr_adjoint_describe")
     tasks = np.zeros((nt.value, 12), dtype=np.int32)
     terms = np.zeros((nr.value, 8), dtype=np.int32)
-    launches = np.zeros((nl.value, 4), dtype=np.int32)
+    launches = np.zeros((nl.value, 6), dtype=np.int32)
     ip = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))  # noqa: E731
     _check(lib.gpr_adjoint_describe(M, G, ip(tasks), nt.value, ctypes.byref(nt), ip(terms),
                                     nr.value, ctypes.byref(nr), ip(launches), nl.value,
