@@ -34,38 +34,52 @@ __device__ inline double rsqrt_refined(double d)
 }
 
 // Cholesky factor and inverse of the 16 x 16 block S[r0.., r0..] (lower
-// triangle read), by one wave: lane i < 16 owns row i in registers and the
-// entries of column j come from their owners by readlane (right-looking); one
-// reciprocal square root per pivot. The inverse is formed one column per lane
-// by forward substitution with the stored pivot reciprocals. On return the
-// block of S holds L (zeros above the diagonal) and the block of Si holds
-// L^{-1}. Returns the first failing local column or -1.
+// triangle read), by one wave, right-looking with one reciprocal square root
+// per pivot. The 64 lanes split the block: lane (g, i) = (lane / 16, lane % 16)
+// holds row i, columns 4q + g (q = 0..3). After column j is scaled by its
+// owners (group j % 4), they write it to the LDS vector col; every lane reads
+// its row's entry and the entries of its own columns from there and updates
+// its four values. The inverse is formed one column per lane by forward
+// substitution with the stored pivot reciprocals. On return the block of S
+// holds L (zeros above the diagonal) and the block of Si holds L^{-1}. Returns
+// the first failing local column or -1. dv: 16 pivot reciprocals, col: 16
+// doubles of LDS scratch.
 __device__ inline int chol_inv16(double (*S)[NB + 1], double (*Si)[NB + 1], int r0, double* dv,
-                                 int lane)
+                                 double* col, int lane)
 {
-    const int i = lane & 15;
-    double a[16];
+    const int i = lane & 15, g = lane >> 4;
+    double a[4];  // a[q] = row i, column 4 q + g
 #pragma unroll
-    for (int k = 0; k < 16; ++k) a[k] = S[r0 + i][r0 + k];
+    for (int q = 0; q < 4; ++q) a[q] = S[r0 + i][r0 + 4 * q + g];
     int bad = -1;
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
-        const double d = lane_bcast(a[j], j);
+        const int gj = j & 3, qj = j >> 2;
+        const double d = lane_bcast(a[qj], 16 * gj + j);
         if (!(d > 0.0) && bad < 0) bad = j;
         const double inv = rsqrt_refined(d);
         const double ljj = d * inv;
-        a[j] = (i == j) ? ljj : (i > j ? a[j] * inv : 0.0);
+        if (g == gj) a[qj] = (i == j) ? ljj : (i > j ? a[qj] * inv : 0.0);
         if (lane == 0) dv[j] = inv;
+        if (j < 15) {
+            if (g == gj) col[i] = a[qj];  // column j of L (zero above the pivot)
+            wave_lds_sync();
+            const double lij = col[i];
 #pragma unroll
-        for (int k = j + 1; k < 16; ++k) {
-            const double lkj = lane_bcast(a[j], k);
-            if (i >= k) a[k] -= a[j] * lkj;
+            for (int q = 0; q < 4; ++q) {
+                // a[k] -= L[i][j] L[k][j] for the columns k > j of this lane, in
+                // rows i >= k (entries above the diagonal are left alone)
+                const int k = 4 * q + g;
+                if (k > j && i >= k) a[q] = fma(-lij, col[k], a[q]);
+            }
+            wave_lds_sync();
         }
     }
     wave_lds_sync();
-    if (lane < 16) {
 #pragma unroll
-        for (int k = 0; k < 16; ++k) S[r0 + i][r0 + k] = (k <= i) ? a[k] : 0.0;
+    for (int q = 0; q < 4; ++q) {
+        const int k = 4 * q + g;
+        S[r0 + i][r0 + k] = (k <= i) ? a[q] : 0.0;
     }
     wave_lds_sync();
     double x[16];
@@ -97,12 +111,12 @@ __device__ inline int chol_inv16(double (*S)[NB + 1], double (*Si)[NB + 1], int 
 // which halves the sequential depth of the 32-column factorisation and its
 // inverse. On return S holds L (zeros above the diagonal) and Si holds L^{-1}
 // (zeros above). Returns the first failing local column or -1. dv: 32 doubles
-// of LDS scratch.
+// and col: 16 doubles of LDS scratch.
 __device__ inline int factor_diag32(double (*S)[NB + 1], double (*Si)[NB + 1], double* dv,
-                                    int lane)
+                                    double* col, int lane)
 {
     const int lr = lane & 15, lk = lane >> 4;
-    int bad = chol_inv16(S, Si, 0, dv, lane);
+    int bad = chol_inv16(S, Si, 0, dv, col, lane);
     // L21 = A21 Y11^T
     dbl4 t = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -121,7 +135,7 @@ __device__ inline int factor_diag32(double (*S)[NB + 1], double (*Si)[NB + 1], d
 #pragma unroll
     for (int v = 0; v < 4; ++v) S[16 + drow(lk, v)][16 + lr] = u[v];
     wave_lds_sync();
-    const int bad2 = chol_inv16(S, Si, 16, dv + 16, lane);
+    const int bad2 = chol_inv16(S, Si, 16, dv + 16, col, lane);
     if (bad < 0 && bad2 >= 0) bad = 16 + bad2;
     // Y21 = -Y22 W, W = L21 Y11 (W held in the Y21 block until it is replaced)
     dbl4 w = {0.0, 0.0, 0.0, 0.0};
@@ -176,6 +190,7 @@ struct PotrfLds {
     double Sacc[NB][NB + 1];
     double Si[NB][NB + 1];
     double dv[NB];
+    double col[16];  // column broadcast of the diagonal-block factorisation
 };
 
 // Row panel w of the POTRF of the m x m tile A (see k_potrf.hip). 256 threads;
@@ -248,7 +263,7 @@ __device__ inline void potrf_panel(double* __restrict__ A, int lda, int m, doubl
     }
     __syncthreads();
     int bad = -1;
-    if (wave == 0) bad = factor_diag32(Sacc, Si, dv, lane);
+    if (wave == 0) bad = factor_diag32(Sacc, Si, dv, sh.col, lane);
     __syncthreads();
     for (int e = tid; e < NB * NB; e += 256) {
         const int r = e / NB, c = e % NB;
