@@ -121,7 +121,8 @@ def mixed_runs(ctx, K, step, mean64, cov64, ms64, flops, args, log):
             "value": round(flops / (ms * 1e-3) / 1e9, 2),
             "speedup_vs_fp64": round(ms64 / ms, 3),
             "precision_used": {0: "fp64", 1: "fp32", 2: "bf16"}[st["precision"]],
-            "ir_steps": st["iters"], "ir_rel_residual": st["rel_residual"],
+            "ir_steps": st["iters"], "ir_method": st["method"],
+            "ir_rel_residual": st["rel_residual"],
             "rel_mean_vs_fp64": rel(mean, m64),
             "rel_cov_vs_fp64": rel(cov, c64),
             "rel_L_vs_fp64": rel(torch.tril(L), torch.tril(L64)),

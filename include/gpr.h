@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define GPR_ABI_VERSION 3
+#define GPR_ABI_VERSION 4
 
 /* Status codes. */
 enum {
@@ -98,12 +98,24 @@ typedef enum {
 typedef struct gpr_ctx gpr_ctx;      /* device, streams, events, workspace   */
 typedef struct gpr_tiled gpr_tiled;  /* lower-tiled symmetric / triangular n x n matrix */
 
+/* How alpha was refined against a mixed-precision factor L~ (the paper
+ * has no mixed mode; these follow the usual FP64 refinement of a
+ * low-precision Cholesky factor). GPR_REFINE_IR: plain refinement
+ * r = y - K alpha, alpha += L~^{-T} L~^{-1} r, throughout.
+ * GPR_REFINE_PCG: plain refinement contracted too slowly (a step gained
+ * less than a factor 4 with ||r|| / ||y|| > 1e-12, as happens when
+ * kappa(K) times the unit roundoff of the updates is not small), and the
+ * remaining steps were conjugate gradients on K alpha = y preconditioned by
+ * L~ L~^T, which converge to the same FP64 alpha. */
+enum { GPR_REFINE_IR = 0, GPR_REFINE_PCG = 1 };
+
 /* Host-side refinement statistics, filled when gpr_predict returns in a
  * mixed precision (it synchronises the stream in that case). */
 typedef struct {
-    int32_t iters;              /* refinement steps taken                        */
+    int32_t iters;              /* refinement steps taken (both kinds)           */
     double rel_residual;        /* ||y - K alpha||_2 / ||y||_2 after the last one */
     int32_t fallback_precision; /* precision the factor was finally computed in  */
+    int32_t method;             /* GPR_REFINE_IR or GPR_REFINE_PCG                */
 } gpr_ir_stats;
 
 /* Tiled-matrix states. */
@@ -159,7 +171,9 @@ int gpr_cholesky_dense(gpr_ctx* ctx, double* A, int64_t n, int32_t tile,
  * row-major, both triangles written (exactly symmetric), or NULL.
  * n_test == 0 is a no-op. In a mixed precision the mean is recovered by FP64
  * iterative refinement (stop at ||r|| / ||y|| <= 1e-14, stagnation, or 50
- * steps), the call synchronises the stream and fills *ir if non-NULL. */
+ * steps; preconditioned conjugate gradients take over when plain
+ * refinement contracts too slowly, see GPR_REFINE_PCG), the call
+ * synchronises the stream and fills *ir if non-NULL. */
 int gpr_predict(gpr_ctx* ctx, gpr_tiled* L, const double* X, const double* y,
                 int64_t n, const double* Xs, int64_t n_test, int32_t D,
                 gpr_hyper h, double* mean, double* cov, gpr_ir_stats* ir,

@@ -22,7 +22,8 @@ class Hyper(ctypes.Structure):
 class IRStats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32),
                 ("rel_residual", ctypes.c_double),
-                ("fallback_precision", ctypes.c_int32)]
+                ("fallback_precision", ctypes.c_int32),
+                ("method", ctypes.c_int32)]
 
 
 _vp = ctypes.c_void_p

@@ -798,7 +798,9 @@ constexpr int RETRY_HIGHER = 100;
 // precision prec. With a mixed-precision factor, alpha is refined in FP64:
 //   r = y - K alpha (K from the saved FP64 copy), d = L^{-T} L^{-1} r,
 //   alpha += d,
-// until ||r|| / ||y|| <= 1e-14, stagnation, or 50 steps; this synchronises
+// until ||r|| / ||y|| <= 1e-14, stagnation, or 50 steps; if a step gains
+// less than a factor 4 while ||r|| / ||y|| > 1e-12, the remaining steps are
+// conjugate gradients preconditioned by the same factor. This synchronises
 // the stream once per step.
 int predict_impl(gpr_ctx* ctx, gpr_tiled* L, const double* X, const double* y, int64_t n,
                  const double* Xs, int64_t n_test, int32_t D, const gpr_hyper& h, double* mean,
@@ -808,7 +810,7 @@ int predict_impl(gpr_ctx* ctx, gpr_tiled* L, const double* X, const double* y, i
     const int m = L->m, M = L->M;
     const int Mhat = (int)((n_test + m - 1) / m);
     const size_t npad = (size_t)M * m;
-    const size_t vec_bytes = 6 * npad * sizeof(double) + 256;
+    const size_t vec_bytes = 8 * npad * sizeof(double) + 256;
     const bool rows = cov || var;  // the test rows V^T are needed
     const size_t v_bytes = rows ? (size_t)Mhat * M * m * m * sizeof(double) : 0;
     const size_t s_bytes = cov ? (size_t)Mhat * (Mhat + 1) / 2 * m * m * sizeof(double) : 0;
@@ -829,7 +831,9 @@ int predict_impl(gpr_ctx* ctx, gpr_tiled* L, const double* X, const double* y, i
     double* acc = alpha + npad;     // refined alpha
     double* scal = acc + npad;      // small scalars (norms)
     double* tmp = scal + npad;      // scratch of the triangular solves
-    double* Vb = tmp + npad;
+    double* pv = tmp + npad;        // conjugate-gradient direction p
+    double* wv = pv + npad;         // -K p
+    double* Vb = wv + npad;
     double* Sb = reinterpret_cast<double*>(reinterpret_cast<char*>(Vb) + v_bytes);
     double* mvw = reinterpret_cast<double*>(reinterpret_cast<char*>(Sb) + s_bytes);
     const int fprec = fused ? prec : L->prec;
@@ -890,6 +894,7 @@ int predict_impl(gpr_ctx* ctx, gpr_tiled* L, const double* X, const double* y, i
         ir->iters = 0;
         ir->rel_residual = -1.0;
         ir->fallback_precision = L->prec;
+        ir->method = GPR_REFINE_IR;
     }
     if (L->prec != GPR_FP64) {
         if (!L->kcopy) return GPR_EINVAL;
@@ -900,27 +905,76 @@ int predict_impl(gpr_ctx* ctx, gpr_tiled* L, const double* X, const double* y, i
         HIP_TRY(hipMemcpyAsync(&yy, scal, sizeof(double), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
         const double yn = std::sqrt(yy);
-        double prev = -1.0, rel = -1.0;
-        int it = 0;
-        for (; it <= 50; ++it) {
-            // r = y - K acc (FP64), padding of r stays zero
-            HIP_TRY(launch_symv_tiled(Kc, M, acc, y, r, n, s));
+        // ||r|| / ||y|| of the residual held in r (host round trip)
+        auto residual = [&](double* out_rel) -> int {
             HIP_TRY(launch_sumsq(r, n, scal, s));
             double rr = 0.0;
             HIP_TRY(hipMemcpyAsync(&rr, scal, sizeof(double), hipMemcpyDeviceToHost, s));
             HIP_TRY(hipStreamSynchronize(s));
             const double rn = std::sqrt(rr);
-            rel = yn > 0 ? rn / yn : rn;
-            if (rel <= 1e-14 || it == 50) break;
-            if (prev >= 0 && rn > 0.9 * prev) break;   // stagnation
-            prev = rn;
+            *out_rel = yn > 0 ? rn / yn : rn;
+            return GPR_OK;
+        };
+        constexpr int max_steps = 50;
+        double prev = -1.0, rel = -1.0;
+        int it = 0;
+        bool to_cg = false;
+        for (; it <= max_steps; ++it) {
+            // r = y - K acc (FP64), padding of r stays zero
+            HIP_TRY(launch_symv_tiled(Kc, M, acc, y, r, n, s));
+            rc = residual(&rel);
+            if (rc) return rc;
+            if (rel <= 1e-14 || it == max_steps) break;
+            // a step that gains less than a factor 4 far above the rounding
+            // floor: the iteration matrix I - (L~ L~^T)^{-1} K contracts slowly
+            // or not at all (kappa(K) u too large); go on with CG
+            if (prev >= 0 && rel > 1e-12 && rel > 0.25 * prev) {
+                to_cg = true;
+                break;
+            }
+            if (prev >= 0 && rel > 0.9 * prev) break;   // stagnation at the floor
+            prev = rel;
             rc = run_trsv_pair(ctx, L, r, tmp, beta, alpha, s);  // alpha = L^{-T} L^{-1} r
             if (rc) return rc;
             HIP_TRY(launch_axpy(acc, alpha, (int64_t)npad, s));
         }
+        if (to_cg) {
+            // Conjugate gradients on K x = y from x = acc, preconditioned by
+            // the mixed factor (z = L~^{-T} L~^{-1} r): converges to the same
+            // FP64 solution as long as L~ L~^T is positive definite, which a
+            // successful factorisation guarantees. Vectors are updated over
+            // the first n entries only, so the padding of r, acc and p stays
+            // zero. The loop stops on the updated residual; the true
+            // residual of the last iterate is reported.
+            double* z = alpha;
+            double* pw = scal + 1;
+            rc = run_trsv_pair(ctx, L, r, tmp, beta, z, s);
+            if (rc) return rc;
+            HIP_TRY(launch_dot(r, z, n, scal + 2, s));
+            HIP_TRY(launch_copy_f64(z, pv, n, (int64_t)npad, s));
+            for (int k = 0; it < max_steps; ++k) {
+                ++it;
+                double* rz = scal + 2 + (k & 1);
+                double* rz_next = scal + 2 + ((k + 1) & 1);
+                HIP_TRY(launch_symv_tiled(Kc, M, pv, nullptr, wv, n, s));  // w = -K p
+                HIP_TRY(launch_dot(pv, wv, n, pw, s));
+                HIP_TRY(launch_cg_xr(acc, r, pv, wv, rz, pw, n, s));
+                rc = residual(&rel);
+                if (rc) return rc;
+                if (!(rel > 1e-14)) break;   // converged, or not finite
+                rc = run_trsv_pair(ctx, L, r, tmp, beta, z, s);
+                if (rc) return rc;
+                HIP_TRY(launch_dot(r, z, n, rz_next, s));
+                HIP_TRY(launch_cg_p(pv, z, rz_next, rz, n, s));
+            }
+            HIP_TRY(launch_symv_tiled(Kc, M, acc, y, r, n, s));
+            rc = residual(&rel);
+            if (rc) return rc;
+        }
         if (ir) {
             ir->iters = it;
             ir->rel_residual = rel;
+            ir->method = to_cg ? GPR_REFINE_PCG : GPR_REFINE_IR;
         }
         // not converged to where the mean can be trusted: let a fused caller retry
         if (fused && !(rel <= 1e-10)) return RETRY_HIGHER;

@@ -146,9 +146,18 @@ hipError_t launch_update_mixed(const UpdateTask* d_tasks, int ntask, int m, int 
 
 // out[0] = sum x_i^2 (deterministic).
 hipError_t launch_sumsq(const double* x, int64_t n, double* out, hipStream_t s);
+// out[0] = sum x_i y_i (deterministic).
+hipError_t launch_dot(const double* x, const double* y, int64_t n, double* out, hipStream_t s);
 // y += x
 hipError_t launch_axpy(double* y, const double* x, int64_t n, hipStream_t s);
-// out = base - K x for K stored as M lower tiles (diagonal tiles full), rows < n.
+// Conjugate-gradient updates, scalars in device memory: with w = -K p,
+// a = rz / -pw, x += a p, r += a w; and p = z + (rz_new / rz_old) p.
+hipError_t launch_cg_xr(double* x, double* r, const double* p, const double* w,
+                        const double* rz, const double* pw, int64_t n, hipStream_t s);
+hipError_t launch_cg_p(double* p, const double* z, const double* rz_new, const double* rz_old,
+                       int64_t n, hipStream_t s);
+// out = base - K x (base null: out = -K x) for K stored as M lower tiles
+// (diagonal tiles full), rows < n.
 hipError_t launch_symv_tiled(const TileMat& K, int M, const double* x, const double* base,
                              double* out, int64_t n, hipStream_t s);
 

@@ -180,6 +180,80 @@ hipError_t launch_sumsq(const double* x, int64_t n, double* out, hipStream_t s)
     return hipGetLastError();
 }
 
+// out[0] = sum x_i y_i, in the same fixed order as k_sumsq.
+__global__ __launch_bounds__(256) void k_dot(const double* __restrict__ x,
+                                            const double* __restrict__ y, int64_t n,
+                                            double* __restrict__ out)
+{
+    __shared__ double part[256];
+    const int tid = threadIdx.x;
+    double s = 0.0;
+    for (int64_t i = tid; i < n; i += 256) s += x[i] * y[i];
+    part[tid] = s;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if (tid < w) part[tid] += part[tid + w];
+        __syncthreads();
+    }
+    if (tid == 0) out[0] = part[0];
+}
+
+hipError_t launch_dot(const double* x, const double* y, int64_t n, double* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_dot, dim3(1), dim3(256), 0, s, x, y, n, out);
+    return hipGetLastError();
+}
+
+// Conjugate-gradient vector updates with the scalars kept in device memory
+// (no host round trip inside an iteration). With w = -K p:
+//   a = rz / (p^T K p) = rz / (-pw);  x += a p;  r += a w   (r -= a K p)
+__global__ void k_cg_xr(double* __restrict__ x, double* __restrict__ r,
+                        const double* __restrict__ p, const double* __restrict__ w,
+                        const double* __restrict__ rz, const double* __restrict__ pw, int64_t n)
+{
+    const double a = rz[0] / -pw[0];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        x[i] += a * p[i];
+        r[i] += a * w[i];
+    }
+}
+
+//   p = z + (rz_new / rz_old) p
+__global__ void k_cg_p(double* __restrict__ p, const double* __restrict__ z,
+                       const double* __restrict__ rz_new, const double* __restrict__ rz_old,
+                       int64_t n)
+{
+    const double b = rz_new[0] / rz_old[0];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = z[i] + b * p[i];
+}
+
+namespace {
+unsigned vec_blocks(int64_t n)
+{
+    int64_t b = (n + 255) / 256;
+    return (unsigned)(b > 2048 ? 2048 : b);
+}
+}  // namespace
+
+hipError_t launch_cg_xr(double* x, double* r, const double* p, const double* w,
+                        const double* rz, const double* pw, int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cg_xr, dim3(vec_blocks(n)), dim3(256), 0, s, x, r, p, w, rz, pw, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg_p(double* p, const double* z, const double* rz_new, const double* rz_old,
+                       int64_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cg_p, dim3(vec_blocks(n)), dim3(256), 0, s, p, z, rz_new, rz_old, n);
+    return hipGetLastError();
+}
+
 // y[i] += x[i]
 __global__ void k_axpy(double* __restrict__ y, const double* __restrict__ x, int64_t n)
 {
@@ -197,7 +271,8 @@ hipError_t launch_axpy(double* y, const double* x, int64_t n, hipStream_t s)
     return hipGetLastError();
 }
 
-// out_i = base_i - (K x)_i for the symmetric matrix stored as lower tiles
+// out_i = base_i - (K x)_i (base may be null: out = -K x) for the symmetric
+// matrix stored as lower tiles
 // (diagonal tiles hold both triangles). Workgroup (I, b) owns rows
 // I m + 32 b .. + 31: it adds the tile-row part sum_{J <= I} K_IJ x_J and the
 // transposed tile-column part sum_{I' > I} K_{I'I}^T x_{I'} in a fixed order
@@ -252,7 +327,7 @@ __global__ __launch_bounds__(256) void k_symv_tiled(TileMat K, int M, const doub
 #pragma unroll
         for (int q = 1; q < 8; ++q) tr += part[q][8 * wave + lane];
         const int64_t gi = (int64_t)I * m + row;
-        if (gi < n) out[gi] = base[gi] - (tot + tr);
+        if (gi < n) out[gi] = (base ? base[gi] : 0.0) - (tot + tr);
     }
 }
 

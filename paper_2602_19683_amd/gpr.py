@@ -47,6 +47,13 @@ def _dev_ptr(t, name, numel=None):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def _ir_dict(st):
+    """Refinement statistics as a dict; method "ir" (plain refinement) or "pcg"
+    (conjugate gradients preconditioned by the mixed factor took over)."""
+    return {"iters": st.iters, "rel_residual": st.rel_residual,
+            "precision": st.fallback_precision, "method": "pcg" if st.method == 1 else "ir"}
+
+
 def _stream(stream=None):
     import torch
     if stream is None:
@@ -170,8 +177,7 @@ class Context:
                                      ctypes.byref(st), _stream(stream)), "gpr_predict")
         out = (mean, cov if full_cov else None)
         if ir_stats:
-            return out + ({"iters": st.iters, "rel_residual": st.rel_residual,
-                           "precision": st.fallback_precision},)
+            return out + (_ir_dict(st),)
         return out
 
     def fit_predict(self, X, y, Xs, hyper, tile, precision="fp64", full_cov=True, K=None,
@@ -198,8 +204,7 @@ class Context:
         K = K if K is not None else Tiled(h, self)
         out = (mean, cov if full_cov else None, K)
         if ir_stats:
-            return out + ({"iters": st.iters, "rel_residual": st.rel_residual,
-                           "precision": st.fallback_precision},)
+            return out + (_ir_dict(st),)
         return out
 
     def predict_var(self, L, X, y, Xs, hyper, full_cov=False, mean=None, var=None, cov=None,
@@ -222,8 +227,7 @@ class Context:
                                          _stream(stream)), "gpr_predict_var")
         out = (mean, var, cov if full_cov else None)
         if ir_stats:
-            return out + ({"iters": st.iters, "rel_residual": st.rel_residual,
-                           "precision": st.fallback_precision},)
+            return out + (_ir_dict(st),)
         return out
 
     def fit_predict_var(self, X, y, Xs, hyper, tile, precision="fp64", full_cov=False, K=None,
@@ -250,8 +254,7 @@ class Context:
         K = K if K is not None else Tiled(h, self)
         out = (mean, var, cov if full_cov else None, K)
         if ir_stats:
-            return out + ({"iters": st.iters, "rel_residual": st.rel_residual,
-                           "precision": st.fallback_precision},)
+            return out + (_ir_dict(st),)
         return out
 
     def solve(self, L, b, x=None, stream=None):

@@ -341,6 +341,35 @@ def test_mixed_fit_predict(ctx, prec, n, ns, tile):
     K.free()
 
 
+def test_bf16_refinement_switches_to_pcg(ctx):
+    """n = 8192, tile 256, BF16 updates: kappa(K) u_bf16 is large enough that
+    plain refinement does not contract (a CPU emulation of the BF16 sweep
+    shows the residual growing by ~1.9x per step), while conjugate gradients
+    preconditioned by the same factor converge (about 20 steps in the
+    emulation). The mean must meet the mixed bar against the oracle in
+    whichever precision was finally used; if BF16 was kept, refinement must
+    have switched to PCG and converged."""
+    n, ns, tile = 8192, 512, 256
+    say(f"bf16 refinement n={n} n_test={ns} tile={tile}")
+    X, y, Xs = nfir_train_test(n, ns)
+    ref = oracle.predict(X, y, Xs, DEFAULT_HYPER, want=("mean",))
+    Xd, yd, Xsd = dev(X), dev(y), dev(Xs)
+    mean, _, K, st = ctx.fit_predict(Xd, yd, Xsd, DEFAULT_HYPER, tile, precision="bf16",
+                                     full_cov=False, ir_stats=True)
+    em = oracle.rel_err(host(mean), ref["mean"])
+    say(f"  steps {st['iters']} ({st['method']}), ||r||/||y|| {st['rel_residual']:.2e}, "
+        f"precision used {st['precision']}; rel(mean) {em:.2e}")
+    assert em <= MEAN_TOL_MIXED
+    if st["precision"] == 2:
+        assert st["method"] == "pcg" and st["rel_residual"] <= 1e-10
+    # the factor alone, refined again through gpr_predict: the same refinement
+    if st["precision"] == 2:
+        m2, _, st2 = ctx.predict(K, Xd, yd, Xsd, DEFAULT_HYPER, full_cov=False, ir_stats=True)
+        np.testing.assert_array_equal(host(m2), host(mean))
+        assert st2["iters"] == st["iters"] and st2["method"] == "pcg"
+    K.free()
+
+
 def test_mixed_cholesky_then_predict(ctx):
     n, ns, tile = 1024, 128, 128
     say(f"mixed fp32 cholesky + predict n={n} n_test={ns} tile={tile}")
