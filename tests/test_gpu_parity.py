@@ -318,7 +318,7 @@ MEAN_TOL_MIXED = 1e-8
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
-@pytest.mark.parametrize("n,ns,tile", [(1024, 256, 128), (4096, 1024, 256)])
+@pytest.mark.parametrize("n,ns,tile", [(1024, 256, 128), (4096, 1024, 256), (4000, 500, 256)])
 def test_mixed_fit_predict(ctx, prec, n, ns, tile):
     say(f"mixed {prec} fit_predict n={n} n_test={ns} tile={tile}")
     X, y, Xs = nfir_train_test(n, ns)
@@ -331,8 +331,9 @@ def test_mixed_fit_predict(ctx, prec, n, ns, tile):
     em = oracle.rel_err(m, ref["mean"])
     ec = oracle.rel_err(c, ref["cov"])
     el = oracle.rel_err_lower(L, ref["L"])
-    say(f"  IR steps {st['iters']}, ||r||/||y|| {st['rel_residual']:.2e}, precision used "
-        f"{st['precision']}; rel(mean) {em:.2e}  rel(L) {el:.2e}  rel(cov) {ec:.2e}")
+    say(f"  refinement steps {st['iters']} ({st['method']}), ||r||/||y|| "
+        f"{st['rel_residual']:.2e}, precision used {st['precision']}; rel(mean) {em:.2e}  "
+        f"rel(L) {el:.2e}  rel(cov) {ec:.2e}")
     assert em <= MEAN_TOL_MIXED
     np.testing.assert_array_equal(c, c.T)
     if st["precision"] != 0:

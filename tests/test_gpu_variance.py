@@ -106,3 +106,31 @@ def test_variance_full_size(ctxs):
     assert v1.min() >= -1e-12 * v and v1.max() <= v * (1 + 1e-12)
     K.free()
     K2.free()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_variance_mixed(ctxs, prec):
+    """Mixed-precision updates with the variances only: the mean meets the
+    mixed bar (1e-8) against the oracle after refinement, the variances carry
+    the error of the low-precision V^T (stated, not pinned; bounded loosely),
+    and with the covariance as well, var is its diagonal bit for bit."""
+    n, ns, tile = 4000, 500, 256
+    say(f"variance mixed {prec} n={n} n_test={ns} tile={tile}")
+    s, _ = ctxs
+    X, y, Xs = nfir_train_test(n, ns)
+    Xd, yd, Xsd = dev(X), dev(y), dev(Xs)
+    ref = oracle.predict(X, y, Xs, DEFAULT_HYPER)
+    mean, var, _, K, st = s.fit_predict_var(Xd, yd, Xsd, DEFAULT_HYPER, tile, precision=prec,
+                                            ir_stats=True)
+    em = oracle.rel_err(host(mean), ref["mean"])
+    ev = oracle.rel_err(host(var), np.diag(ref["cov"]))
+    say(f"  refinement {st['iters']} ({st['method']}), precision used {st['precision']}; "
+        f"rel(mean) {em:.2e} rel(var) {ev:.2e}")
+    assert em <= 1e-8
+    assert ev <= (1e-3 if st["precision"] == 1 else 1e-1)
+    m2, v2, c2, K2 = s.fit_predict_var(Xd, yd, Xsd, DEFAULT_HYPER, tile, precision=prec,
+                                       full_cov=True)
+    np.testing.assert_array_equal(host(v2), np.diag(host(c2)))
+    assert s.sync()[0] == 0
+    K.free()
+    K2.free()
