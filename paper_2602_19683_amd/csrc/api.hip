@@ -815,8 +815,11 @@ int predict_impl(gpr_ctx* ctx, gpr_tiled* L, const double* X, const double* y, i
     const size_t v_bytes = rows ? (size_t)Mhat * M * m * m * sizeof(double) : 0;
     const size_t s_bytes = cov ? (size_t)Mhat * (Mhat + 1) / 2 * m * m * sizeof(double) : 0;
     const size_t mv_bytes = (size_t)matvec_chunks(n_test, n) * n_test * sizeof(double);
+    const int fprec = fused ? prec : L->prec;
+    // partial products of the refinement's K x (mixed precision only)
+    const size_t sv_bytes = fprec != GPR_FP64 ? symv_work_doubles(M, m) * sizeof(double) : 0;
     int rc = ensure_device_bytes(&ctx->d_ws, &ctx->ws_cap,
-                                 vec_bytes + v_bytes + s_bytes + mv_bytes);
+                                 vec_bytes + v_bytes + s_bytes + mv_bytes + sv_bytes);
     if (rc) return rc;
     if (fused && !L->tinv) {
         if (hipMalloc(reinterpret_cast<void**>(&L->tinv), (size_t)M * m * m * sizeof(double)) !=
@@ -836,7 +839,7 @@ int predict_impl(gpr_ctx* ctx, gpr_tiled* L, const double* X, const double* y, i
     double* Vb = wv + npad;
     double* Sb = reinterpret_cast<double*>(reinterpret_cast<char*>(Vb) + v_bytes);
     double* mvw = reinterpret_cast<double*>(reinterpret_cast<char*>(Sb) + s_bytes);
-    const int fprec = fused ? prec : L->prec;
+    double* svw = reinterpret_cast<double*>(reinterpret_cast<char*>(mvw) + mv_bytes);
 
     DescBuffer db;
     SweepMats SM{kmat(L), L->tinv, TileMat{Vb, m, 1, M}, TileMat{Sb, m, 0, 0}, M,
@@ -921,7 +924,7 @@ int predict_impl(gpr_ctx* ctx, gpr_tiled* L, const double* X, const double* y, i
         bool to_cg = false;
         for (; it <= max_steps; ++it) {
             // r = y - K acc (FP64), padding of r stays zero
-            HIP_TRY(launch_symv_tiled(Kc, M, acc, y, r, n, s));
+            HIP_TRY(launch_symv_tiled(Kc, M, acc, y, r, n, svw, s));
             rc = residual(&rel);
             if (rc) return rc;
             if (rel <= 1e-14 || it == max_steps) break;
@@ -956,7 +959,7 @@ int predict_impl(gpr_ctx* ctx, gpr_tiled* L, const double* X, const double* y, i
                 ++it;
                 double* rz = scal + 2 + (k & 1);
                 double* rz_next = scal + 2 + ((k + 1) & 1);
-                HIP_TRY(launch_symv_tiled(Kc, M, pv, nullptr, wv, n, s));  // w = -K p
+                HIP_TRY(launch_symv_tiled(Kc, M, pv, nullptr, wv, n, svw, s));  // w = -K p
                 HIP_TRY(launch_dot(pv, wv, n, pw, s));
                 HIP_TRY(launch_cg_xr(acc, r, pv, wv, rz, pw, n, s));
                 rc = residual(&rel);
@@ -967,7 +970,7 @@ int predict_impl(gpr_ctx* ctx, gpr_tiled* L, const double* X, const double* y, i
                 HIP_TRY(launch_dot(r, z, n, rz_next, s));
                 HIP_TRY(launch_cg_p(pv, z, rz_next, rz, n, s));
             }
-            HIP_TRY(launch_symv_tiled(Kc, M, acc, y, r, n, s));
+            HIP_TRY(launch_symv_tiled(Kc, M, acc, y, r, n, svw, s));
             rc = residual(&rel);
             if (rc) return rc;
         }

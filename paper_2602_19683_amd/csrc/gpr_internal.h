@@ -157,9 +157,11 @@ hipError_t launch_cg_xr(double* x, double* r, const double* p, const double* w,
 hipError_t launch_cg_p(double* p, const double* z, const double* rz_new, const double* rz_old,
                        int64_t n, hipStream_t s);
 // out = base - K x (base null: out = -K x) for K stored as M lower tiles
-// (diagonal tiles full), rows < n.
+// (diagonal tiles full), rows < n; work: symv_work_doubles(M, m) doubles of
+// partial products (m a multiple of 32, at most 1024).
+size_t symv_work_doubles(int M, int m);
 hipError_t launch_symv_tiled(const TileMat& K, int M, const double* x, const double* base,
-                             double* out, int64_t n, hipStream_t s);
+                             double* out, int64_t n, double* work, hipStream_t s);
 
 // Adjoint sweep tile products; bm in {32, 64, 128} divides m.
 int tgemm_block(int ntask, int m);

@@ -272,69 +272,144 @@ hipError_t launch_axpy(double* y, const double* x, int64_t n, hipStream_t s)
 }
 
 // out_i = base_i - (K x)_i (base may be null: out = -K x) for the symmetric
-// matrix stored as lower tiles
-// (diagonal tiles hold both triangles). Workgroup (I, b) owns rows
-// I m + 32 b .. + 31: it adds the tile-row part sum_{J <= I} K_IJ x_J and the
-// transposed tile-column part sum_{I' > I} K_{I'I}^T x_{I'} in a fixed order
-// (no atomics), reading each off-diagonal tile twice over the whole launch.
-__global__ __launch_bounds__(256) void k_symv_tiled(TileMat K, int M, const double* __restrict__ x,
-                                                    const double* __restrict__ base,
-                                                    double* __restrict__ out, int64_t n)
+// matrix stored as M lower tiles (layout 0, diagonal tiles full):
+//   (K x)_I = sum_{J <= I} K_IJ x_J + sum_{I' > I} K_{I'I}^T x_{I'}.
+// Pass 1 reads every stored tile once: workgroup (t, s) takes rows
+// 32 s .. 32 s + 31 of lower tile t = (I, J) and writes those rows of K_IJ x_J
+// (complete) to prow[t], and, for I > J, the part of K_IJ^T x_I over its 32
+// rows (a length-m partial) to pcol[t][s]. Pass 2 adds, for each output row,
+// its I + 1 row products and (M - 1 - I) m / 32 column partials in a fixed
+// order. No atomics: the result is bitwise reproducible.
+namespace {
+constexpr int SV_R = 32;   // rows per pass-1 workgroup (8 per wave)
+constexpr int SV_KC = 4;   // column groups of 64 per load chunk (32 loads in flight)
+}
+
+size_t symv_work_doubles(int M, int m)
 {
-    __shared__ double part[8][32];
-    const int m = K.m;
-    const int per = m / 32;
-    const int I = blockIdx.x / per, b = blockIdx.x % per;
+    const size_t T = (size_t)M * (M + 1) / 2;
+    return T * m + T * (size_t)(m / SV_R) * m;
+}
+
+__global__ __launch_bounds__(256) void k_symv_part(TileMat K, const double* __restrict__ x,
+                                                   double* __restrict__ prow,
+                                                   double* __restrict__ pcol)
+{
+    __shared__ double part[4][1024];
+    const int m = K.m, S = m / SV_R;
+    const int t = blockIdx.x / S, s = blockIdx.x % S;
+    int I = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+    while ((I + 1) * (I + 2) / 2 <= t) ++I;
+    while (I * (I + 1) / 2 > t) --I;
+    const int J = t - I * (I + 1) / 2;
+    const bool offd = I > J;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    // row part: wave w takes rows 8w .. 8w+7 of the block, lanes stride columns
-    double s[8];
+    const int row0 = SV_R * s + 8 * wave;  // this wave's 8 rows, within the tile
+    const double* T = tile_ptr(K, I, J) + (size_t)row0 * m;
+    const double* xJ = x + (size_t)J * m;
+    const double* xI = x + (size_t)I * m + row0;
+    double xr[8], rs[8];
 #pragma unroll
-    for (int r = 0; r < 8; ++r) s[r] = 0.0;
-    for (int J = 0; J <= I; ++J) {
-        const double* T = tile_ptr(K, I, J) + (size_t)(32 * b + 8 * wave) * m;
-        const double* xj = x + (size_t)J * m;
-        for (int c = lane; c < m; c += 64) {
-            const double xc = xj[c];
+    for (int r = 0; r < 8; ++r) {
+        xr[r] = xI[r];
+        rs[r] = 0.0;
+    }
+    const int G = (m + 63) / 64;  // column groups of 64
+    for (int k0 = 0; k0 < G; k0 += SV_KC) {
+        double a[8][SV_KC], xc[SV_KC];
 #pragma unroll
-            for (int r = 0; r < 8; ++r) s[r] += T[(size_t)r * m + c] * xc;
+        for (int kk = 0; kk < SV_KC; ++kk) {
+            const int c = lane + 64 * (k0 + kk);
+            const bool in = k0 + kk < G && c < m;
+            xc[kk] = in ? xJ[c] : 0.0;
+#pragma unroll
+            for (int r = 0; r < 8; ++r) a[r][kk] = in ? T[(size_t)r * m + c] : 0.0;
+        }
+#pragma unroll
+        for (int kk = 0; kk < SV_KC; ++kk) {
+#pragma unroll
+            for (int r = 0; r < 8; ++r) rs[r] = fma(a[r][kk], xc[kk], rs[r]);
+            const int c = lane + 64 * (k0 + kk);
+            if (offd && k0 + kk < G && c < m) {
+                double cs = 0.0;
+#pragma unroll
+                for (int r = 0; r < 8; ++r) cs = fma(a[r][kk], xr[r], cs);
+                part[wave][c] = cs;
+            }
         }
     }
 #pragma unroll
-    for (int r = 0; r < 8; ++r) {
-        double v = s[r];
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-        s[r] = v;
-    }
-    // transposed part: thread (g, c) sums column 32 b + c over row group g of
-    // every tile below the diagonal in tile column I
-    const int c = tid & 31, g = tid >> 5;
-    double t = 0.0;
-    for (int Ip = I + 1; Ip < M; ++Ip) {
-        const double* T = tile_ptr(K, Ip, I) + 32 * b + c;
-        const double* xi = x + (size_t)Ip * m;
-        const int rows = m / 8;
-        for (int r = g * rows; r < (g + 1) * rows; ++r) t += T[(size_t)r * m] * xi[r];
-    }
-    part[g][c] = t;
-    __syncthreads();
+    for (int r = 0; r < 8; ++r) rs[r] = wave_sum(rs[r]);
     if (lane < 8) {
-        const int row = 32 * b + 8 * wave + lane;     // row within the tile row
-        double tot = s[0];
+        double v = rs[0];
 #pragma unroll
-        for (int r = 1; r < 8; ++r) tot = (lane == r) ? s[r] : tot;
-        double tr = part[0][8 * wave + lane];
+        for (int r = 1; r < 8; ++r) v = (lane == r) ? rs[r] : v;
+        prow[(size_t)t * m + row0 + lane] = v;
+    }
+    if (offd) {
+        __syncthreads();
+        double* pc = pcol + ((size_t)t * S + s) * m;
+        for (int c = tid; c < m; c += 256)
+            pc[c] = ((part[0][c] + part[1][c]) + part[2][c]) + part[3][c];
+    }
+}
+
+// Pass 2: workgroup b takes output rows 32 b .. 32 b + 31 (one tile row I,
+// since m is a multiple of 32); thread (g, e), g < 8, adds entries g, g + 8,
+// ... of row e's list (the row products of tiles (I, 0..I), then the column
+// partials of tiles (I + 1.., I) slice by slice); the 8 sums are added in g
+// order.
+__global__ __launch_bounds__(256) void k_symv_sum(int M, int m, const double* __restrict__ prow,
+                                                  const double* __restrict__ pcol,
+                                                  const double* __restrict__ base,
+                                                  double* __restrict__ out, int64_t n)
+{
+    __shared__ double part[8][32];
+    const int S = m / SV_R;
+    const int tid = threadIdx.x, e = tid & 31, g = tid >> 5;
+    const int64_t i = (int64_t)blockIdx.x * 32 + e;
+    const int I = (int)(i / m), li = (int)(i % m);
+    const int nrow = I + 1, ntot = nrow + (M - 1 - I) * S;
+    double acc = 0.0;
+    for (int q0 = g; q0 < ntot; q0 += 8 * 8) {
+        double v[8];
 #pragma unroll
-        for (int q = 1; q < 8; ++q) tr += part[q][8 * wave + lane];
-        const int64_t gi = (int64_t)I * m + row;
-        if (gi < n) out[gi] = (base ? base[gi] : 0.0) - (tot + tr);
+        for (int u = 0; u < 8; ++u) {
+            const int q = q0 + 8 * u;
+            const double* p = nullptr;
+            if (q < nrow) {
+                p = prow + (size_t)(I * (I + 1) / 2 + q) * m;
+            } else if (q < ntot) {
+                const int w = q - nrow, Ip = I + 1 + w / S, sp = w % S;
+                p = pcol + ((size_t)(Ip * (Ip + 1) / 2 + I) * S + sp) * m;
+            }
+            v[u] = p ? p[li] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += v[u];
+    }
+    part[g][e] = acc;
+    __syncthreads();
+    if (tid < 32 && i < n) {
+        double tot = part[0][e];
+#pragma unroll
+        for (int q = 1; q < 8; ++q) tot += part[q][e];
+        out[i] = (base ? base[i] : 0.0) - tot;
     }
 }
 
 hipError_t launch_symv_tiled(const TileMat& K, int M, const double* x, const double* base,
-                             double* out, int64_t n, hipStream_t s)
+                             double* out, int64_t n, double* work, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_symv_tiled, dim3(M * (K.m / 32)), dim3(256), 0, s, K, M, x, base, out, n);
+    const int m = K.m;
+    if (M <= 0 || m % SV_R || m > 1024) return hipErrorInvalidValue;
+    const size_t T = (size_t)M * (M + 1) / 2;
+    double* prow = work;
+    double* pcol = work + T * m;
+    hipLaunchKernelGGL(k_symv_part, dim3((unsigned)(T * (m / SV_R))), dim3(256), 0, s, K, x, prow,
+                       pcol);
+    hipLaunchKernelGGL(k_symv_sum, dim3((unsigned)((size_t)M * m / 32)), dim3(256), 0, s, M, m,
+                       prow, pcol, base, out, n);
     return hipGetLastError();
 }
 
