@@ -31,12 +31,12 @@ __device__ inline dbl4 accum32(const double* __restrict__ A, int lda, const doub
         for (int u = 0; u < NL; ++u) {
             const int e = tid + 256 * u;
             const int r = e / CPR, c = (e % CPR) * 2;  // row r (< 32), columns c, c + 1
-            ra[u] = *reinterpret_cast<const double2*>(A + (size_t)r * lda + k0 + c);
+            ra[u] = gld2(A + (size_t)r * lda + k0 + c);
             if (NT) {
-                rb[u] = *reinterpret_cast<const double2*>(B + (size_t)r * ldb + k0 + c);
+                rb[u] = gld2(B + (size_t)r * ldb + k0 + c);
             } else {
                 const int kr = e >> 4, jc = (e & 15) * 2;  // k row (< KC), columns jc, jc + 1
-                rb[u] = *reinterpret_cast<const double2*>(B + (size_t)(k0 + kr) * ldb + jc);
+                rb[u] = gld2(B + (size_t)(k0 + kr) * ldb + jc);
             }
         }
     };

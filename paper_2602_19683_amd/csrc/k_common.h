@@ -7,6 +7,31 @@ namespace gpr {
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
+// Loads and stores through pointers that address device memory. Pointers read
+// from task descriptors have no known address space, so plain accesses
+// compile to flat instructions; a flat load also counts against the LDS
+// counter, and the wait for an LDS read then waits for it too (a prefetch
+// from HBM would stall the MFMA loop). These go through the global address
+// space instead.
+template <typename T>
+__device__ inline T gld(const T* p)
+{
+    return *(const __attribute__((address_space(1))) T*)p;
+}
+template <typename T>
+__device__ inline void gst(T* p, T v)
+{
+    *(__attribute__((address_space(1))) T*)p = v;
+}
+// Two consecutive doubles (16-byte aligned) as one global load; HIP's
+// double2 is a class whose copy would go through a generic reference.
+typedef double dbl2v __attribute__((ext_vector_type(2)));
+__device__ inline double2 gld2(const double* p)
+{
+    const dbl2v v = *(const __attribute__((address_space(1))) dbl2v*)p;
+    return make_double2(v.x, v.y);
+}
+
 // MI355X has 8 XCDs, each with its own L2; consecutive workgroup ids are
 // dealt round-robin to the XCDs. This maps the hardware id to a logical id so
 // that logical ids [x*q, (x+1)*q) all run on XCD x: the workgroups of one

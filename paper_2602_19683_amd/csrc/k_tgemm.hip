@@ -67,7 +67,7 @@ __global__ __launch_bounds__(WR * WC * 64, WR * WC / 2) void k_tgemm_f64(
                 const int r = e / (KB / 2), kk = (e % (KB / 2)) * 2;
                 srow = i0 + r;
                 scol = k0 + kk;
-                ra[u] = *reinterpret_cast<const double2*>(tm.A + (size_t)srow * tm.lda + scol);
+                ra[u] = gld2(tm.A + (size_t)srow * tm.lda + scol);
                 if (tm.flags & TG_TRI_A) {
                     if (scol > srow) ra[u].x = 0.0;
                     if (scol + 1 > srow) ra[u].y = 0.0;
@@ -76,7 +76,7 @@ __global__ __launch_bounds__(WR * WC * 64, WR * WC / 2) void k_tgemm_f64(
                 const int kk = e / (BM / 2), r = (e % (BM / 2)) * 2;
                 srow = k0 + kk;
                 scol = i0 + r;
-                ra[u] = *reinterpret_cast<const double2*>(tm.A + (size_t)srow * tm.lda + scol);
+                ra[u] = gld2(tm.A + (size_t)srow * tm.lda + scol);
                 if (tm.flags & TG_TRI_A) {
                     if (scol > srow) ra[u].x = 0.0;
                     if (scol + 1 > srow) ra[u].y = 0.0;
@@ -86,7 +86,7 @@ __global__ __launch_bounds__(WR * WC * 64, WR * WC / 2) void k_tgemm_f64(
                 const int c = e / (KB / 2), kk = (e % (KB / 2)) * 2;
                 srow = j0 + c;
                 scol = k0 + kk;
-                rb[u] = *reinterpret_cast<const double2*>(tm.B + (size_t)srow * tm.ldb + scol);
+                rb[u] = gld2(tm.B + (size_t)srow * tm.ldb + scol);
                 if (tm.flags & TG_TRI_B) {
                     if (scol > srow) rb[u].x = 0.0;
                     if (scol + 1 > srow) rb[u].y = 0.0;
@@ -95,7 +95,7 @@ __global__ __launch_bounds__(WR * WC * 64, WR * WC / 2) void k_tgemm_f64(
                 const int kk = e / (BM / 2), c = (e % (BM / 2)) * 2;
                 srow = k0 + kk;
                 scol = j0 + c;
-                rb[u] = *reinterpret_cast<const double2*>(tm.B + (size_t)srow * tm.ldb + scol);
+                rb[u] = gld2(tm.B + (size_t)srow * tm.ldb + scol);
                 if (tm.flags & TG_TRI_B) {
                     if (scol > srow) rb[u].x = 0.0;
                     if (scol + 1 > srow) rb[u].y = 0.0;
@@ -162,16 +162,16 @@ __global__ __launch_bounds__(WR * WC * 64, WR * WC / 2) void k_tgemm_f64(
                 const int gi = i0 + wr + 16 * i + drow(lk, v);
                 const int gj = j0 + wc + 16 * j + lr;
                 double val = acc[i][j][v];
-                if (tk.beta != 0.0) val += tk.beta * tk.Cin[(size_t)gi * tk.ldcin + gj];
+                if (tk.beta != 0.0) val += tk.beta * gld(tk.Cin + (size_t)gi * tk.ldcin + gj);
                 for (int p = 0; p < tk.npart; ++p)
-                    val += tk.part[(size_t)p * tk.part_stride + (size_t)gi * m + gj];
+                    val += gld(tk.part + (size_t)p * tk.part_stride + (size_t)gi * m + gj);
                 if (tk.epi == TG_EPI_PHI) {
-                    tk.C[(size_t)gi * tk.ldc + gj] = gj > gi ? 0.0 : (gj == gi ? 0.5 * val : val);
+                    gst(tk.C + (size_t)gi * tk.ldc + gj, gj > gi ? 0.0 : (gj == gi ? 0.5 * val : val));
                 } else if (tk.epi == TG_EPI_SYM) {
-                    if (gi >= gj) tk.C[(size_t)gi * tk.ldc + gj] = val;
-                    if (gi > gj) tk.C[(size_t)gj * tk.ldc + gi] = val;
+                    if (gi >= gj) gst(tk.C + (size_t)gi * tk.ldc + gj, val);
+                    if (gi > gj) gst(tk.C + (size_t)gj * tk.ldc + gi, val);
                 } else {
-                    tk.C[(size_t)gi * tk.ldc + gj] = val;
+                    gst(tk.C + (size_t)gi * tk.ldc + gj, val);
                 }
             }
 }

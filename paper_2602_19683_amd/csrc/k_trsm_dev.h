@@ -38,7 +38,7 @@ __device__ inline void trsm_strip(const TrsmTask& tk, int s, int m, TrsmLds& sh,
         dbl4 acc;
 #pragma unroll
         for (int v = 0; v < 4; ++v)
-            acc[v] = B[(size_t)(16 * qi + drow(lk, v)) * ldb + c0 + 16 * qj + lr];
+            acc[v] = gld(B + (size_t)(16 * qi + drow(lk, v)) * ldb + c0 + 16 * qj + lr);
         // minus the finished blocks X[:, 0:c0] times rows c0.. of L_JJ (transposed)
         acc = accum32<true, TK>(B, ldb, tk.L + (size_t)c0 * ldl, ldl, c0, acc, -1.0, As, Bs, tid);
 #pragma unroll
@@ -47,12 +47,12 @@ __device__ inline void trsm_strip(const TrsmTask& tk, int s, int m, TrsmLds& sh,
         const double* dq = tk.Dinv + (size_t)(c0 + 16 * qj + lr) * ldd + c0 + lk;
         dbl4 o = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int k = 0; k < 32; k += 4) o = mfma16(Sacc[16 * qi + lr][k + lk], dq[k], o);
+        for (int k = 0; k < 32; k += 4) o = mfma16(Sacc[16 * qi + lr][k + lk], gld(dq + k), o);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int row = 16 * qi + drow(lk, v), col = c0 + 16 * qj + lr;
-            B[(size_t)row * ldb + col] = o[v];
-            if (B32) B32[(size_t)row * m + col] = (float)o[v];
+            gst(B + (size_t)row * ldb + col, o[v]);
+            if (B32) gst(B32 + (size_t)row * m + col, (float)o[v]);
         }
         __syncthreads();  // X_p stored (read by every wave next), Sacc free
     }

@@ -45,8 +45,8 @@ __device__ inline void update_block(const UpdateTask& tk, int bi, int bj, int m,
         for (int q = 0; q < NLD; ++q) {
             const int e = tid + NT * q;
             const int r = e / (KB / 2), kk = (e % (KB / 2)) * 2;
-            ra[q] = *reinterpret_cast<const double2*>(A + (size_t)r * lda + k0 + kk);
-            rb[q] = *reinterpret_cast<const double2*>(B + (size_t)r * ldb + k0 + kk);
+            ra[q] = gld2(A + (size_t)r * lda + k0 + kk);
+            rb[q] = gld2(B + (size_t)r * ldb + k0 + kk);
         }
     };
     auto swrite = [&](int buf) {
@@ -98,7 +98,8 @@ __device__ inline void update_block(const UpdateTask& tk, int bi, int bj, int m,
             for (int v = 0; v < 4; ++v) {
                 const int row = wr + 16 * i + drow(lk, v);
                 const int col = wc + 16 * j + lr;
-                C[(size_t)row * ldc + col] -= acc[i][j][v];
+                double* c = C + (size_t)row * ldc + col;
+                gst(c, gld(c) - acc[i][j][v]);
             }
 }
 

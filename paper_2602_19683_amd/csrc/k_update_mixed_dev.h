@@ -49,8 +49,8 @@ __device__ inline void update_block_f32(const UpdateTask& tk, int bi, int bj, in
         for (int q = 0; q < NLD; ++q) {
             const int e = tid + NT * q;
             const int r = e / (KB / 2), kk = (e % (KB / 2)) * 2;
-            ra[q] = *reinterpret_cast<const double2*>(A + (size_t)r * lda + k0 + kk);
-            rb[q] = *reinterpret_cast<const double2*>(B + (size_t)r * ldb + k0 + kk);
+            ra[q] = gld2(A + (size_t)r * lda + k0 + kk);
+            rb[q] = gld2(B + (size_t)r * ldb + k0 + kk);
         }
     };
     auto swrite = [&](int buf) {
@@ -101,7 +101,8 @@ __device__ inline void update_block_f32(const UpdateTask& tk, int bi, int bj, in
             for (int v = 0; v < 4; ++v) {
                 const int row = wr + 16 * i + frow(lk, v);
                 const int col = wc + 16 * j + lr;
-                C[(size_t)row * ldc + col] -= (double)acc[i][j][v];
+                double* c = C + (size_t)row * ldc + col;
+                gst(c, gld(c) - (double)acc[i][j][v]);
             }
 }
 
