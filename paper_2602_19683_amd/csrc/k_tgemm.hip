@@ -153,6 +153,36 @@ __global__ __launch_bounds__(WR * WC * 64, WR * WC / 2) void k_tgemm_f64(
         }
     }
 
+    // Epilogue: each input tile (Cin, then the partial tiles) is read for all
+    // of this lane's elements before anything is added or written (C may be
+    // Cin, so per-element load-add-store sequences would serialise); every
+    // element still sums acc + beta Cin + part 0 + part 1 + ... in that order.
+    double val[TR][TC][4];
+#pragma unroll
+    for (int i = 0; i < TR; ++i)
+#pragma unroll
+        for (int j = 0; j < TC; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) val[i][j][v] = acc[i][j][v];
+    auto addtile = [&](const double* T, int ld, double f) {
+        double t[TR][TC][4];
+#pragma unroll
+        for (int i = 0; i < TR; ++i)
+#pragma unroll
+            for (int j = 0; j < TC; ++j)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    t[i][j][v] = gld(T + (size_t)(i0 + wr + 16 * i + drow(lk, v)) * ld + j0 + wc +
+                                     16 * j + lr);
+#pragma unroll
+        for (int i = 0; i < TR; ++i)
+#pragma unroll
+            for (int j = 0; j < TC; ++j)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) val[i][j][v] += f * t[i][j][v];
+    };
+    if (tk.beta != 0.0) addtile(tk.Cin, tk.ldcin, tk.beta);
+    for (int p = 0; p < tk.npart; ++p) addtile(tk.part + (size_t)p * tk.part_stride, m, 1.0);
 #pragma unroll
     for (int i = 0; i < TR; ++i)
 #pragma unroll
@@ -161,17 +191,14 @@ __global__ __launch_bounds__(WR * WC * 64, WR * WC / 2) void k_tgemm_f64(
             for (int v = 0; v < 4; ++v) {
                 const int gi = i0 + wr + 16 * i + drow(lk, v);
                 const int gj = j0 + wc + 16 * j + lr;
-                double val = acc[i][j][v];
-                if (tk.beta != 0.0) val += tk.beta * gld(tk.Cin + (size_t)gi * tk.ldcin + gj);
-                for (int p = 0; p < tk.npart; ++p)
-                    val += gld(tk.part + (size_t)p * tk.part_stride + (size_t)gi * m + gj);
+                const double x = val[i][j][v];
                 if (tk.epi == TG_EPI_PHI) {
-                    gst(tk.C + (size_t)gi * tk.ldc + gj, gj > gi ? 0.0 : (gj == gi ? 0.5 * val : val));
+                    gst(tk.C + (size_t)gi * tk.ldc + gj, gj > gi ? 0.0 : (gj == gi ? 0.5 * x : x));
                 } else if (tk.epi == TG_EPI_SYM) {
-                    if (gi >= gj) gst(tk.C + (size_t)gi * tk.ldc + gj, val);
-                    if (gi > gj) gst(tk.C + (size_t)gj * tk.ldc + gi, val);
+                    if (gi >= gj) gst(tk.C + (size_t)gi * tk.ldc + gj, x);
+                    if (gi > gj) gst(tk.C + (size_t)gj * tk.ldc + gi, x);
                 } else {
-                    gst(tk.C + (size_t)gi * tk.ldc + gj, val);
+                    gst(tk.C + (size_t)gi * tk.ldc + gj, x);
                 }
             }
 }
