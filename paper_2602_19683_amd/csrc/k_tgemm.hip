@@ -205,9 +205,11 @@ __global__ __launch_bounds__(WR * WC * 64, WR * WC / 2) void k_tgemm_f64(
 
 int tgemm_block(int ntask, int m)
 {
-    // the largest block that still gives about two workgroups per CU
+    // the largest block that still gives a launch about two workgroups per
+    // CU (128-row blocks) or four (64-row blocks): measured best for 8 to 128
+    // tasks per launch of 256 and 512 tiles
     if (m % 128 == 0 && (long)ntask * (m / 128) * (m / 128) >= 512) return 128;
-    if (m % 64 == 0 && (long)ntask * (m / 64) * (m / 64) >= 256) return 64;
+    if (m % 64 == 0 && (long)ntask * (m / 64) * (m / 64) >= 1024) return 64;
     return 32;
 }
 
