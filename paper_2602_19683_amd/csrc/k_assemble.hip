@@ -27,6 +27,12 @@ __device__ inline void lower_tile_coords(int64_t t, int& I, int& J)
     J = (int)(t - (int64_t)i * (i + 1) / 2);
 }
 
+// DT > 0: the feature count D equals DT (loops unrolled, the column point's
+// features held in registers across the thread's four rows); DT = 0: any D.
+// Both accumulate d2 = fma(q_d, q_d, d2) in feature order, written out so
+// that the compiler cannot fuse a different product of an unrolled pair
+// (same bits for every D).
+template <int DT>
 __global__ __launch_bounds__(256) void k_assemble(TileMat T, int tile_rows, int64_t ntiles,
                                                   const double* __restrict__ A, int64_t na,
                                                   const double* __restrict__ B, int64_t nb, int D,
@@ -63,18 +69,31 @@ __global__ __launch_bounds__(256) void k_assemble(TileMat T, int tile_rows, int6
         __syncthreads();
         const int c = tid & 31;
         const int64_t j = j0 + c;
+        double bc[DT > 0 ? DT : 1];
+        if constexpr (DT > 0) {
+#pragma unroll
+            for (int d = 0; d < DT; ++d) bc[d] = Sb[d][c];
+        }
         for (int r = tid >> 5; r < SB; r += 8) {
             const int64_t i = i0 + r;
             double val;
             if (i < na && j < nb) {
                 double d2 = 0.0;
-                for (int d = 0; d < Dl; ++d) {
-                    const double q = Sa[r][d] - Sb[d][c];
-                    d2 += q * q;
-                }
-                for (int d = Dl; d < D; ++d) {  // dimensions beyond the LDS stage
-                    const double q = A[i * D + d] - B[j * D + d];
-                    d2 += q * q;
+                if constexpr (DT > 0) {
+#pragma unroll
+                    for (int d = 0; d < DT; ++d) {
+                        const double q = Sa[r][d] - bc[d];
+                        d2 = fma(q, q, d2);
+                    }
+                } else {
+                    for (int d = 0; d < Dl; ++d) {
+                        const double q = Sa[r][d] - Sb[d][c];
+                        d2 = fma(q, q, d2);
+                    }
+                    for (int d = Dl; d < D; ++d) {  // dimensions beyond the LDS stage
+                        const double q = A[i * D + d] - B[j * D + d];
+                        d2 = fma(q, q, d2);
+                    }
                 }
                 val = v * exp(-d2 * inv2l);
                 if (diag_noise && i == j) val += s2;
@@ -95,8 +114,22 @@ hipError_t launch_assemble(const TileMat& T, int tile_rows, const double* A, int
     if (ntiles <= 0) return hipSuccess;
     const int64_t subs = ntiles * (T.m / SB) * (T.m / SB);
     const int64_t grid = subs < 65536 ? subs : 65536;
-    hipLaunchKernelGGL(k_assemble, dim3((unsigned)grid), dim3(256), 0, s, T, tile_rows, ntiles,
-                       A, na, B, nb, D, l, v, s2, diag_noise ? 1 : 0, identity_pad ? 1 : 0);
+    const int dn = diag_noise ? 1 : 0, ip = identity_pad ? 1 : 0;
+#define GPR_ASM(DT)                                                                              \
+    hipLaunchKernelGGL(k_assemble<DT>, dim3((unsigned)grid), dim3(256), 0, s, T, tile_rows,     \
+                       ntiles, A, na, B, nb, D, l, v, s2, dn, ip)
+    switch (D) {
+    case 1: GPR_ASM(1); break;
+    case 2: GPR_ASM(2); break;
+    case 3: GPR_ASM(3); break;
+    case 4: GPR_ASM(4); break;
+    case 5: GPR_ASM(5); break;
+    case 6: GPR_ASM(6); break;
+    case 7: GPR_ASM(7); break;
+    case 8: GPR_ASM(8); break;
+    default: GPR_ASM(0); break;
+    }
+#undef GPR_ASM
     return hipGetLastError();
 }
 
