@@ -105,6 +105,60 @@ __global__ __launch_bounds__(256) void k_assemble(TileMat T, int tile_rows, int6
     }
 }
 
+// Assembly without LDS or barriers, for m a multiple of 64 and D = DT known:
+// a workgroup fills a 64 x 64 block, wave w rows 16 w .. 16 w + 15 and lane l
+// column l. The lane's column point stays in registers; a row point is the
+// same for the whole wave, so its features come through scalar loads; every
+// row is stored as 512 contiguous bytes. Same arithmetic as k_assemble.
+template <int DT>
+__global__ __launch_bounds__(256) void k_assemble_w(TileMat T, int64_t ntiles,
+                                                    const double* __restrict__ A, int64_t na,
+                                                    const double* __restrict__ B, int64_t nb,
+                                                    double l, double v, double s2, int diag_noise,
+                                                    int identity_pad)
+{
+    const int m = T.m;
+    const int bt = m / 64;                     // 64 x 64 blocks per tile side
+    const int64_t per_tile = (int64_t)bt * bt;
+    const int64_t total = ntiles * per_tile;
+    const double inv2l = 1.0 / (2.0 * l);
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
+        const int64_t t = w / per_tile;
+        const int sub = (int)(w - t * per_tile);
+        int I, J;
+        if (T.layout == 0) lower_tile_coords(t, I, J);
+        else { I = (int)(t / T.ncolt); J = (int)(t - (int64_t)I * T.ncolt); }
+        const int si = sub / bt, sj = sub - si * bt;
+        const int r0 = si * 64 + wave * 16;    // first row of this wave, within the tile
+        const int64_t j = (int64_t)J * m + sj * 64 + lane;
+        double* out = tile_ptr(T, I, J) + (size_t)r0 * m + sj * 64 + lane;
+        const bool jin = j < nb;
+        double bc[DT];
+#pragma unroll
+        for (int d = 0; d < DT; ++d) bc[d] = jin ? B[j * DT + d] : 0.0;
+        for (int r = 0; r < 16; ++r) {
+            const int64_t i = (int64_t)I * m + r0 + r;   // uniform across the wave
+            double val;
+            if (i < na && jin) {
+                const double* ar = A + i * DT;
+                double d2 = 0.0;
+#pragma unroll
+                for (int d = 0; d < DT; ++d) {
+                    const double q = ar[d] - bc[d];
+                    d2 = fma(q, q, d2);
+                }
+                val = v * exp(-d2 * inv2l);
+                if (diag_noise && i == j) val += s2;
+            } else {
+                val = (identity_pad && i == j) ? 1.0 : 0.0;
+            }
+            out[(size_t)r * m] = val;
+        }
+    }
+}
+
 hipError_t launch_assemble(const TileMat& T, int tile_rows, const double* A, int64_t na,
                            const double* B, int64_t nb, int D, double l, double v, double s2,
                            bool diag_noise, bool identity_pad, hipStream_t s)
@@ -115,6 +169,25 @@ hipError_t launch_assemble(const TileMat& T, int tile_rows, const double* A, int
     const int64_t subs = ntiles * (T.m / SB) * (T.m / SB);
     const int64_t grid = subs < 65536 ? subs : 65536;
     const int dn = diag_noise ? 1 : 0, ip = identity_pad ? 1 : 0;
+    if (T.m % 64 == 0 && D >= 1 && D <= 8) {
+        const int64_t items = ntiles * (T.m / 64) * (T.m / 64);
+        const int64_t g = items < 65536 ? items : 65536;
+#define GPR_ASMW(DT)                                                                             \
+    hipLaunchKernelGGL(k_assemble_w<DT>, dim3((unsigned)g), dim3(256), 0, s, T, ntiles, A, na, B, \
+                       nb, l, v, s2, dn, ip)
+        switch (D) {
+        case 1: GPR_ASMW(1); break;
+        case 2: GPR_ASMW(2); break;
+        case 3: GPR_ASMW(3); break;
+        case 4: GPR_ASMW(4); break;
+        case 5: GPR_ASMW(5); break;
+        case 6: GPR_ASMW(6); break;
+        case 7: GPR_ASMW(7); break;
+        default: GPR_ASMW(8); break;
+        }
+#undef GPR_ASMW
+        return hipGetLastError();
+    }
 #define GPR_ASM(DT)                                                                              \
     hipLaunchKernelGGL(k_assemble<DT>, dim3((unsigned)grid), dim3(256), 0, s, T, tile_rows,     \
                        ntiles, A, na, B, nb, D, l, v, s2, dn, ip)
