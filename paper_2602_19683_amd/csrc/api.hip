@@ -378,6 +378,9 @@ int run_sweep(gpr_ctx* ctx, const SweepMats& X, const SweepPlan& P, const DescBu
         HIP_TRY(hipStreamWaitEvent(phys[q], ctx->ev_fork, 0));
     }
     const int m = X.m;
+    // after a failed pivot the rest of a factorising sweep is skipped (the
+    // record was reset before this sweep; a sweep with a given factor has none)
+    const int* abort_info = sweep_factors(P.mode) ? ctx->d_info : nullptr;
     for (size_t li = 0; li < Ls.size(); ++li) {
         const SchedLaunch& L = Ls[li];
         hipStream_t st = phys[L.stream];
@@ -394,17 +397,18 @@ int run_sweep(gpr_ctx* ctx, const SweepMats& X, const SweepPlan& P, const DescBu
                                      ++ctx->epoch, ctx->d_info + 2, st));
         } else if (L.kind == LK_TRSM) {
             ProfScope ps(ctx, st, PK_TRSM, L.count * m3, 0.0);
-            HIP_TRY(launch_trsm_f64(db.dev<TrsmTask>(ctx, P.off[li]), L.count, m, st));
+            HIP_TRY(launch_trsm_f64(db.dev<TrsmTask>(ctx, P.off[li]), L.count, m, abort_info, st));
         } else {
             double f = 0.0;
             for (int t = L.first; t < L.first + L.count; ++t)
                 f += P.sched.tasks[t].kind == K_SYRK ? m3 : 2.0 * m3;
             ProfScope ps(ctx, st, PK_UPDATE, f, 0.0);
             if (X.prec == GPR_FP64)
-                HIP_TRY(launch_update_f64(db.dev<UpdateTask>(ctx, P.off[li]), L.count, m, st));
+                HIP_TRY(launch_update_f64(db.dev<UpdateTask>(ctx, P.off[li]), L.count, m,
+                                          abort_info, st));
             else
                 HIP_TRY(launch_update_mixed(db.dev<UpdateTask>(ctx, P.off[li]), L.count, m,
-                                            X.prec, st));
+                                            X.prec, abort_info, st));
         }
         if (waited[li]) HIP_TRY(hipEventRecord(ctx->evpool[li], st));
     }

@@ -112,8 +112,14 @@ hipError_t launch_dense_to_tiled(const double* A, int64_t n, int64_t lda, const 
 hipError_t launch_tiled_to_dense(const TileMat& T, int64_t n, double* out, int64_t ldo,
                                  bool mirror, hipStream_t s);
 
-hipError_t launch_update_f64(const UpdateTask* d_tasks, int ntask, int m, hipStream_t s);
-hipError_t launch_trsm_f64(const TrsmTask* d_tasks, int ntask, int m, hipStream_t s);
+// Tile updates and TRSM strips of a sweep. abort_info (nullable, device):
+// the factorisation's failed-pivot record; when it is > 0 at a launch's start
+// the launch returns at once (nothing of a failed factorisation is used).
+// Pass it only for sweeps that factorise, where it was reset beforehand.
+hipError_t launch_update_f64(const UpdateTask* d_tasks, int ntask, int m, const int* abort_info,
+                             hipStream_t s);
+hipError_t launch_trsm_f64(const TrsmTask* d_tasks, int ntask, int m, const int* abort_info,
+                           hipStream_t s);
 // POTRF of one diagonal tile, m / 32 cooperating workgroups ordered by
 // flags[0 .. 2 m/32) (set to `epoch` as parts of a row panel are done; epoch
 // must differ from every value the flags hold). *err is set if a wait hits
@@ -142,7 +148,7 @@ hipError_t launch_kernel_matvec(const double* A, int64_t na, const double* B, in
 
 // Mixed-precision tile updates (prec GPR_MIXED_FP32 or GPR_MIXED_BF16); m % 64 == 0.
 hipError_t launch_update_mixed(const UpdateTask* d_tasks, int ntask, int m, int prec,
-                               hipStream_t s);
+                               const int* abort_info, hipStream_t s);
 
 // out[0] = sum x_i^2 (deterministic).
 hipError_t launch_sumsq(const double* x, int64_t n, double* out, hipStream_t s);

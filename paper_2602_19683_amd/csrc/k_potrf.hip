@@ -37,6 +37,13 @@ __global__ __launch_bounds__(256) void k_potrf_f64(double* __restrict__ A, int l
                                                    unsigned* __restrict__ flags, unsigned epoch,
                                                    int* __restrict__ err)
 {
+    // a pivot already failed in an earlier tile: nothing of this factorisation
+    // is used any more. Failures of this launch are recorded as columns
+    // > col_base, so every workgroup of the launch takes the same branch.
+    if (info != nullptr) {
+        const int f = *info;
+        if (f > 0 && f <= col_base) return;
+    }
     __shared__ PotrfLds sh;
     potrf_panel(A, lda, m, Tinv, ldt, info, col_base, flags, epoch, err, blockIdx.x, sh,
                 threadIdx.x);

@@ -20,8 +20,10 @@
 
 namespace gpr {
 
-__global__ __launch_bounds__(256) void k_trsm_f64(const TrsmTask* __restrict__ tasks, int m)
+__global__ __launch_bounds__(256) void k_trsm_f64(const TrsmTask* __restrict__ tasks, int m,
+                                                  const int* __restrict__ abort_info)
 {
+    if (abort_info != nullptr && *abort_info > 0) return;  // the factorisation failed
     __shared__ TrsmLds sh;
     const int strips = m / 32;
     const int lid = xcd_remap(blockIdx.x, gridDim.x);
@@ -29,10 +31,12 @@ __global__ __launch_bounds__(256) void k_trsm_f64(const TrsmTask* __restrict__ t
     trsm_strip(tasks[t], s, m, sh, threadIdx.x);
 }
 
-hipError_t launch_trsm_f64(const TrsmTask* d_tasks, int ntask, int m, hipStream_t s)
+hipError_t launch_trsm_f64(const TrsmTask* d_tasks, int ntask, int m, const int* abort_info,
+                           hipStream_t s)
 {
     if (ntask <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_trsm_f64, dim3(ntask * (m / 32)), dim3(256), 0, s, d_tasks, m);
+    hipLaunchKernelGGL(k_trsm_f64, dim3(ntask * (m / 32)), dim3(256), 0, s, d_tasks, m,
+                       abort_info);
     return hipGetLastError();
 }
 

@@ -23,8 +23,9 @@ namespace gpr {
 
 template <int BM, int WR, int WC>
 __global__ __launch_bounds__(WR * WC * 64, WR * WC / 2) void k_update_f64(
-    const UpdateTask* __restrict__ tasks, int m)
+    const UpdateTask* __restrict__ tasks, int m, const int* __restrict__ abort_info)
 {
+    if (abort_info != nullptr && *abort_info > 0) return;  // the factorisation failed
     __shared__ UpdLds<BM> sh;
     const int nb = m / BM;
     const int lid = xcd_remap(blockIdx.x, gridDim.x);
@@ -50,19 +51,20 @@ int update_block_f64(int ntask, int m)
     return 32;
 }
 
-hipError_t launch_update_f64(const UpdateTask* d_tasks, int ntask, int m, hipStream_t s)
+hipError_t launch_update_f64(const UpdateTask* d_tasks, int ntask, int m, const int* abort_info,
+                             hipStream_t s)
 {
     if (ntask <= 0) return hipSuccess;
     const int bm = update_block_f64(ntask, m);
     if (bm == 128) {
         const int nb = m / 128;
-        hipLaunchKernelGGL((k_update_f64<128, 4, 4>), dim3(ntask * nb * nb), dim3(1024), 0, s, d_tasks, m);
+        hipLaunchKernelGGL((k_update_f64<128, 4, 4>), dim3(ntask * nb * nb), dim3(1024), 0, s, d_tasks, m, abort_info);
     } else if (bm == 64) {
         const int nb = m / 64;
-        hipLaunchKernelGGL((k_update_f64<64, 2, 2>), dim3(ntask * nb * nb), dim3(256), 0, s, d_tasks, m);
+        hipLaunchKernelGGL((k_update_f64<64, 2, 2>), dim3(ntask * nb * nb), dim3(256), 0, s, d_tasks, m, abort_info);
     } else {
         const int nb = m / 32;
-        hipLaunchKernelGGL((k_update_f64<32, 2, 2>), dim3(ntask * nb * nb), dim3(256), 0, s, d_tasks, m);
+        hipLaunchKernelGGL((k_update_f64<32, 2, 2>), dim3(ntask * nb * nb), dim3(256), 0, s, d_tasks, m, abort_info);
     }
     return hipGetLastError();
 }

@@ -23,8 +23,9 @@ typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 
 template <int BM, int WR, int WC>
 __global__ __launch_bounds__(WR * WC * 64, WR * WC / 2) void k_update_f32(
-    const UpdateTask* __restrict__ tasks, int m)
+    const UpdateTask* __restrict__ tasks, int m, const int* __restrict__ abort_info)
 {
+    if (abort_info != nullptr && *abort_info > 0) return;  // the factorisation failed
     __shared__ UpdLdsF32<BM> sh;
     const int nb = m / BM;
     const int lid = xcd_remap(blockIdx.x, gridDim.x);
@@ -38,8 +39,9 @@ __global__ __launch_bounds__(WR * WC * 64, WR * WC / 2) void k_update_f32(
 
 template <int BM, int WR, int WC>
 __global__ __launch_bounds__(WR * WC * 64, WR * WC / 2) void k_update_bf16(
-    const UpdateTask* __restrict__ tasks, int m)
+    const UpdateTask* __restrict__ tasks, int m, const int* __restrict__ abort_info)
 {
+    if (abort_info != nullptr && *abort_info > 0) return;  // the factorisation failed
     constexpr int NT = WR * WC * 64;
     constexpr int KB = 32;
     constexpr int TR = BM / WR / 16, TC = BM / WC / 16;
@@ -129,7 +131,7 @@ __global__ __launch_bounds__(WR * WC * 64, WR * WC / 2) void k_update_bf16(
 }
 
 hipError_t launch_update_mixed(const UpdateTask* d_tasks, int ntask, int m, int prec,
-                               hipStream_t s)
+                               const int* abort_info, hipStream_t s)
 {
     if (ntask <= 0) return hipSuccess;
     const bool big = m % 128 == 0;
@@ -137,11 +139,11 @@ hipError_t launch_update_mixed(const UpdateTask* d_tasks, int ntask, int m, int 
     const int nb = m / BM;
     const dim3 grid(ntask * nb * nb);
     if (prec == GPR_MIXED_FP32) {
-        if (big) hipLaunchKernelGGL((k_update_f32<128, 4, 4>), grid, dim3(1024), 0, s, d_tasks, m);
-        else hipLaunchKernelGGL((k_update_f32<64, 2, 2>), grid, dim3(256), 0, s, d_tasks, m);
+        if (big) hipLaunchKernelGGL((k_update_f32<128, 4, 4>), grid, dim3(1024), 0, s, d_tasks, m, abort_info);
+        else hipLaunchKernelGGL((k_update_f32<64, 2, 2>), grid, dim3(256), 0, s, d_tasks, m, abort_info);
     } else {
-        if (big) hipLaunchKernelGGL((k_update_bf16<128, 4, 4>), grid, dim3(1024), 0, s, d_tasks, m);
-        else hipLaunchKernelGGL((k_update_bf16<64, 2, 2>), grid, dim3(256), 0, s, d_tasks, m);
+        if (big) hipLaunchKernelGGL((k_update_bf16<128, 4, 4>), grid, dim3(1024), 0, s, d_tasks, m, abort_info);
+        else hipLaunchKernelGGL((k_update_bf16<64, 2, 2>), grid, dim3(256), 0, s, d_tasks, m, abort_info);
     }
     return hipGetLastError();
 }

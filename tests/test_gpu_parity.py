@@ -122,6 +122,36 @@ def test_cholesky_reports_failed_pivot(ctx):
     K.free()
 
 
+def test_failed_factorisation_does_not_affect_later_calls(ctx):
+    """A factorising sweep skips its remaining launches once a pivot has
+    failed; the failure record it reads is reset before every factorising
+    sweep and not consulted by a sweep with a given factor. So after a
+    failed factorisation (early column), a prediction with a good factor
+    and a new factorisation on the same context are both exact."""
+    n, ns, tile = 512, 256, 64
+    say(f"failed factorisation, then predict / fit_predict n={n} n_test={ns} tile={tile}")
+    X, y, Xs = nfir_train_test(n, ns)
+    Xd, yd, Xsd = dev(X), dev(y), dev(Xs)
+    ref = oracle.predict(X, y, Xs, DEFAULT_HYPER)
+    good = ctx.assemble(Xd, DEFAULT_HYPER, tile)
+    ctx.cholesky(good)
+    assert ctx.sync()[0] == 0
+    bad = ctx.assemble(Xd, (1.0, 1.0, -2.0), tile)     # first pivot fails
+    ctx.cholesky(bad)
+    st, col = ctx.sync(raise_on_error=False)
+    assert st == 1 and col == 1
+    mean, cov = ctx.predict(good, Xd, yd, Xsd, DEFAULT_HYPER)
+    em, ec = oracle.rel_err(host(mean), ref["mean"]), oracle.rel_err(host(cov), ref["cov"])
+    say(f"  given factor after the failure: rel(mean) {em:.2e} rel(cov) {ec:.2e}")
+    assert em <= TOL and ec <= TOL
+    m2, c2, K2 = ctx.fit_predict(Xd, yd, Xsd, DEFAULT_HYPER, tile)
+    assert ctx.sync()[0] == 0
+    np.testing.assert_array_equal(host(m2), host(mean))
+    np.testing.assert_array_equal(host(c2), host(cov))
+    for k in (good, bad, K2):
+        k.free()
+
+
 # --------------------------------------------------------------------------
 # solves and prediction (eqs. (2), (3))
 # --------------------------------------------------------------------------
