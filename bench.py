@@ -282,6 +282,14 @@ def nlml_run(ctx, args, log):
             out["grad"] = [float(v) for v in g.cpu()]
         else:
             out["ms_nlml_only"] = round(ms, 4)
+    # the hyperparameter fit (gpr_fit_hyper): Adam steps, each one NLML and
+    # gradient evaluation plus the host-side step and one synchronisation
+    import time
+    ctx.fit_hyper(Xd, yd, h, tile, max_steps=1)
+    t0 = time.perf_counter()
+    th, tr, k = ctx.fit_hyper(Xd, yd, h, tile, max_steps=args.steps)
+    out["ms_per_adam_step"] = round((time.perf_counter() - t0) * 1e3 / k, 4)
+    out["adam_nlml_first_last"] = [float(tr[0]), float(tr[-1])]
     out["config"] = f"n={n}, D=8, tile {tile}, (l, v, sigma^2) = {h}, fp64"
     log(f"nlml: {out}")
     return out

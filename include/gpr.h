@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define GPR_ABI_VERSION 4
+#define GPR_ABI_VERSION 5
 
 /* Status codes. */
 enum {
@@ -243,6 +243,25 @@ int gpr_solve(gpr_ctx* ctx, gpr_tiled* L, const double* b, double* x, void* stre
 int gpr_nlml_grad(gpr_ctx* ctx, const double* X, const double* y, int64_t n,
                   int32_t D, gpr_hyper h, int32_t tile, gpr_precision prec,
                   double* out_nlml, double* out_grad3, double* out_Kbar,
+                  void* stream);
+
+/* Hyperparameter fit: Adam on z = log theta (theta = (lengthscale, vertical
+ * variance, noise variance); the log keeps theta > 0) minimising the NLML of
+ * gpr_nlml_grad, from theta0. Each step evaluates the NLML and its gradient
+ * at theta = exp(z) on the GPU (FP64), then takes the bias-corrected Adam
+ * step with (lr, beta1, beta2, eps). The paper fixes the hyperparameters
+ * (Sec. 3); this is the usual maximum-likelihood fit of the same model.
+ * Stops after max_steps, or once the NLML changed by at most tol relative to
+ * the previous evaluation (tol = 0: never). theta0, theta_out (3 doubles),
+ * nlml_trace (max_steps doubles, the NLML before each step; may be NULL) and
+ * steps_done (may be NULL) are HOST pointers; X and y are device arrays as in
+ * gpr_nlml_grad. Synchronises the stream once per step. Errors as in
+ * gpr_nlml_grad; GPR_ENOTPD if K(theta) stopped being positive definite
+ * along the way (theta_out is then not written). */
+int gpr_fit_hyper(gpr_ctx* ctx, const double* X, const double* y, int64_t n,
+                  int32_t D, int32_t tile, const double* theta0, int32_t max_steps,
+                  double lr, double beta1, double beta2, double eps, double tol,
+                  double* theta_out, double* nlml_trace, int32_t* steps_done,
                   void* stream);
 
 /* ---- handles and utilities ----------------------------------------------- */

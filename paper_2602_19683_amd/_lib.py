@@ -54,6 +54,11 @@ SIGNATURES = {
     "gpr_solve": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "gpr_nlml_grad": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, Hyper, _i32, ctypes.c_int, _vp,
                                      _vp, _vp, _vp]),
+    "gpr_fit_hyper": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, _i32,
+                                     ctypes.POINTER(ctypes.c_double), _i32, ctypes.c_double,
+                                     ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                     ctypes.c_double, ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_double), _i32p, _vp]),
     "gpr_profile_enable": (ctypes.c_int, [_vp, ctypes.c_int]),
     "gpr_profile_read": (ctypes.c_int, [_vp, ctypes.c_int, _i64p, ctypes.POINTER(ctypes.c_double),
                                         ctypes.POINTER(ctypes.c_double),

@@ -44,6 +44,7 @@ struct gpr_ctx {
     size_t ws_cap = 0;
     gpr_tiled* scratch = nullptr; // for gpr_cholesky_dense
     gpr_tiled* nlml_K = nullptr;  // factor kept by gpr_nlml_grad
+    double* d_fit = nullptr;      // NLML and gradient of gpr_fit_hyper's current step
     char* d_adj = nullptr;        // adjoint workspace (Lbar, Abar, partial tiles)
     size_t adj_cap = 0;
     // persistent executor: ticket order of the last sweep shape (device copy)
@@ -669,6 +670,7 @@ int gpr_ctx_destroy(gpr_ctx* c)
     (void)hipDeviceSynchronize();
     if (c->scratch) gpr_tiled_free(c->scratch);
     if (c->nlml_K) gpr_tiled_free(c->nlml_K);
+    if (c->d_fit) (void)hipFree(c->d_fit);
     if (c->d_adj) (void)hipFree(c->d_adj);
     for (auto e : c->evpool) (void)hipEventDestroy(e);
     for (auto e : c->tpool) (void)hipEventDestroy(e);
@@ -1266,6 +1268,64 @@ int gpr_tiled_free(gpr_tiled* T)
     if (T->tinv) (void)hipFree(T->tinv);
     if (T->kcopy) (void)hipFree(T->kcopy);
     delete T;
+    return GPR_OK;
+}
+
+int gpr_fit_hyper(gpr_ctx* ctx, const double* X, const double* y, int64_t n, int32_t D,
+                  int32_t tile, const double* theta0, int32_t max_steps, double lr, double beta1,
+                  double beta2, double eps, double tol, double* theta_out, double* nlml_trace,
+                  int32_t* steps_done, void* stream)
+{
+    if (!ctx || !X || !y || !theta0 || !theta_out || max_steps < 1 || !(lr > 0) ||
+        !(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) || !(eps >= 0) || !(tol >= 0))
+        return GPR_EINVAL;
+    for (int k = 0; k < 3; ++k)
+        if (!(theta0[k] > 0) || !std::isfinite(theta0[k])) return GPR_EINVAL;
+    if (steps_done) *steps_done = 0;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int rc = check_device(ctx->device);
+    if (rc) return rc;
+    if (!ctx->d_fit) {
+        if (hipMalloc(reinterpret_cast<void**>(&ctx->d_fit), 8 * sizeof(double)) != hipSuccess) {
+            (void)hipGetLastError();
+            return GPR_ENOMEM;
+        }
+    }
+    // Adam on z = log theta: the NLML and its gradient come from the GPU
+    // (gpr_nlml_grad); the moments and the step are three scalars each, kept
+    // here between evaluations, since the next evaluation takes theta by value
+    double z[3], mom[3] = {0.0, 0.0, 0.0}, sec[3] = {0.0, 0.0, 0.0};
+    for (int k = 0; k < 3; ++k) z[k] = std::log(theta0[k]);
+    double prev = 0.0, b1t = 1.0, b2t = 1.0;
+    int t = 0;
+    while (t < max_steps) {
+        const double th[3] = {std::exp(z[0]), std::exp(z[1]), std::exp(z[2])};
+        const gpr_hyper h{th[0], th[1], th[2]};
+        rc = gpr_nlml_grad(ctx, X, y, n, D, h, tile, GPR_FP64, ctx->d_fit, ctx->d_fit + 1,
+                           nullptr, stream);
+        if (rc) return rc;
+        double out[4];
+        HIP_TRY(hipMemcpyAsync(out, ctx->d_fit, sizeof(out), hipMemcpyDeviceToHost, s));
+        rc = gpr_sync(ctx, stream, nullptr);
+        if (rc) return rc;   // GPR_ENOTPD: K(theta) lost positive definiteness
+        const double f = out[0];
+        if (!std::isfinite(f)) return GPR_ENOTPD;
+        if (nlml_trace) nlml_trace[t] = f;
+        ++t;
+        b1t *= beta1;
+        b2t *= beta2;
+        for (int k = 0; k < 3; ++k) {
+            const double gz = out[1 + k] * th[k];   // d/dlog(theta) = theta d/dtheta
+            mom[k] = beta1 * mom[k] + (1.0 - beta1) * gz;
+            sec[k] = beta2 * sec[k] + (1.0 - beta2) * gz * gz;
+            const double mh = mom[k] / (1.0 - b1t), sh = sec[k] / (1.0 - b2t);
+            z[k] -= lr * mh / (std::sqrt(sh) + eps);
+        }
+        if (t > 1 && tol > 0 && std::fabs(f - prev) <= tol * std::fabs(prev)) break;
+        prev = f;
+    }
+    for (int k = 0; k < 3; ++k) theta_out[k] = std::exp(z[k]);
+    if (steps_done) *steps_done = t;
     return GPR_OK;
 }
 

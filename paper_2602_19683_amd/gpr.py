@@ -290,6 +290,34 @@ class Context:
                "gpr_nlml_grad")
         return out_nlml, (out_grad if grad else None), (out_kbar if kbar else None)
 
+    def fit_hyper(self, X, y, theta0, tile, max_steps=20, lr=0.05, betas=(0.9, 0.999),
+                  eps=1e-8, tol=0.0, stream=None):
+        """Adam on log theta from theta0 = (l, v, sigma^2), each step one GPU
+        NLML-and-gradient evaluation (gpr_fit_hyper). Returns (theta (numpy, 3),
+        NLML before each step (numpy), steps taken)."""
+        n, D = X.shape
+        th0 = (ctypes.c_double * 3)(*[float(v) for v in theta0])
+        out = (ctypes.c_double * 3)()
+        trace = (ctypes.c_double * int(max_steps))()
+        done = ctypes.c_int32(0)
+        _check(self._lib.gpr_fit_hyper(self._h, _dev_ptr(X, "X"), _dev_ptr(y, "y", n), n, D,
+                                       int(tile), th0, int(max_steps), float(lr),
+                                       float(betas[0]), float(betas[1]), float(eps), float(tol),
+                                       out, trace, ctypes.byref(done), _stream(stream)),
+               "gpr_fit_hyper")
+        k = done.value
+        return np.array(out[:]), np.array(trace[:k]), k
+
+    def fit_hyper_restarts(self, X, y, starts, tile, **kw):
+        """fit_hyper from each theta0 in starts; returns the fit (theta, trace,
+        steps) whose last NLML is lowest, and the index of its start."""
+        best, best_i = None, -1
+        for i, th0 in enumerate(starts):
+            r = self.fit_hyper(X, y, th0, tile, **kw)
+            if best is None or r[1][-1] < best[1][-1]:
+                best, best_i = r, i
+        return best, best_i
+
     # ---- instrumentation --------------------------------------------------
     PROFILE_KINDS = ("potrf", "trtri", "trsm", "update", "assemble", "trsv", "matvec", "export",
                      "adjoint", "reduce", "persist")

@@ -29,7 +29,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_abi_version_and_strerror():
     lib = _lib.load()
-    assert lib.gpr_abi_version() == 4
+    assert lib.gpr_abi_version() == 5
     for code in [0, 1, -1, -2, -3, -4, -5]:
         assert lib.gpr_strerror(code)
     assert b"unknown" in lib.gpr_strerror(12345)
@@ -106,3 +106,14 @@ def test_adjoint_describe_argument_errors():
     assert lib.gpr_adjoint_describe(1, 2, None, 0, ctypes.byref(nt), None, 0, ctypes.byref(nr),
                                     None, 0, ctypes.byref(nl)) == _lib.GPR_EINVAL
     assert (nt.value, nr.value, nl.value) == (3, 3, 3)  # M = 1: the three POTRF-adjoint products
+
+
+def test_fit_hyper_rejects_bad_arguments():
+    import ctypes
+    from paper_2602_19683_amd import _lib
+    lib = _lib.load()
+    th = (ctypes.c_double * 3)(0.3, 2.0, 0.5)
+    out = (ctypes.c_double * 3)()
+    # no context
+    assert lib.gpr_fit_hyper(None, None, None, 8, 1, 32, th, 5, 0.05, 0.9, 0.999, 1e-8, 0.0,
+                             out, None, None, None) == -1

@@ -181,3 +181,48 @@ def test_adam_fit_through_autograd_matches_oracle(ctx):
     assert worst <= 1e-8
     assert gpu_trace[-1][1] < gpu_trace[0][1]
     np.testing.assert_allclose(torch.exp(z).detach().numpy(), ref_final, rtol=1e-8)
+
+
+def test_fit_hyper_matches_oracle_adam(ctx):
+    """gpr_fit_hyper: 20 Adam steps on log theta from (0.3, 2.0, 0.5), each a
+    GPU NLML-and-gradient evaluation, against the oracle's replay of the same
+    optimiser (NLML before each step to 1e-8, final theta to 1e-8)."""
+    n, tile = 1024, 256
+    X, y = nfir(n)
+    Xd, yd = dev(X), dev(y)
+    theta, trace, steps = ctx.fit_hyper(Xd, yd, C4_HYPER, tile, max_steps=20)
+    ref_trace, ref_final = oracle.adam_fit(X, y, C4_HYPER, steps=20)
+    assert steps == 20 and len(trace) == 20
+    worst = max(abs(f - fr) / abs(fr) for f, (_, fr) in zip(trace, ref_trace))
+    say(f"fit_hyper: NLML {trace[0]:.6f} -> {trace[-1]:.6f}, worst step rel {worst:.2e}, "
+        f"theta {theta}")
+    assert worst <= 1e-8
+    np.testing.assert_allclose(theta, ref_final, rtol=1e-8)
+    assert trace[-1] < trace[0]
+
+
+def test_fit_hyper_tolerance_and_restarts(ctx):
+    """Stopping on the relative NLML change, and the best of several starts.
+    The trajectory does not depend on the stopping rule, so the first 20
+    NLMLs equal those of a 20-step run bit for bit."""
+    n, tile = 1024, 256
+    X, y = nfir(n)
+    Xd, yd = dev(X), dev(y)
+    _, tr20, _ = ctx.fit_hyper(Xd, yd, C4_HYPER, tile, max_steps=20)
+    tol, cap = 1e-4, 200
+    theta, trace, steps = ctx.fit_hyper(Xd, yd, C4_HYPER, tile, max_steps=cap, tol=tol)
+    say(f"fit_hyper tol {tol}: {steps} steps, NLML {trace[0]:.6f} -> {trace[-1]:.6f}, "
+        f"theta {theta}")
+    k0 = min(steps, 20)
+    np.testing.assert_array_equal(trace[:k0], tr20[:k0])
+    assert 1 <= steps <= cap and len(trace) == steps
+    # the rule: no earlier step met the tolerance; a stop before the cap met it
+    assert all(abs(trace[k] - trace[k - 1]) > tol * abs(trace[k - 1]) for k in range(1, steps - 1))
+    if steps < cap:
+        assert abs(trace[-1] - trace[-2]) <= tol * abs(trace[-2])
+    assert trace[-1] < trace[0]
+    starts = [C4_HYPER, (1.0, 1.0, 0.1), (3.0, 0.5, 1.0)]
+    (tb, trb, kb), ib = ctx.fit_hyper_restarts(Xd, yd, starts, tile, max_steps=30)
+    finals = [ctx.fit_hyper(Xd, yd, s, tile, max_steps=30)[1][-1] for s in starts]
+    say(f"restarts: final NLMLs {finals}, best start {ib}")
+    assert ib == int(np.argmin(finals)) and trb[-1] == min(finals)
