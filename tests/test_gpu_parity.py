@@ -61,6 +61,32 @@ def test_assemble_matches_oracle(ctx, n, tile, h):
     K.free()
 
 
+@pytest.mark.parametrize("D", [1, 3, 5, 8, 9, 12])
+@pytest.mark.parametrize("n,ns,tile", [(200, 70, 64), (150, 40, 32), (300, 130, 128)])
+def test_assemble_feature_counts(ctx, D, n, ns, tile):
+    """Assembly for every compiled form: feature counts 1..8 (unrolled; the
+    form without LDS when the tile is a multiple of 64, the LDS form
+    otherwise) and the generic form (D > 8); K with noise, the cross
+    covariance and the test block through a variance-only prediction."""
+    rng = np.random.default_rng(100 + D)
+    X = rng.uniform(-1.0, 1.0, size=(n, D))
+    Xs = rng.uniform(-1.0, 1.0, size=(ns, D))
+    y = rng.standard_normal(n)
+    h = (0.7 * D / 8 + 0.2, 1.3, 0.05)
+    K = ctx.assemble(dev(X), h, tile)
+    got = host(ctx.to_dense(K))
+    ref = oracle.assemble_K(X, h)
+    say(f"assemble D={D} n={n} tile={tile}: max rel {oracle.max_rel(got, ref):.2e}")
+    assert oracle.max_rel(got, ref) <= 1e-14
+    np.testing.assert_array_equal(np.diag(got), np.diag(ref))
+    K.free()
+    mean, var, _, K2 = ctx.fit_predict_var(dev(X), dev(y), dev(Xs), h, tile)
+    r = oracle.predict(X, y, Xs, h)
+    assert oracle.rel_err(host(mean), r["mean"]) <= TOL
+    assert oracle.rel_err(host(var), np.diag(r["cov"])) <= TOL
+    K2.free()
+
+
 # --------------------------------------------------------------------------
 # Cholesky (Fig. 1): single tile = POTRF + inverse; 2 tiles add TRSM and
 # SYRK; 3+ tiles add GEMM; ragged n exercises the identity padding
