@@ -78,6 +78,9 @@ struct gpr_tiled {
     double* data = nullptr;
     double* tinv = nullptr;
     double* kcopy = nullptr;      // FP64 copy of K kept by a mixed-precision factorisation
+    double* tpair = nullptr;      // W_p of the two-tile solves (M / 2 tiles), then scratch
+    char* tpair_desc = nullptr;   // device descriptors of the two W_p launches (fixed per handle)
+    char* tpair_host = nullptr;   // their pinned host copy
     int state = GPR_STATE_EMPTY;
     int prec = GPR_FP64;
 };
@@ -466,6 +469,56 @@ bool valid_prec(int prec, int m)
     return (prec == GPR_MIXED_FP32 || prec == GPR_MIXED_BF16) && m % 64 == 0;
 }
 
+// Off-diagonal blocks of the inverses of the 2 x 2 tile blocks (J, J + 1),
+// J = 2 p, for the two-tile vector solves (k_trsv.hip):
+//   W_p = -Tinv_{J+1} (L_{J+1,J} Tinv_J),
+// two batched adjoint-GEMM launches (the second reads the first's products
+// from the scratch half of tpair). Needs the diagonal-tile inverses; the
+// handle's data and tinv buffers are allocated before and never move.
+int build_tinv_pairs(gpr_ctx* ctx, gpr_tiled* L, hipStream_t s)
+{
+    const int M = L->M, m = L->m, P = M / 2;
+    if (P < 1) return GPR_OK;
+    const size_t mm = (size_t)m * m;
+    const size_t ts = ((size_t)P * sizeof(TGemmTask) + 63) & ~size_t(63);
+    const size_t us = ((size_t)P * sizeof(TGemmTerm) + 63) & ~size_t(63);
+    if (!L->tpair) {
+        // the W_p / scratch tiles, and the two launches' descriptors, which
+        // depend only on this handle's buffers: written once, kept with the
+        // handle (the context's descriptor buffer may hold a pending plan)
+        if (hipMalloc(reinterpret_cast<void**>(&L->tpair), 2 * (size_t)P * mm * sizeof(double)) !=
+                hipSuccess ||
+            hipMalloc(reinterpret_cast<void**>(&L->tpair_desc), 2 * (ts + us)) != hipSuccess ||
+            hipHostMalloc(reinterpret_cast<void**>(&L->tpair_host), 2 * (ts + us)) != hipSuccess) {
+            (void)hipGetLastError();
+            return GPR_ENOMEM;
+        }
+        double* W = L->tpair;
+        double* Q = L->tpair + (size_t)P * mm;
+        TGemmTask* t1 = reinterpret_cast<TGemmTask*>(L->tpair_host);
+        TGemmTerm* u1 = reinterpret_cast<TGemmTerm*>(L->tpair_host + ts);
+        TGemmTask* t2 = reinterpret_cast<TGemmTask*>(L->tpair_host + ts + us);
+        TGemmTerm* u2 = reinterpret_cast<TGemmTerm*>(L->tpair_host + 2 * ts + us);
+        for (int p = 0; p < P; ++p) {
+            const int J = 2 * p;
+            t1[p] = TGemmTask{Q + p * mm, nullptr, nullptr, 0, 0.0, m, m, 0, p, 1, TG_EPI_NONE};
+            u1[p] = TGemmTerm{tile_ptr(kmat(L), J + 1, J), L->tinv + (size_t)J * mm, 1.0, m, m, 0, 0};
+            t2[p] = TGemmTask{W + p * mm, nullptr, nullptr, 0, 0.0, m, m, 0, p, 1, TG_EPI_NONE};
+            u2[p] = TGemmTerm{L->tinv + (size_t)(J + 1) * mm, Q + p * mm, -1.0, m, m, 0, 0};
+        }
+        HIP_TRY(hipMemcpyAsync(L->tpair_desc, L->tpair_host, 2 * (ts + us), hipMemcpyHostToDevice,
+                               s));
+    }
+    const char* d = L->tpair_desc;
+    ProfScope ps(ctx, s, PK_TRTRI, 4.0 * P * (double)m * m * m, 0.0);
+    const int bm = tgemm_block(P, m);
+    HIP_TRY(launch_tgemm_f64(reinterpret_cast<const TGemmTask*>(d), P,
+                             reinterpret_cast<const TGemmTerm*>(d + ts), m, bm, s));
+    HIP_TRY(launch_tgemm_f64(reinterpret_cast<const TGemmTask*>(d + ts + us), P,
+                             reinterpret_cast<const TGemmTerm*>(d + 2 * ts + us), m, bm, s));
+    return GPR_OK;
+}
+
 // Vector solves with the factor: beta = L^{-1} rhs, alpha = L^{-T} beta
 // (k_trsv.hip); tmp is scratch. All vectors have length M m.
 int run_trsv_pair(gpr_ctx* ctx, const gpr_tiled* L, const double* rhs, double* tmp,
@@ -475,11 +528,11 @@ int run_trsv_pair(gpr_ctx* ctx, const gpr_tiled* L, const double* rhs, double* t
     const double f = 2.0 * (double)m * m * ((double)M * (M - 1) / 2 + M);
     {
         ProfScope ps(ctx, s, PK_TRSV, f, 0.0);
-        HIP_TRY(launch_trsv(kmat(L), L->tinv, M, rhs, tmp, beta, false, s));
+        HIP_TRY(launch_trsv(kmat(L), L->tinv, L->tpair, M, rhs, tmp, beta, false, s));
     }
     {
         ProfScope ps(ctx, s, PK_TRSV, f, 0.0);
-        HIP_TRY(launch_trsv(kmat(L), L->tinv, M, beta, tmp, alpha, true, s));
+        HIP_TRY(launch_trsv(kmat(L), L->tinv, L->tpair, M, beta, tmp, alpha, true, s));
     }
     return GPR_OK;
 }
@@ -755,6 +808,8 @@ int gpr_cholesky(gpr_ctx* ctx, gpr_tiled* K, gpr_precision prec, int32_t* info_d
         ProfScope ps(ctx, s, PK_TRTRI, M * (double)m * m * m / 3.0, 0.0);
         HIP_TRY(launch_trtri_f64(kmat(K), M, K->tinv, s));
     }
+    rc = build_tinv_pairs(ctx, K, s);
+    if (rc) return rc;
     rc = finish_info(ctx, info_dev, s);
     if (rc) return rc;
     K->state = GPR_STATE_L;
@@ -877,8 +932,12 @@ int predict_impl(gpr_ctx* ctx, gpr_tiled* L, const double* X, const double* y, i
         if (rc) return rc;
     }
     if (fused) {
-        ProfScope ps(ctx, s, PK_TRTRI, M * (double)m * m * m / 3.0, 0.0);
-        HIP_TRY(launch_trtri_f64(kmat(L), M, L->tinv, s));
+        {
+            ProfScope ps(ctx, s, PK_TRTRI, M * (double)m * m * m / 3.0, 0.0);
+            HIP_TRY(launch_trtri_f64(kmat(L), M, L->tinv, s));
+        }
+        rc = build_tinv_pairs(ctx, L, s);
+        if (rc) return rc;
     }
     if (fused) {
         L->state = GPR_STATE_L;
@@ -1185,6 +1244,8 @@ int gpr_nlml_grad(gpr_ctx* ctx, const double* X, const double* y, int64_t n, int
         ProfScope ps(ctx, s, PK_TRTRI, M * (double)m * m * m / 3.0, 0.0);
         HIP_TRY(launch_trtri_f64(kmat(K), M, K->tinv, s));
     }
+    rc = build_tinv_pairs(ctx, K, s);
+    if (rc) return rc;
     K->state = GPR_STATE_L;
     K->prec = GPR_FP64;
     rc = finish_info(ctx, nullptr, s);
@@ -1267,6 +1328,9 @@ int gpr_tiled_free(gpr_tiled* T)
     if (T->data) (void)hipFree(T->data);
     if (T->tinv) (void)hipFree(T->tinv);
     if (T->kcopy) (void)hipFree(T->kcopy);
+    if (T->tpair) (void)hipFree(T->tpair);
+    if (T->tpair_desc) (void)hipFree(T->tpair_desc);
+    if (T->tpair_host) (void)hipHostFree(T->tpair_host);
     delete T;
     return GPR_OK;
 }

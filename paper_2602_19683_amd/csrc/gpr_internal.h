@@ -132,10 +132,12 @@ hipError_t launch_potrf_f64(double* A, int lda, int m, double* Tinv, int ldt, in
 // 32 x 32 diagonal blocks must already hold the block inverses.
 hipError_t launch_trtri_f64(const TileMat& K, int M, double* Tinv, hipStream_t s);
 // x = L^{-1} b (trans: L^{-T} b) over the lower tiles of L with the inverses of
-// its diagonal tiles (Tinv, M tiles), two launches per tile row; r: scratch of
-// length M m (b is copied there first).
-hipError_t launch_trsv(const TileMat& L, const double* Tinv, int M, const double* b, double* r,
-                       double* x, bool trans, hipStream_t s);
+// its diagonal tiles (Tinv, M tiles); r: scratch of length M m (b is copied
+// there first). W (nullable): the off-diagonal blocks W_p = -Tinv_{2p+1}
+// L_{2p+1,2p} Tinv_{2p} of the inverses of the 2 x 2 tile blocks (M / 2
+// tiles); with it, two launches per pair of tile rows, else per tile row.
+hipError_t launch_trsv(const TileMat& L, const double* Tinv, const double* W, int M,
+                       const double* b, double* r, double* x, bool trans, hipStream_t s);
 
 // out_i = base_i - k(A_i, B) x  (subtract) or out_i = k(A_i, B) x  (base == nullptr),
 // where k(A_i, B) x = sum_j k(a_i, b_j) x_j + (noise ? s2 x_i : 0) over j < nb.
