@@ -175,6 +175,49 @@ def persistent_run(Xd, yd, Xsd, h, tile, mean64, cov64, ms64, flops, args, log):
     return out
 
 
+def mixed_mid_run(ctx, args, log):
+    """Mixed precision where BF16 factors: n = 8192, n_test = 2048, tile 256,
+    (l, v, sigma^2) = (1, 1, 0.1). Plain refinement does not contract with
+    BF16 updates here, and conjugate gradients preconditioned by the BF16
+    factor take over. Time per fused call (mean + full covariance), the
+    refinement used, and errors against the FP64 call."""
+    import torch
+    from gpr_inputs import DEFAULT_HYPER, nfir_train_test
+    n, ns, tile = 8192, 2048, 256
+    X, y, Xs = nfir_train_test(n, ns)
+    d = lambda a: torch.from_numpy(a).to("cuda:0")
+    Xd, yd, Xsd = d(X), d(y), d(Xs)
+    out, ref = {}, None
+    for prec in ("fp64", "fp32", "bf16"):
+        mean = torch.empty(ns, dtype=torch.float64, device="cuda:0")
+        cov = torch.empty(ns, ns, dtype=torch.float64, device="cuda:0")
+        _, _, K, st = ctx.fit_predict(Xd, yd, Xsd, DEFAULT_HYPER, tile, prec, mean=mean, cov=cov,
+                                      ir_stats=True)
+        ctx.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            _, _, _, st = ctx.fit_predict(Xd, yd, Xsd, DEFAULT_HYPER, tile, prec, K=K, mean=mean,
+                                          cov=cov, ir_stats=True)
+        ctx.sync()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        rel = lambda a, b: float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
+        r = {"ms_per_call": round(ms, 4)}
+        if prec == "fp64":
+            ref = (mean.clone(), cov.clone())
+        else:
+            r.update({"precision_used": {0: "fp64", 1: "fp32", 2: "bf16"}[st["precision"]],
+                      "refinement": st["method"], "refinement_steps": st["iters"],
+                      "rel_residual": st["rel_residual"],
+                      "rel_mean_vs_fp64": rel(mean, ref[0]), "rel_cov_vs_fp64": rel(cov, ref[1])})
+        out[prec] = r
+        K.free()
+    out["config"] = f"n={n}, n_test={ns}, D=8, tile {tile}, (l, v, sigma^2) = {DEFAULT_HYPER}"
+    log(f"mixed at n=8192: {out}")
+    return out
+
+
 def variants_run(ctx, K, Xd, yd, Xsd, h, tile, args, log):
     """The prediction variants of the same fit (FP64, one fused call each):
     mean only (no test rows swept) and mean + predictive variances (V^T
@@ -428,6 +471,7 @@ def main():
     mixed = None
     if not args.no_mixed and args.precision == "fp64":
         mixed = mixed_runs(ctx, K, step, mean, cov, ms, flops, args, log)
+        mixed["n8192_tile256"] = mixed_mid_run(ctx, args, log)
     nlml = None
     if not args.no_nlml:
         nlml = nlml_run(ctx, args, log)
