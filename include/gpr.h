@@ -149,11 +149,13 @@ int gpr_assemble(gpr_ctx* ctx, const double* X, int64_t n, int32_t D,
 
 /* Factorises K = L L^T in place with the tiled right-looking algorithm of
  * Sec. 4.2 (Fig. 1). The handle must hold K (GPR_EINVAL otherwise); it holds
- * L afterwards, plus the inverse of every diagonal tile of L, which the
- * solves use. prec chooses the precision of the GEMM/SYRK updates.
+ * L afterwards, plus the inverse of every diagonal tile of L and of every
+ * 2 x 2 block of tiles, which the solves use. prec chooses the precision of
+ * the GEMM/SYRK updates.
  * info_dev (optional, device int32): set to 0, or to the 1-based global
  * column of the first pivot that was not > 0 (LAPACK convention); gpr_sync
- * then returns GPR_ENOTPD. After a failed pivot the factor is garbage. */
+ * then returns GPR_ENOTPD. After a failed pivot the rest of the
+ * factorisation is skipped and the handle's contents are meaningless. */
 int gpr_cholesky(gpr_ctx* ctx, gpr_tiled* K, gpr_precision prec,
                  int32_t* info_dev, void* stream);
 
