@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define GPR_ABI_VERSION 5
+#define GPR_ABI_VERSION 6
 
 /* Status codes. */
 enum {
@@ -285,7 +285,11 @@ int gpr_tiled_free(gpr_tiled* T);
 /* Blocks until `stream` has finished the context's queued work, then
  * returns GPR_ENOTPD if any factorisation queued since the previous gpr_sync
  * hit a non-positive pivot (its column in *column if non-NULL, else 0),
- * GPR_OK otherwise. */
+ * GPR_OK otherwise. GPR_EHIP: a HIP call failed, or a device-side wait
+ * between the workgroups of a factorisation (POTRF, persistent sweep) hit its
+ * spin limit; the results of every call queued since the previous gpr_sync
+ * are then invalid. The record is cleared when it is reported, so the
+ * context stays usable and later calls are unaffected. */
 int gpr_sync(gpr_ctx* ctx, void* stream, int64_t* column);
 
 /* ---- instrumentation ------------------------------------------------------
@@ -379,6 +383,11 @@ int gpr_persist_describe(int32_t M, int32_t Mhat, int32_t mode, int32_t tile, in
 
 /* ABI version of the loaded library (GPR_ABI_VERSION it was built with). */
 int gpr_abi_version(void);
+
+/* First 16 hex digits of the SHA-256 of the sources the library was built
+ * from (static string owned by the library), so that a loader can refuse a
+ * binary that does not match its source tree. */
+const char* gpr_source_hash(void);
 
 #ifdef __cplusplus
 }

@@ -35,6 +35,7 @@ _i64p = ctypes.POINTER(ctypes.c_int64)
 # name -> (restype, argtypes)
 SIGNATURES = {
     "gpr_abi_version": (ctypes.c_int, []),
+    "gpr_source_hash": (ctypes.c_char_p, []),
     "gpr_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "gpr_ctx_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, ctypes.c_int]),
     "gpr_ctx_destroy": (ctypes.c_int, [_vp]),
@@ -79,7 +80,8 @@ _LIB = None
 
 
 def load():
-    """Loads the built library; raises if it has not been built (no fallback)."""
+    """Loads the built library; raises if it has not been built, or was built
+    from sources other than the ones in this tree (no fallback)."""
     global _LIB
     if _LIB is None:
         if not os.path.exists(LIB_PATH):
@@ -91,5 +93,16 @@ def load():
             f = getattr(lib, name)
             f.restype = res
             f.argtypes = args
+        from .build import source_hash
+        built, here = lib.gpr_source_hash().decode(), source_hash()
+        if built != here:
+            raise ImportError(
+                f"libgpr.so was built from other sources (hash {built}, tree {here}); "
+                "rebuild it with `python -m paper_2602_19683_amd.build`")
         _LIB = lib
     return _LIB
+
+
+def library_hash() -> str:
+    """Source hash compiled into the loaded library."""
+    return load().gpr_source_hash().decode()

@@ -1,12 +1,15 @@
 """Builds libgpr.so (all HIP sources in csrc/) for gfx950 with hipcc, in-tree.
 
 Every source is compiled on each call (the objects go to a temporary folder),
-then linked into paper_2602_19683_amd/libgpr.so.
+then linked into paper_2602_19683_amd/libgpr.so. The SHA-256 of the sources
+(csrc/ and include/) is compiled into the library (gpr_source_hash), so a
+loader can refuse a library built from other sources.
 """
 from __future__ import annotations
 
 import concurrent.futures as cf
 import glob
+import hashlib
 import os
 import shutil
 import subprocess
@@ -32,10 +35,24 @@ def _sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
 
 
-def _compile(src, obj, verbose):
-    cmd = [HIPCC, *FLAGS, "-c", src, "-o", obj]
+def source_hash() -> str:
+    """First 16 hex digits of the SHA-256 over every file the library is
+    built from (csrc/*, include/*), by name and content, in sorted order."""
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(CSRC, "*")) + glob.glob(os.path.join(ROOT, "include", "*")))
+    for f in files:
+        if os.path.isfile(f):
+            h.update(os.path.relpath(f, ROOT).encode())
+            h.update(b"\0")
+            h.update(open(f, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def _compile(src, obj, verbose, digest):
+    flags = [*FLAGS, f'-DGPR_SOURCE_HASH="{digest}"']
+    cmd = [HIPCC, *flags, "-c", src, "-o", obj]
     if src.endswith(".cpp"):
-        cmd = [HIPCC, "-x", "hip", *FLAGS, "-c", src, "-o", obj]
+        cmd = [HIPCC, "-x", "hip", *flags, "-c", src, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -51,9 +68,10 @@ def build(verbose: bool = False) -> str:
     tmp = tempfile.mkdtemp(prefix="gpr_build_")
     try:
         srcs = _sources()
+        digest = source_hash()
         objs = [os.path.join(tmp, os.path.basename(s) + ".o") for s in srcs]
         with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-            list(ex.map(lambda so: _compile(so[0], so[1], verbose), zip(srcs, objs)))
+            list(ex.map(lambda so: _compile(so[0], so[1], verbose, digest), zip(srcs, objs)))
         out_tmp = LIB + ".tmp"
         cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", out_tmp]
         if verbose:

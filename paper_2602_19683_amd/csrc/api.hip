@@ -671,6 +671,11 @@ extern "C" {
 
 int gpr_abi_version(void) { return GPR_ABI_VERSION; }
 
+#ifndef GPR_SOURCE_HASH
+#define GPR_SOURCE_HASH "unknown"
+#endif
+const char* gpr_source_hash(void) { return GPR_SOURCE_HASH; }
+
 const char* gpr_strerror(int status)
 {
     switch (status) {
@@ -712,6 +717,7 @@ int gpr_ctx_create(gpr_ctx** out, int device, int n_streams, gpr_executor ex)
         gpr_ctx_destroy(c);
         return GPR_EHIP;
     }
+
     *out = c;
     return GPR_OK;
 }
@@ -1404,7 +1410,14 @@ int gpr_sync(gpr_ctx* ctx, void* stream, int64_t* column)
     if (ctx->last_valid) HIP_TRY(hipEventSynchronize(ctx->ev_last));
     int info[3] = {0, 0, 0};
     HIP_TRY(hipMemcpy(info, ctx->d_info, sizeof(info), hipMemcpyDeviceToHost));
-    if (info[2] != 0) return GPR_EHIP;  // a device-side wait timed out
+    if (info[2] != 0) {
+        // a device-side wait timed out: the results of the calls queued since
+        // the previous gpr_sync are invalid; clear the record (and a pivot
+        // failure recorded with it) so that later calls wait normally again
+        const int zero[2] = {0, 0};
+        HIP_TRY(hipMemcpy(ctx->d_info + 1, zero, sizeof(zero), hipMemcpyHostToDevice));
+        return GPR_EHIP;
+    }
     if (info[1] > 0) {
         if (column) *column = info[1];
         const int zero = 0;
