@@ -36,9 +36,9 @@ def _lib(real: str = "double"):
             _build.build()
         lib = ctypes.CDLL(path)
         lib.orc_real_bytes.restype = ctypes.c_int
+        lib.orc_num_threads.restype = ctypes.c_int
         lib.orc_kernel_matrix.argtypes = [_f64p, _i64, _f64p, _i64, ctypes.c_int,
-                                          ctypes.c_double, ctypes.c_double,
-                                          ctypes.c_double, ctypes.c_int, _f64p]
+                                          ctypes.c_double, ctypes.c_double, _f64p]
         lib.orc_assemble_K.argtypes = [_f64p, _i64, ctypes.c_int, ctypes.c_double,
                                        ctypes.c_double, ctypes.c_double, _f64p]
         lib.orc_cholesky.argtypes = [_f64p, _i64, _f64p]
@@ -75,13 +75,19 @@ class OracleError(RuntimeError):
         self.info = info
 
 
-def kernel_matrix(A, B, hyper, add_noise=False, real="double"):
-    """``k(a_i, b_j)`` for all rows (eq. (1)); ``add_noise`` adds sigma^2 where i == j."""
+def num_threads(real="double"):
+    """Threads the oracle's parallel loops run with (OpenMP)."""
+    return int(_lib(real).orc_num_threads())
+
+
+def kernel_matrix(A, B, hyper, real="double"):
+    """``v exp(-|a_i - b_j|^2 / (2 l))`` for all rows (eq. (1) without its
+    noise term: the cross and test covariances carry none)."""
     A, B = _c(A), _c(B)
-    l, v, s2 = hyper
+    l, v, _ = hyper
     out = np.empty((A.shape[0], B.shape[0]))
     _lib(real).orc_kernel_matrix(_p(A), A.shape[0], _p(B), B.shape[0], A.shape[1],
-                                 l, v, s2, int(add_noise), _p(out))
+                                 l, v, _p(out))
     return out
 
 

@@ -31,6 +31,7 @@
  * rounding and the order of sums).
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -45,6 +46,18 @@ typedef OR_REAL real;
 
 /* sizeof the arithmetic type, so a caller can tell the two builds apart. */
 int orc_real_bytes(void) { return (int)sizeof(real); }
+
+/* Threads an OpenMP parallel region of this library runs with. */
+int orc_num_threads(void)
+{
+    int t = 1;
+#pragma omp parallel
+    {
+#pragma omp single
+        t = omp_get_num_threads();
+    }
+    return t;
+}
 
 /* ---------------------------------------------------------------------- */
 /* Kernel, eq. (1)                                                         */
@@ -69,20 +82,16 @@ static real kse(const double* a, const double* b, int D, real l, real v)
 }
 
 /* out[i*nb + j] = v exp(-|a_i - b_j|^2 / (2 l)) for the rows a_i of A
- * (na x D) and b_j of B (nb x D). With add_noise != 0, sigma^2 is added where
- * i == j (the Kronecker delta of eq. (1), applied by index, which is only
- * meaningful when A and B are the same training set). */
+ * (na x D) and b_j of B (nb x D): the squared-exponential part of eq. (1),
+ * no noise term (the cross covariance K_{X*,X} and the test block K_{X*,X*}
+ * carry none under the index reading of eq. (1)'s Kronecker delta). */
 void orc_kernel_matrix(const double* A, int64_t na, const double* B, int64_t nb,
-                       int D, double l, double v, double s2, int add_noise,
-                       double* out)
+                       int D, double l, double v, double* out)
 {
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < na; ++i)
-        for (int64_t j = 0; j < nb; ++j) {
-            real k = kse(A + i * D, B + j * D, D, (real)l, (real)v);
-            if (add_noise && i == j) k += (real)s2;
-            out[i * nb + j] = (double)k;
-        }
+        for (int64_t j = 0; j < nb; ++j)
+            out[i * nb + j] = (double)kse(A + i * D, B + j * D, D, (real)l, (real)v);
 }
 
 /* Training covariance K = k(X, X) + sigma^2 I: entries with i >= j are

@@ -2,9 +2,13 @@
 and checks that the pins in test_oracle_pins catch every one of them: a
 dropped term, a wrong sign, a transposed index, a swapped operand, the
 textbook 2 l^2 in place of eq. (1)'s printed 2 l, noise put on the wrong
-covariance."""
+covariance. The error metrics (Python) get the same treatment: a mutated
+copy of each metric function replaces it, and the hand-worked metric pins
+must fail."""
+import inspect
 import os
 import subprocess
+import textwrap
 
 import pytest
 
@@ -79,4 +83,52 @@ def test_pins_catch_mutant(tmp_path, monkeypatch, name, old, new):
 
 def test_unmutated_oracle_passes_all_listed_pins():
     for pin in PINS:
+        pin()
+
+
+METRIC_MUTANTS = [
+    ("rel_err divides by ||A||", "rel_err", "nb = float(np.linalg.norm(B))",
+     "nb = float(np.linalg.norm(A))"),
+    ("rel_err uses the max norm", "rel_err", "d = float(np.linalg.norm(A - B))",
+     "d = float(np.max(np.abs(A - B)))"),
+    ("rel_err without the division", "rel_err", "return d / nb if nb > 0 else d", "return d"),
+    ("rel_err squared norms", "rel_err", "return d / nb if nb > 0 else d",
+     "return (d / nb) ** 2 if nb > 0 else d"),
+    ("rel_err_lower takes upper triangles", "rel_err_lower",
+     "return rel_err(np.tril(A), np.tril(B))", "return rel_err(np.triu(A), np.triu(B))"),
+    ("rel_err_lower drops the diagonal", "rel_err_lower",
+     "return rel_err(np.tril(A), np.tril(B))", "return rel_err(np.tril(A, -1), np.tril(B, -1))"),
+    ("max_rel signed max", "max_rel", "mb = float(np.max(np.abs(B))) if B.size else 0.0",
+     "mb = float(np.max(B)) if B.size else 0.0"),
+    ("max_rel uses the mean difference", "max_rel",
+     "md = float(np.max(np.abs(A - B))) if A.size else 0.0",
+     "md = float(np.mean(np.abs(A - B))) if A.size else 0.0"),
+]
+
+METRIC_PINS = [pins.test_rel_err_hand_values, pins.test_rel_err_lower_hand_values,
+               pins.test_max_rel_hand_values]
+
+
+@pytest.mark.parametrize("name,func,old,new", METRIC_MUTANTS, ids=[m[0] for m in METRIC_MUTANTS])
+def test_metric_pins_catch_mutant(monkeypatch, name, func, old, new):
+    src = textwrap.dedent(inspect.getsource(getattr(oracle, func)))
+    assert old in src, f"mutation site not found: {old!r}"
+    ns = dict(vars(oracle))
+    exec(compile(src.replace(old, new), f"<mutant {name}>", "exec"), ns)
+    monkeypatch.setattr(oracle, func, ns[func])
+    if func == "rel_err":
+        # rel_err_lower calls rel_err through the module namespace
+        src_l = textwrap.dedent(inspect.getsource(oracle.rel_err_lower))
+        exec(compile(src_l, "<rel_err_lower>", "exec"), ns)
+        monkeypatch.setattr(oracle, "rel_err_lower", ns["rel_err_lower"])
+    for pin in METRIC_PINS:
+        try:
+            pin()
+        except AssertionError:
+            return
+    pytest.fail(f"no metric pin caught mutant: {name}")
+
+
+def test_unmutated_metrics_pass_their_pins():
+    for pin in METRIC_PINS:
         pin()

@@ -398,3 +398,43 @@ def test_adam_replay_vs_torch_adam():
         opt.step()
     np.testing.assert_allclose(th_end, torch.exp(z).detach().numpy(), rtol=1e-10)
     assert trace[-1][1] < trace[0][1]
+
+
+# --------------------------------------------------------------------------
+# Error metrics (the normwise reading of "relative error 1e-10"): values
+# worked out by hand
+# --------------------------------------------------------------------------
+
+def test_rel_err_hand_values():
+    # vectors: diff (1, 0, -2), ||diff|| = sqrt(5), ||B|| = sqrt(14)
+    assert oracle.rel_err([2.0, 2.0, 1.0], [1.0, 2.0, 3.0]) == pytest.approx(math.sqrt(5 / 14),
+                                                                           rel=1e-15)
+    # matrices use the Frobenius norm: diff [[0, -2], [0, -2]], ||B||_F = sqrt(14)
+    A = np.array([[1.0, 0.0], [0.0, 1.0]])
+    B = np.array([[1.0, 2.0], [0.0, 3.0]])
+    assert oracle.rel_err(A, B) == pytest.approx(math.sqrt(8 / 14), rel=1e-15)
+    # not symmetric in its arguments: ||A - B|| / ||B||, not / ||A||
+    assert oracle.rel_err(B, A) == pytest.approx(math.sqrt(8 / 2), rel=1e-15)
+    # zero reference: the absolute norm of the difference
+    assert oracle.rel_err([1.0, 2.0, 2.0], [0.0, 0.0, 0.0]) == 3.0
+    assert oracle.rel_err([0.0], [0.0]) == 0.0
+
+
+def test_rel_err_lower_hand_values():
+    # only the lower triangles count: diff tril = [[0, 0], [2, 0]],
+    # ||tril B||_F = sqrt(1 + 0 + 9) (the upper entries 9 and -5 are ignored)
+    A = np.array([[1.0, 9.0], [2.0, 3.0]])
+    B = np.array([[1.0, -5.0], [0.0, 3.0]])
+    assert oracle.rel_err_lower(A, B) == pytest.approx(2 / math.sqrt(10), rel=1e-15)
+    # the diagonal is part of the lower triangle
+    C = np.array([[2.0, 0.0], [0.0, 3.0]])
+    assert oracle.rel_err_lower(C, B) == pytest.approx(1 / math.sqrt(10), rel=1e-15)
+
+
+def test_max_rel_hand_values():
+    # max|A - B| = |4 - (-8)| = 12, max|B| = 8 (absolute values, not signed max)
+    A = np.array([[1.0, 2.0], [3.0, 4.0]])
+    B = np.array([[1.0, 2.5], [2.0, -8.0]])
+    assert oracle.max_rel(A, B) == 1.5
+    assert oracle.max_rel(B, B) == 0.0
+    assert oracle.max_rel([0.5], [0.0]) == 0.5
