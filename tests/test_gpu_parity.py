@@ -4,8 +4,9 @@ FP64 bar: normwise relative error <= 1e-10 against the double oracle
 (Frobenius norm over the lower triangle for L, 2-norm for the mean,
 Frobenius for the covariance). The achieved figures are printed; they are
 expected near 1e-14. At the full benchmark size (n = 16384, n_test = 4096,
-tile 512) the oracle would take minutes, so the check there uses outputs the
-oracle computes one by one plus properties that hold at any size.
+tile 512) the three-call path is checked here through outputs the oracle
+computes one by one plus properties that hold at any size; the fused call the
+benchmark times is compared with the full oracle in test_gpu_c3_oracle.py.
 """
 import numpy as np
 import pytest
@@ -246,7 +247,8 @@ def test_predict_4096_tile_sweep(ctx, tile):
     assert em <= TOL and ec <= TOL
 
 
-@pytest.mark.parametrize("n,ns,tile", [(128, 128, 32), (1000, 300, 128), (4096, 1024, 256)])
+@pytest.mark.parametrize("n,ns,tile", [(128, 128, 32), (1000, 300, 128), (4096, 1024, 256),
+                                       (4096, 1024, 512), (3000, 700, 512)])
 def test_fused_sweep_equals_three_calls(ctx, n, ns, tile):
     say(f"fit_predict vs assemble+cholesky+predict n={n} n_test={ns} tile={tile}")
     X, y, Xs = nfir_train_test(n, ns)
@@ -258,6 +260,10 @@ def test_fused_sweep_equals_three_calls(ctx, n, ns, tile):
     assert int(info.item()) == 0
     np.testing.assert_array_equal(m, a[0])
     np.testing.assert_array_equal(c, a[1])
+    ref = oracle.predict(X, y, Xs, DEFAULT_HYPER, want=("mean", "cov"))
+    em, ec = oracle.rel_err(m, ref["mean"]), oracle.rel_err(c, ref["cov"])
+    say(f"  fused vs oracle: rel(mean) = {em:.3e}  rel(cov) = {ec:.3e}")
+    assert em <= TOL and ec <= TOL
     # the handle now holds the factor: a second prediction through it agrees
     m2, c2 = ctx.predict(K, Xd, yd, Xsd, DEFAULT_HYPER)
     np.testing.assert_array_equal(host(m2), m)

@@ -4,8 +4,9 @@ per-tile progress counters) against the stream executor and the oracle.
 Both executors run the same device routines with the same per-element
 operation order, so every FP64 result must agree BIT FOR BIT: factor,
 mean, covariance, NLML and gradient. Small cases are also checked against
-the oracle (FP64 bar 1e-10), and the full benchmark shape (n = 16384,
-n_test = 4096, tile 512) is compared bitwise with the stream executor.
+the oracle (FP64 bar 1e-10) at every size up to n = 4096; the full benchmark
+shape (n = 16384, n_test = 4096, tile 512) is compared bitwise with the stream
+executor here and with the oracle in test_gpu_c3_oracle.py.
 """
 import numpy as np
 import pytest
@@ -62,12 +63,11 @@ def test_cholesky_bitwise_equal_to_streams(ctxs, n, tile):
     Ls = factor(s, X, DEFAULT_HYPER, tile)
     Lp = factor(p, X, DEFAULT_HYPER, tile)
     np.testing.assert_array_equal(Lp, Ls)
-    if n <= 1000:
-        Lref, info = oracle.cholesky(oracle.assemble_K(X, DEFAULT_HYPER))
-        assert info == 0
-        e = oracle.rel_err_lower(np.tril(Lp), Lref)
-        say(f"  rel(L) vs oracle {e:.3e}")
-        assert e <= TOL
+    Lref, info = oracle.cholesky(oracle.assemble_K(X, DEFAULT_HYPER))
+    assert info == 0
+    e = oracle.rel_err_lower(np.tril(Lp), Lref)
+    say(f"  rel(L) vs oracle {e:.3e}")
+    assert e <= TOL
 
 
 @pytest.mark.parametrize("n,ns,tile", [(128, 128, 32), (70, 5, 32), (1000, 300, 128),
@@ -89,11 +89,10 @@ def test_fit_predict_bitwise_equal_to_streams(ctxs, n, ns, tile):
         K.free()
     np.testing.assert_array_equal(out[1][0], out[0][0])
     np.testing.assert_array_equal(out[1][1], out[0][1])
-    if n <= 1000:
-        ref = oracle.predict(X, y, Xs, DEFAULT_HYPER)
-        em, ec = oracle.rel_err(out[1][0], ref["mean"]), oracle.rel_err(out[1][1], ref["cov"])
-        say(f"  rel(mean) {em:.3e} rel(cov) {ec:.3e}")
-        assert em <= TOL and ec <= TOL
+    ref = oracle.predict(X, y, Xs, DEFAULT_HYPER)
+    em, ec = oracle.rel_err(out[1][0], ref["mean"]), oracle.rel_err(out[1][1], ref["cov"])
+    say(f"  rel(mean) {em:.3e} rel(cov) {ec:.3e}")
+    assert em <= TOL and ec <= TOL
 
 
 @pytest.mark.parametrize("prec,n,ns,tile", [("fp32", 1000, 300, 128), ("fp32", 4096, 1024, 512),
