@@ -1,7 +1,7 @@
-"""The tile schedule (host logic, no GPU): task multiset of Fig. 1, the
-Fig. 2 example, a race check of the two-stream launch order against the
-sequential loop nest of Fig. 1, and a host execution of the schedule in
-random orders compared with the oracle."""
+"""The tile schedule (host logic, no GPU): task counts of Fig. 1, the Fig. 2
+example, a race check of the three-stream launch order against the data
+dependencies of the block Cholesky equations (Sec. 4.2), and a host execution
+of the schedule in random orders compared with the oracle."""
 import os
 import random
 
@@ -17,46 +17,57 @@ POTRF, TRSM, SYRK, GEMM = 0, 1, 2, 3
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "fig2_first_iteration.txt")
 
 
-def fig1_program(M, Mhat, mode):
-    """The loop nest of Fig. 1 as a sequential task list, extended with the
-    test rows M..M+Mhat-1 of the covariance solve (modes 1 to 4; modes 3 and 4
-    leave out the updates of the test block, K >= M)."""
+def block_cholesky_tasks(M, Mhat, mode):
+    """Tile tasks and their data dependencies, derived from the block form of
+    K = L L^T on lower tiles (Sec. 4.2) rather than from a printed loop:
+      L_KK = chol(A_KK - sum_{J<K} L_KJ L_KJ^T),
+      L_IK = (A_IK - sum_{J<K} L_IJ L_KJ^T) L_KK^{-T}     (I > K),
+    extended with the test rows M..M+Mhat-1 of the covariance solve
+    (V^T = K_{X*,X} L^{-T} and K_{X*,X*} - V^T V; modes 1 to 4, modes 3 and 4
+    without the test block). Each term L_IJ L_KJ^T is one update task
+    (I, K, J) (SYRK when I == K, else GEMM) applied to tile (I, K) in
+    increasing J; a tile becomes final by its POTRF or TRSM. Returns the task
+    list and the edges (a, b): b reads what a writes, or both update the same
+    tile in that order (so the accumulation order is fixed)."""
     factor = mode in (0, 2, 4)
     predict = mode in (1, 2, 3, 4)
     block = mode in (1, 2)
     T = M + (Mhat if predict else 0)
-    rows = [I for I in range(T) if (I < M and factor) or (I >= M and predict)]
-    prog = []
-    for J in range(M):
-        if factor:
-            prog.append((POTRF, J, J, J))
-        for I in rows:
-            if I > J:
-                prog.append((TRSM, I, J, J))
-        for I in rows:
-            if I <= J:
+
+    def row_swept(I):
+        return (I < M and factor) or (I >= M and predict)
+
+    def producer(I, K):
+        """The task that makes L tile (I, K) (K < M) final; None if given."""
+        if not row_swept(I):
+            return None
+        return (POTRF, K, K, K) if I == K else (TRSM, I, K, K)
+
+    tasks, edges = [], []
+    for I in range(T):
+        if not row_swept(I):
+            continue
+        for K in range(I + 1):
+            if K >= M and not block:
                 continue
-            if I < M or block:
-                prog.append((SYRK, I, I, J))
-            for K in range(J + 1, I):
-                if (I >= M or factor) and (K < M or block):
-                    prog.append((GEMM, I, K, J))
-    return prog
-
-
-def accesses(task, M, mode):
-    kind, I, K, J = task
-    def w(t):
-        return (t, "w")
-    def r(t):
-        return (t, "r")
-    if kind == POTRF:
-        return [w((J, J))]
-    if kind == TRSM:
-        return [r((J, J)), w((I, J))]
-    if kind == SYRK:
-        return [r((I, J)), w((I, I))]
-    return [r((I, J)), r((K, J)), w((I, K))]
+            prev = None
+            for J in range(min(K, M)):
+                u = (SYRK if I == K else GEMM, I, K, J)
+                tasks.append(u)
+                for src in (producer(I, J), producer(K, J)):
+                    if src is not None:
+                        edges.append((src, u))
+                if prev is not None:
+                    edges.append((prev, u))
+                prev = u
+            if K < M:
+                fin = producer(I, K)
+                tasks.append(fin)
+                if prev is not None:
+                    edges.append((prev, fin))
+                if I != K and producer(K, K) is not None:
+                    edges.append((producer(K, K), fin))
+    return tasks, edges
 
 
 def happens_before(launches):
@@ -130,36 +141,31 @@ def test_memory_fraction_of_lower_tiles():
                                          (5, 3, 4), (2, 2, 4), (1, 3, 4), (6, 1, 4)])
 def test_schedule_has_no_races(M, Mhat, mode):
     tasks, launches = schedule_describe(M, Mhat, mode)
-    prog = fig1_program(M, Mhat, mode)
+    want, edges = block_cholesky_tasks(M, Mhat, mode)
     got = sorted(tuple(t[:4]) for t in tasks)
-    assert got == sorted(prog), "schedule task multiset differs from Fig. 1"
+    assert got == sorted(want), "schedule task multiset differs from the block equations"
     where = {tuple(t[:4]): int(t[4]) for t in tasks}
     reach, _ = happens_before([tuple(l) for l in launches])
     # launches only wait on earlier launches of other streams
     for i, (st, w0, w1, w2, _) in enumerate(launches):
         for w in (w0, w1, w2):
             assert w < i and (w < 0 or launches[w][0] != st)
-
-    def ordered(a, b):
+    # every data dependency is ordered by stream order or an event (two
+    # tasks of one launch run concurrently, so a dependency between them is
+    # a race)
+    for a, b in edges:
         la, lb = where[a], where[b]
-        return la != lb and (reach[lb] >> la) & 1
-
-    last_w = {}
-    reads = {}
-    for task in prog:
-        for tile, kind in accesses(task, M, mode):
-            if kind == "r":
-                if tile in last_w:
-                    assert ordered(last_w[tile], task), f"RAW race {last_w[tile]} -> {task}"
-                reads.setdefault(tile, []).append(task)
-            else:
-                if tile in last_w:
-                    assert ordered(last_w[tile], task), f"WAW race {last_w[tile]} -> {task}"
-                for rd in reads.get(tile, []):
-                    if rd != task:
-                        assert ordered(rd, task), f"WAR race {rd} -> {task}"
-                reads[tile] = []
-                last_w[tile] = task
+        assert la != lb and (reach[lb] >> la) & 1, f"race {a} -> {b}"
+    # and every write of a tile is ordered with every other access to it
+    # through those edges: the only writers of tile (I, K) are its updates
+    # (chained) and its POTRF / TRSM (after the chain); its readers come
+    # after its final writer
+    writers = {}
+    for t in want:
+        writers.setdefault((t[1], t[2]), []).append(t)
+    for tile, ws in writers.items():
+        for x, y in zip(ws, ws[1:]):
+            assert (reach[where[y]] >> where[x]) & 1, f"unordered writes of {tile}: {x}, {y}"
 
 
 def run_schedule_on_host(tiles, tinv, tasks, launches, rng):
