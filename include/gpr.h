@@ -253,11 +253,16 @@ int gpr_nlml_grad(gpr_ctx* ctx, const double* X, const double* y, int64_t n,
  * at theta = exp(z) on the GPU (FP64), then takes the bias-corrected Adam
  * step with (lr, beta1, beta2, eps). The paper fixes the hyperparameters
  * (Sec. 3); this is the usual maximum-likelihood fit of the same model.
+ * The loop is device-resident: z, the moments and theta stay in device
+ * memory, the kernels of each evaluation read theta from there, and a
+ * one-thread kernel takes the Adam step, so the host does not wait between
+ * steps; it reads the stop flag every 4 steps (evaluations issued after the
+ * stop leave the result unchanged).
  * Stops after max_steps, or once the NLML changed by at most tol relative to
  * the previous evaluation (tol = 0: never). theta0, theta_out (3 doubles),
  * nlml_trace (max_steps doubles, the NLML before each step; may be NULL) and
  * steps_done (may be NULL) are HOST pointers; X and y are device arrays as in
- * gpr_nlml_grad. Synchronises the stream once per step. Errors as in
+ * gpr_nlml_grad. Returns after synchronising the stream. Errors as in
  * gpr_nlml_grad; GPR_ENOTPD if K(theta) stopped being positive definite
  * along the way (theta_out is then not written). */
 int gpr_fit_hyper(gpr_ctx* ctx, const double* X, const double* y, int64_t n,

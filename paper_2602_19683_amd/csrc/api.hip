@@ -15,6 +15,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstddef>
 #include <cstdlib>
 #include <cstring>
 #include <new>
@@ -44,7 +45,8 @@ struct gpr_ctx {
     size_t ws_cap = 0;
     gpr_tiled* scratch = nullptr; // for gpr_cholesky_dense
     gpr_tiled* nlml_K = nullptr;  // factor kept by gpr_nlml_grad
-    double* d_fit = nullptr;      // NLML and gradient of gpr_fit_hyper's current step
+    char* d_fit = nullptr;        // gpr_fit_hyper: NLML and gradient, Adam state, NLML trace
+    size_t fit_cap = 0;
     char* d_adj = nullptr;        // adjoint workspace (Lbar, Abar, partial tiles)
     size_t adj_cap = 0;
     // persistent executor: ticket order of the last sweep shape (device copy)
@@ -1077,6 +1079,131 @@ int predict_impl(gpr_ctx* ctx, gpr_tiled* L, const double* X, const double* y, i
     return GPR_OK;
 }
 
+// One NLML (and gradient) evaluation, split into the part that depends only
+// on the shape (buffers and launch descriptors, uploaded once) and the
+// launches, so that a loop of evaluations (the hyperparameter fit) plans once.
+struct NlmlRun {
+    gpr_tiled* K = nullptr;
+    bool grad = false;
+    int nparts = 0;
+    double *r = nullptr, *beta = nullptr, *alpha = nullptr, *tmp = nullptr, *parts = nullptr;
+    SweepMats SM{};
+    SweepPlan PP;
+    AdjPlan AP;
+    AdjExec AE;
+    AdjBufs AB{};
+    DescBuffer db;
+};
+
+int nlml_prepare(gpr_ctx* ctx, int64_t n, int32_t tile, bool grad, NlmlRun& R, hipStream_t s)
+{
+    gpr_tiled* K = ctx->nlml_K;
+    if (K && (K->n != n || K->m != tile)) {
+        gpr_tiled_free(K);
+        K = ctx->nlml_K = nullptr;
+    }
+    if (!K) {
+        int rc = alloc_tiled(ctx, n, tile, &K);
+        if (rc) return rc;
+        ctx->nlml_K = K;
+    }
+    const int m = K->m, M = K->M;
+    if (!K->tinv) {
+        if (hipMalloc(reinterpret_cast<void**>(&K->tinv), (size_t)M * m * m * sizeof(double)) !=
+            hipSuccess) {
+            (void)hipGetLastError();
+            return GPR_ENOMEM;
+        }
+    }
+    R.K = K;
+    R.grad = grad;
+    const size_t npad = (size_t)M * m;
+    R.nparts = grad ? grad_reduce_parts(M, m) : 0;
+    int rc = ensure_device_bytes(&ctx->d_ws, &ctx->ws_cap,
+                                 (4 * npad + 3 * (size_t)(R.nparts + 1)) * sizeof(double) + 256);
+    if (rc) return rc;
+    R.r = reinterpret_cast<double*>(ctx->d_ws);
+    R.beta = R.r + npad;
+    R.alpha = R.beta + npad;
+    R.tmp = R.alpha + npad;     // scratch of the triangular solves
+    R.parts = R.tmp + npad;
+    R.SM = SweepMats{kmat(K), K->tinv, TileMat{nullptr, m, 1, M}, TileMat{nullptr, m, 0, 0}, M,
+                     0, m, GPR_FP64};
+    R.PP = plan_sweep(ctx, R.SM, SWEEP_CHOLESKY, R.db);
+    if (grad) {
+        R.AP = build_adjoint(M, ADJ_CHUNK);
+        const size_t tb = tiled_bytes(K);
+        const size_t m2b = (size_t)m * m * sizeof(double);
+        rc = ensure_device_bytes(&ctx->d_adj, &ctx->adj_cap,
+                                 2 * tb + (size_t)(R.AP.max_part + 3) * m2b);
+        if (rc) return rc;
+        double* base = reinterpret_cast<double*>(ctx->d_adj);
+        R.AB.L = kmat(K);
+        R.AB.Lbar = TileMat{base, m, 0, 0};
+        R.AB.Abar = TileMat{base + tb / sizeof(double), m, 0, 0};
+        R.AB.part = base + 2 * tb / sizeof(double);
+        R.AB.q = R.AB.part + (size_t)R.AP.max_part * m * m;
+        R.AB.g = R.AB.q + (size_t)m * m;
+        R.AB.x = R.AB.g + (size_t)m * m;
+        R.AB.tinv = K->tinv;
+        R.AB.m = m;
+        R.AE = plan_adjoint_exec(R.AP, R.AB, R.db);
+    }
+    return R.db.upload(ctx, s);
+}
+
+// The launches of one evaluation at (l, v, sigma^2) = h, or at the device
+// array hyp (3 doubles) when it is given.
+int nlml_launch(gpr_ctx* ctx, NlmlRun& R, const double* X, const double* y, int64_t n, int32_t D,
+                const gpr_hyper& h, const double* hyp, double* out_nlml, double* out_grad3,
+                double* out_Kbar, hipStream_t s)
+{
+    gpr_tiled* K = R.K;
+    const int m = K->m, M = K->M;
+    const size_t npad = (size_t)M * m;
+    // K (with noise), its factor, and the diagonal-tile inverses
+    {
+        ProfScope ps(ctx, s, PK_ASSEMBLE, 0.0, (double)tiled_bytes(K));
+        HIP_TRY(launch_assemble(kmat(K), M, X, n, X, n, D, h.lengthscale, h.vertical_variance,
+                                h.noise_variance, true, true, s, hyp));
+    }
+    K->state = GPR_STATE_K;
+    HIP_TRY(launch_set_int(ctx->d_info, 0, s));
+    int rc = run_sweep(ctx, R.SM, R.PP, R.db, s);
+    if (rc) return rc;
+    {
+        ProfScope ps(ctx, s, PK_TRTRI, M * (double)m * m * m / 3.0, 0.0);
+        HIP_TRY(launch_trtri_f64(kmat(K), M, K->tinv, s));
+    }
+    rc = build_tinv_pairs(ctx, K, s);
+    if (rc) return rc;
+    K->state = GPR_STATE_L;
+    K->prec = GPR_FP64;
+    rc = finish_info(ctx, nullptr, s);
+    if (rc) return rc;
+    // beta = L^{-1} y (kept), alpha = L^{-T} beta
+    HIP_TRY(launch_copy_f64(y, R.r, n, (int64_t)npad, s));
+    rc = run_trsv_pair(ctx, K, R.r, R.tmp, R.beta, R.alpha, s);
+    if (rc) return rc;
+    if (R.grad) {
+        {
+            ProfScope ps(ctx, s, PK_REDUCE, 0.0, (double)tiled_bytes(K));
+            HIP_TRY(launch_lbar_init(R.AB.Lbar, R.AB.L, M, R.alpha, R.beta, s));
+        }
+        rc = run_adjoint(ctx, R.AP, R.AE, m, R.db, s);
+        if (rc) return rc;
+        {
+            ProfScope ps(ctx, s, PK_REDUCE, 0.0, (double)tiled_bytes(K));
+            HIP_TRY(launch_grad_reduce(R.AB.Abar, M, X, n, D, h.lengthscale, R.parts, s, hyp));
+        }
+        if (out_Kbar) HIP_TRY(launch_kbar_export(R.AB.Abar, n, out_Kbar, s));
+    }
+    HIP_TRY(launch_nlml_finish(kmat(K), R.beta, n, R.parts, out_grad3 ? R.nparts : 0,
+                               h.lengthscale, h.vertical_variance, ctx->d_info, out_nlml,
+                               out_grad3, s, hyp));
+    return GPR_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1177,104 +1304,11 @@ int gpr_nlml_grad(gpr_ctx* ctx, const double* X, const double* y, int64_t n, int
     hipStream_t s = static_cast<hipStream_t>(stream);
     int rc = begin_call(ctx, s);
     if (rc) return rc;
-    gpr_tiled* K = ctx->nlml_K;
-    if (K && (K->n != n || K->m != tile)) {
-        gpr_tiled_free(K);
-        K = ctx->nlml_K = nullptr;
-    }
-    if (!K) {
-        rc = alloc_tiled(ctx, n, tile, &K);
-        if (rc) return rc;
-        ctx->nlml_K = K;
-    }
-    const int m = K->m, M = K->M;
-    if (!K->tinv) {
-        if (hipMalloc(reinterpret_cast<void**>(&K->tinv), (size_t)M * m * m * sizeof(double)) !=
-            hipSuccess) {
-            (void)hipGetLastError();
-            return GPR_ENOMEM;
-        }
-    }
-    const bool grad = out_grad3 || out_Kbar;
-    const size_t npad = (size_t)M * m;
-    const int nparts = grad ? grad_reduce_parts(M, m) : 0;
-    rc = ensure_device_bytes(&ctx->d_ws, &ctx->ws_cap,
-                             (4 * npad + 3 * (size_t)(nparts + 1)) * sizeof(double) + 256);
+    NlmlRun R;
+    rc = nlml_prepare(ctx, n, tile, out_grad3 || out_Kbar, R, s);
     if (rc) return rc;
-    double* r = reinterpret_cast<double*>(ctx->d_ws);
-    double* beta = r + npad;
-    double* alpha = beta + npad;
-    double* tmp = alpha + npad;     // scratch of the triangular solves
-    double* parts = tmp + npad;
-
-    DescBuffer db;
-    SweepMats SM{kmat(K), K->tinv, TileMat{nullptr, m, 1, M}, TileMat{nullptr, m, 0, 0}, M, 0, m,
-                 GPR_FP64};
-    SweepPlan PP = plan_sweep(ctx, SM, SWEEP_CHOLESKY, db);
-    AdjPlan AP;
-    AdjExec AE;
-    AdjBufs AB{};
-    if (grad) {
-        AP = build_adjoint(M, ADJ_CHUNK);
-        const size_t tb = tiled_bytes(K);
-        const size_t m2b = (size_t)m * m * sizeof(double);
-        rc = ensure_device_bytes(&ctx->d_adj, &ctx->adj_cap,
-                                 2 * tb + (size_t)(AP.max_part + 3) * m2b);
-        if (rc) return rc;
-        double* base = reinterpret_cast<double*>(ctx->d_adj);
-        AB.L = kmat(K);
-        AB.Lbar = TileMat{base, m, 0, 0};
-        AB.Abar = TileMat{base + tb / sizeof(double), m, 0, 0};
-        AB.part = base + 2 * tb / sizeof(double);
-        AB.q = AB.part + (size_t)AP.max_part * m * m;
-        AB.g = AB.q + (size_t)m * m;
-        AB.x = AB.g + (size_t)m * m;
-        AB.tinv = K->tinv;
-        AB.m = m;
-        AE = plan_adjoint_exec(AP, AB, db);
-    }
-    rc = db.upload(ctx, s);
+    rc = nlml_launch(ctx, R, X, y, n, D, h, nullptr, out_nlml, out_grad3, out_Kbar, s);
     if (rc) return rc;
-
-    // K (with noise), its factor, and the diagonal-tile inverses
-    {
-        ProfScope ps(ctx, s, PK_ASSEMBLE, 0.0, (double)tiled_bytes(K));
-        HIP_TRY(launch_assemble(kmat(K), M, X, n, X, n, D, h.lengthscale, h.vertical_variance,
-                                h.noise_variance, true, true, s));
-    }
-    K->state = GPR_STATE_K;
-    HIP_TRY(launch_set_int(ctx->d_info, 0, s));
-    rc = run_sweep(ctx, SM, PP, db, s);
-    if (rc) return rc;
-    {
-        ProfScope ps(ctx, s, PK_TRTRI, M * (double)m * m * m / 3.0, 0.0);
-        HIP_TRY(launch_trtri_f64(kmat(K), M, K->tinv, s));
-    }
-    rc = build_tinv_pairs(ctx, K, s);
-    if (rc) return rc;
-    K->state = GPR_STATE_L;
-    K->prec = GPR_FP64;
-    rc = finish_info(ctx, nullptr, s);
-    if (rc) return rc;
-    // beta = L^{-1} y (kept), alpha = L^{-T} beta
-    HIP_TRY(launch_copy_f64(y, r, n, (int64_t)npad, s));
-    rc = run_trsv_pair(ctx, K, r, tmp, beta, alpha, s);
-    if (rc) return rc;
-    if (grad) {
-        {
-            ProfScope ps(ctx, s, PK_REDUCE, 0.0, (double)tiled_bytes(K));
-            HIP_TRY(launch_lbar_init(AB.Lbar, AB.L, M, alpha, beta, s));
-        }
-        rc = run_adjoint(ctx, AP, AE, m, db, s);
-        if (rc) return rc;
-        {
-            ProfScope ps(ctx, s, PK_REDUCE, 0.0, (double)tiled_bytes(K));
-            HIP_TRY(launch_grad_reduce(AB.Abar, M, X, n, D, h.lengthscale, parts, s));
-        }
-        if (out_Kbar) HIP_TRY(launch_kbar_export(AB.Abar, n, out_Kbar, s));
-    }
-    HIP_TRY(launch_nlml_finish(kmat(K), beta, n, parts, out_grad3 ? nparts : 0, h.lengthscale,
-                               h.vertical_variance, ctx->d_info, out_nlml, out_grad3, s));
     return end_call(ctx, s);
 }
 
@@ -1346,56 +1380,68 @@ int gpr_fit_hyper(gpr_ctx* ctx, const double* X, const double* y, int64_t n, int
                   double beta2, double eps, double tol, double* theta_out, double* nlml_trace,
                   int32_t* steps_done, void* stream)
 {
-    if (!ctx || !X || !y || !theta0 || !theta_out || max_steps < 1 || !(lr > 0) ||
-        !(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) || !(eps >= 0) || !(tol >= 0))
+    if (!ctx || !X || !y || n < 1 || D < 1 || !valid_tile(tile) || !theta0 || !theta_out ||
+        max_steps < 1 || !(lr > 0) || !(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) ||
+        !(eps >= 0) || !(tol >= 0))
         return GPR_EINVAL;
     for (int k = 0; k < 3; ++k)
         if (!(theta0[k] > 0) || !std::isfinite(theta0[k])) return GPR_EINVAL;
     if (steps_done) *steps_done = 0;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    int rc = check_device(ctx->device);
+    int rc = begin_call(ctx, s);
     if (rc) return rc;
-    if (!ctx->d_fit) {
-        if (hipMalloc(reinterpret_cast<void**>(&ctx->d_fit), 8 * sizeof(double)) != hipSuccess) {
-            (void)hipGetLastError();
-            return GPR_ENOMEM;
+    // device buffer: NLML and gradient of the current step (4 doubles), the
+    // Adam state, then the NLML trace (max_steps doubles)
+    const size_t st_off = 64, tr_off = 64 + ((sizeof(AdamState) + 63) / 64) * 64;
+    rc = ensure_device_bytes(&ctx->d_fit, &ctx->fit_cap, tr_off + (size_t)max_steps * sizeof(double));
+    if (rc) return rc;
+    double* fit = reinterpret_cast<double*>(ctx->d_fit);
+    AdamState* st = reinterpret_cast<AdamState*>(ctx->d_fit + st_off);
+    double* trace = reinterpret_cast<double*>(ctx->d_fit + tr_off);
+    const double* theta_dev =
+        reinterpret_cast<const double*>(ctx->d_fit + st_off + offsetof(AdamState, theta));
+    static_assert(offsetof(AdamState, stop) == offsetof(AdamState, t) + sizeof(int),
+                  "t and stop are read together");
+    NlmlRun R;
+    rc = nlml_prepare(ctx, n, tile, true, R, s);
+    if (rc) return rc;
+    // Adam on z = log theta, entirely on the device: each evaluation reads
+    // theta = exp(z) from the state, and the step kernel updates it; the host
+    // only reads the stop flag every few steps (the evaluations issued after
+    // a stop leave the state as it is)
+    HIP_TRY(launch_adam_init(st, std::log(theta0[0]), std::log(theta0[1]), std::log(theta0[2]), s));
+    const gpr_hyper h0{theta0[0], theta0[1], theta0[2]};  // unused: the kernels read theta
+    constexpr int CHECK_EVERY = 4;
+    int issued = 0, t = 0, stop = 0;
+    while (issued < max_steps) {
+        const int chunk = std::min(CHECK_EVERY, max_steps - issued);
+        for (int c = 0; c < chunk; ++c) {
+            rc = nlml_launch(ctx, R, X, y, n, D, h0, theta_dev, fit, fit + 1, nullptr, s);
+            if (rc) return rc;
+            HIP_TRY(launch_adam_step(st, fit, trace, max_steps, lr, beta1, beta2, eps, tol, s));
         }
+        issued += chunk;
+        int ts[2] = {0, 0};   // AdamState::t and ::stop are adjacent
+        HIP_TRY(hipMemcpyAsync(ts, ctx->d_fit + st_off + offsetof(AdamState, t), sizeof(ts),
+                               hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        t = ts[0];
+        stop = ts[1];
+        if (stop) break;
     }
-    // Adam on z = log theta: the NLML and its gradient come from the GPU
-    // (gpr_nlml_grad); the moments and the step are three scalars each, kept
-    // here between evaluations, since the next evaluation takes theta by value
-    double z[3], mom[3] = {0.0, 0.0, 0.0}, sec[3] = {0.0, 0.0, 0.0};
-    for (int k = 0; k < 3; ++k) z[k] = std::log(theta0[k]);
-    double prev = 0.0, b1t = 1.0, b2t = 1.0;
-    int t = 0;
-    while (t < max_steps) {
-        const double th[3] = {std::exp(z[0]), std::exp(z[1]), std::exp(z[2])};
-        const gpr_hyper h{th[0], th[1], th[2]};
-        rc = gpr_nlml_grad(ctx, X, y, n, D, h, tile, GPR_FP64, ctx->d_fit, ctx->d_fit + 1,
-                           nullptr, stream);
-        if (rc) return rc;
-        double out[4];
-        HIP_TRY(hipMemcpyAsync(out, ctx->d_fit, sizeof(out), hipMemcpyDeviceToHost, s));
-        rc = gpr_sync(ctx, stream, nullptr);
-        if (rc) return rc;   // GPR_ENOTPD: K(theta) lost positive definiteness
-        const double f = out[0];
-        if (!std::isfinite(f)) return GPR_ENOTPD;
-        if (nlml_trace) nlml_trace[t] = f;
-        ++t;
-        b1t *= beta1;
-        b2t *= beta2;
-        for (int k = 0; k < 3; ++k) {
-            const double gz = out[1 + k] * th[k];   // d/dlog(theta) = theta d/dtheta
-            mom[k] = beta1 * mom[k] + (1.0 - beta1) * gz;
-            sec[k] = beta2 * sec[k] + (1.0 - beta2) * gz * gz;
-            const double mh = mom[k] / (1.0 - b1t), sh = sec[k] / (1.0 - b2t);
-            z[k] -= lr * mh / (std::sqrt(sh) + eps);
-        }
-        if (t > 1 && tol > 0 && std::fabs(f - prev) <= tol * std::fabs(prev)) break;
-        prev = f;
-    }
-    for (int k = 0; k < 3; ++k) theta_out[k] = std::exp(z[k]);
+    double th[3];
+    HIP_TRY(hipMemcpyAsync(th, theta_dev, sizeof(th), hipMemcpyDeviceToHost, s));
+    if (nlml_trace && t > 0)
+        HIP_TRY(hipMemcpyAsync(nlml_trace, trace, (size_t)t * sizeof(double),
+                               hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    rc = end_call(ctx, s);
+    if (rc) return rc;
+    rc = gpr_sync(ctx, stream, nullptr);
     if (steps_done) *steps_done = t;
+    if (rc) return rc;   // GPR_ENOTPD: K(theta) lost positive definiteness
+    if (stop == 2) return GPR_ENOTPD;
+    for (int k = 0; k < 3; ++k) theta_out[k] = th[k];
     return GPR_OK;
 }
 

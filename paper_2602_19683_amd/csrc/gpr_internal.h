@@ -98,10 +98,12 @@ struct TGemmTask {
 // Entry (i, j) of the padded matrix: for i < na and j < nb,
 // v exp(-|a_i - b_j|^2 / (2 l)) plus s2 where diag_noise and i == j;
 // otherwise (padding) 1 where identity_pad and i == j, else 0.
+// hyp (nullable, device, 3 doubles): when given, (l, v, s2) are read from it
+// by the kernel instead (hyperparameters kept on the device).
 hipError_t launch_assemble(const TileMat& T, int tile_rows, const double* A, int64_t na,
                            const double* B, int64_t nb, int D, double l, double v,
                            double s2, bool diag_noise, bool identity_pad,
-                           hipStream_t s);
+                           hipStream_t s, const double* hyp = nullptr);
 
 // Dense row-major n x n (ld) -> lower tiles of T (padding: identity).
 hipError_t launch_dense_to_tiled(const double* A, int64_t n, int64_t lda, const TileMat& T,
@@ -184,7 +186,7 @@ hipError_t launch_lbar_init(const TileMat& W, const TileMat& L, int M, const dou
 // over the lower tiles of A; returns the number of partial triples written.
 int grad_reduce_parts(int M, int m);
 hipError_t launch_grad_reduce(const TileMat& A, int M, const double* X, int64_t n, int D,
-                              double l, double* parts, hipStream_t s);
+                              double l, double* parts, hipStream_t s, const double* hyp = nullptr);
 // Dense symmetric adjoint from the lower-convention Abar: out_ij = Abar_ii on the
 // diagonal, Abar_{max(i,j), min(i,j)} / 2 elsewhere (n x n, row-major).
 hipError_t launch_kbar_export(const TileMat& A, int64_t n, double* out, hipStream_t s);
@@ -193,7 +195,26 @@ hipError_t launch_kbar_export(const TileMat& A, int64_t n, double* out, hipStrea
 hipError_t launch_nlml_finish(const TileMat& L, const double* beta, int64_t n,
                               const double* parts, int nparts, double l, double v,
                               const int* info, double* out_nlml, double* out_grad3,
-                              hipStream_t s);
+                              hipStream_t s, const double* hyp = nullptr);
+
+// Adam on z = log theta kept on the device (the hyperparameter fit). theta =
+// exp(z) is what the next evaluation reads (as its `hyp` array).
+struct AdamState {
+    double z[3], m[3], s[3], theta[3];
+    double b1t, b2t, prev;
+    int t;     // steps taken
+    int stop;  // 0 running, 1 stopped (tolerance or step limit), 2 non-finite NLML
+};
+// state := start at z0 (moments zero, theta = exp(z0)).
+hipError_t launch_adam_init(AdamState* st, double z0, double z1, double z2, hipStream_t s);
+// One bias-corrected Adam step from fit = (nlml, d/dl, d/dv, d/dsigma^2) at
+// theta, unless the state has stopped: trace[t] = nlml, the moments and z
+// updated with the gradient in log theta (theta_k d/dtheta_k), theta =
+// exp(z); stops once |nlml - previous| <= tol |previous| (tol > 0, from the
+// second step on), at max_steps, or on a non-finite NLML (trace not written).
+hipError_t launch_adam_step(AdamState* st, const double* fit, double* trace, int max_steps,
+                            double lr, double beta1, double beta2, double eps, double tol,
+                            hipStream_t s);
 
 // var_i = v - sum_j V^T_ij^2 over the M tiles of test-tile row i / m of V
 // (layout 1), i < n_test; and out_i = S_ii for the lower-tiled S, i < n.

@@ -76,8 +76,10 @@ int grad_reduce_parts(int M, int m)
 // columns are staged in LDS GR_DC dimensions at a time.
 __global__ __launch_bounds__(256) void k_grad_reduce(TileMat A, int M, const double* __restrict__ X,
                                                      int64_t n, int D, double l,
-                                                     double* __restrict__ parts)
+                                                     double* __restrict__ parts,
+                                                     const double* __restrict__ hyp)
 {
+    if (hyp) l = hyp[0];  // lengthscale held on the device
     __shared__ double Xr[GR_B][GR_DC + 1];
     __shared__ double Xc[GR_B][GR_DC + 1];
     __shared__ double red[3][256];
@@ -142,10 +144,10 @@ __global__ __launch_bounds__(256) void k_grad_reduce(TileMat A, int M, const dou
 }
 
 hipError_t launch_grad_reduce(const TileMat& A, int M, const double* X, int64_t n, int D,
-                              double l, double* parts, hipStream_t s)
+                              double l, double* parts, hipStream_t s, const double* hyp)
 {
     hipLaunchKernelGGL(k_grad_reduce, dim3(grad_reduce_parts(M, A.m)), dim3(256), 0, s, A, M, X, n,
-                       D, l, parts);
+                       D, l, parts, hyp);
     return hipGetLastError();
 }
 
@@ -175,8 +177,13 @@ __global__ __launch_bounds__(256) void k_nlml_finish(TileMat L, const double* __
                                                      int nparts, double l, double v,
                                                      const int* __restrict__ info,
                                                      double* __restrict__ out_nlml,
-                                                     double* __restrict__ out_grad3)
+                                                     double* __restrict__ out_grad3,
+                                                     const double* __restrict__ hyp)
 {
+    if (hyp) {  // hyperparameters held on the device
+        l = hyp[0];
+        v = hyp[1];
+    }
     __shared__ double red[5][256];
     const int tid = threadIdx.x;
     const int m = L.m;
@@ -217,10 +224,70 @@ __global__ __launch_bounds__(256) void k_nlml_finish(TileMat L, const double* __
 
 hipError_t launch_nlml_finish(const TileMat& L, const double* beta, int64_t n, const double* parts,
                               int nparts, double l, double v, const int* info, double* out_nlml,
-                              double* out_grad3, hipStream_t s)
+                              double* out_grad3, hipStream_t s, const double* hyp)
 {
     hipLaunchKernelGGL(k_nlml_finish, dim3(1), dim3(256), 0, s, L, beta, n, parts, nparts, l, v,
-                       info, out_nlml, out_grad3);
+                       info, out_nlml, out_grad3, hyp);
+    return hipGetLastError();
+}
+
+// Adam on log theta, one thread: the state lives in device memory between
+// the evaluations, so the fit needs no host round trip per step.
+__global__ void k_adam_init(AdamState* st, double z0, double z1, double z2)
+{
+    const double z[3] = {z0, z1, z2};
+    for (int k = 0; k < 3; ++k) {
+        st->z[k] = z[k];
+        st->m[k] = 0.0;
+        st->s[k] = 0.0;
+        st->theta[k] = exp(z[k]);
+    }
+    st->b1t = 1.0;
+    st->b2t = 1.0;
+    st->prev = 0.0;
+    st->t = 0;
+    st->stop = 0;
+}
+
+__global__ void k_adam_step(AdamState* st, const double* __restrict__ fit,
+                            double* __restrict__ trace, int max_steps, double lr, double beta1,
+                            double beta2, double eps, double tol)
+{
+    if (st->stop) return;
+    const double f = fit[0];
+    if (!isfinite(f)) {
+        st->stop = 2;
+        return;
+    }
+    if (trace) trace[st->t] = f;
+    const int t = ++st->t;
+    st->b1t *= beta1;
+    st->b2t *= beta2;
+    for (int k = 0; k < 3; ++k) {
+        const double gz = fit[1 + k] * st->theta[k];   // d/dlog(theta) = theta d/dtheta
+        st->m[k] = beta1 * st->m[k] + (1.0 - beta1) * gz;
+        st->s[k] = beta2 * st->s[k] + (1.0 - beta2) * gz * gz;
+        const double mh = st->m[k] / (1.0 - st->b1t), sh = st->s[k] / (1.0 - st->b2t);
+        st->z[k] -= lr * mh / (sqrt(sh) + eps);
+        st->theta[k] = exp(st->z[k]);
+    }
+    if ((t > 1 && tol > 0 && fabs(f - st->prev) <= tol * fabs(st->prev)) || t >= max_steps)
+        st->stop = 1;
+    st->prev = f;
+}
+
+hipError_t launch_adam_init(AdamState* st, double z0, double z1, double z2, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_adam_init, dim3(1), dim3(1), 0, s, st, z0, z1, z2);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam_step(AdamState* st, const double* fit, double* trace, int max_steps,
+                            double lr, double beta1, double beta2, double eps, double tol,
+                            hipStream_t s)
+{
+    hipLaunchKernelGGL(k_adam_step, dim3(1), dim3(1), 0, s, st, fit, trace, max_steps, lr, beta1,
+                       beta2, eps, tol);
     return hipGetLastError();
 }
 

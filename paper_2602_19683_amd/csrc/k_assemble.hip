@@ -37,8 +37,13 @@ __global__ __launch_bounds__(256) void k_assemble(TileMat T, int tile_rows, int6
                                                   const double* __restrict__ A, int64_t na,
                                                   const double* __restrict__ B, int64_t nb, int D,
                                                   double l, double v, double s2, int diag_noise,
-                                                  int identity_pad)
+                                                  int identity_pad, const double* __restrict__ hyp)
 {
+    if (hyp) {  // hyperparameters held on the device (l, v, sigma^2)
+        l = hyp[0];
+        v = hyp[1];
+        s2 = hyp[2];
+    }
     __shared__ double Sa[SB][MAXD + 1];
     __shared__ double Sb[MAXD][SB + 1];
     const int m = T.m;
@@ -115,8 +120,13 @@ __global__ __launch_bounds__(256) void k_assemble_w(TileMat T, int64_t ntiles,
                                                     const double* __restrict__ A, int64_t na,
                                                     const double* __restrict__ B, int64_t nb,
                                                     double l, double v, double s2, int diag_noise,
-                                                    int identity_pad)
+                                                    int identity_pad, const double* __restrict__ hyp)
 {
+    if (hyp) {  // hyperparameters held on the device (l, v, sigma^2)
+        l = hyp[0];
+        v = hyp[1];
+        s2 = hyp[2];
+    }
     const int m = T.m;
     const int bt = m / 64;                     // 64 x 64 blocks per tile side
     const int64_t per_tile = (int64_t)bt * bt;
@@ -161,7 +171,7 @@ __global__ __launch_bounds__(256) void k_assemble_w(TileMat T, int64_t ntiles,
 
 hipError_t launch_assemble(const TileMat& T, int tile_rows, const double* A, int64_t na,
                            const double* B, int64_t nb, int D, double l, double v, double s2,
-                           bool diag_noise, bool identity_pad, hipStream_t s)
+                           bool diag_noise, bool identity_pad, hipStream_t s, const double* hyp)
 {
     const int64_t ntiles = T.layout == 0 ? (int64_t)tile_rows * (tile_rows + 1) / 2
                                          : (int64_t)tile_rows * T.ncolt;
@@ -174,7 +184,7 @@ hipError_t launch_assemble(const TileMat& T, int tile_rows, const double* A, int
         const int64_t g = items < 65536 ? items : 65536;
 #define GPR_ASMW(DT)                                                                             \
     hipLaunchKernelGGL(k_assemble_w<DT>, dim3((unsigned)g), dim3(256), 0, s, T, ntiles, A, na, B, \
-                       nb, l, v, s2, dn, ip)
+                       nb, l, v, s2, dn, ip, hyp)
         switch (D) {
         case 1: GPR_ASMW(1); break;
         case 2: GPR_ASMW(2); break;
@@ -190,7 +200,7 @@ hipError_t launch_assemble(const TileMat& T, int tile_rows, const double* A, int
     }
 #define GPR_ASM(DT)                                                                              \
     hipLaunchKernelGGL(k_assemble<DT>, dim3((unsigned)grid), dim3(256), 0, s, T, tile_rows,     \
-                       ntiles, A, na, B, nb, D, l, v, s2, dn, ip)
+                       ntiles, A, na, B, nb, D, l, v, s2, dn, ip, hyp)
     switch (D) {
     case 1: GPR_ASM(1); break;
     case 2: GPR_ASM(2); break;
