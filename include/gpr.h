@@ -131,7 +131,13 @@ enum { GPR_STATE_EMPTY = 0, GPR_STATE_K = 1, GPR_STATE_L = 2 };
  * the panel work shares the caller's stream.
  * Returns GPR_ENODEV if the device does not exist, GPR_ENOTSUP for an
  * executor this build lacks. On success *out must later go to
- * gpr_ctx_destroy. */
+ * gpr_ctx_destroy.
+ * Device-memory cap: if the environment variable GPR_MAX_DEVICE_BYTES holds a
+ * positive integer when the context is created, the device memory held by
+ * the context's workspace and by the handles it creates may not exceed that
+ * many bytes in total; a call whose allocation would exceed it returns
+ * GPR_ENOMEM (as does a failed allocation). Handles keep counting against
+ * the cap after the context is destroyed, until they are freed. */
 int gpr_ctx_create(gpr_ctx** out, int device, int n_streams, gpr_executor ex);
 
 /* Waits for all work of the context, frees its workspace and the context. */

@@ -14,10 +14,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstddef>
 #include <cstdlib>
 #include <cstring>
+#include <memory>
 #include <new>
 #include <vector>
 
@@ -25,8 +27,19 @@
 
 using namespace gpr;
 
+// Device bytes held by a context's workspace and by the handles it created,
+// against the cap read from the environment variable GPR_MAX_DEVICE_BYTES
+// when the context was created (none if unset or 0). Handles keep the
+// counter alive after their context is destroyed.
+struct DevBudget {
+    std::atomic<uint64_t> used{0};
+    uint64_t cap = UINT64_MAX;
+};
+using Budget = std::shared_ptr<DevBudget>;
+
 struct gpr_ctx {
     int device = 0;
+    Budget budget;                // device bytes held and their cap
     int n_streams = 3;            // 1: every launch on the caller's stream
     hipStream_t panel = nullptr;  // panel TRSMs and next-column GEMMs
     hipStream_t bulk = nullptr;   // trailing updates
@@ -74,6 +87,8 @@ struct gpr_ctx {
 
 struct gpr_tiled {
     int device = 0;
+    Budget budget;                // the creating context's counter
+    size_t dev_bytes = 0;         // device bytes this handle holds
     int64_t n = 0;
     int m = 0;
     int M = 0;
@@ -111,20 +126,53 @@ bool valid_hyper(const gpr_hyper& h)
            std::isfinite(h.noise_variance) && h.lengthscale > 0 && h.vertical_variance > 0;
 }
 
-int ensure_device_bytes(char** p, size_t* cap, size_t need)
+// hipMalloc counted against the budget: GPR_ENOMEM if it would exceed the
+// cap or the allocation fails.
+int budget_malloc(const Budget& b, void** p, size_t bytes)
+{
+    *p = nullptr;
+    if (b) {
+        uint64_t cur = b->used.load();
+        do {
+            if (bytes > b->cap || cur > b->cap - bytes) return GPR_ENOMEM;
+        } while (!b->used.compare_exchange_weak(cur, cur + bytes));
+    }
+    if (hipMalloc(p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        if (b) b->used -= bytes;
+        return GPR_ENOMEM;
+    }
+    return GPR_OK;
+}
+
+void budget_free(const Budget& b, void* p, size_t bytes)
+{
+    if (!p) return;
+    (void)hipFree(p);
+    if (b) b->used -= bytes;
+}
+
+// Device memory of a handle, counted against its context's budget.
+int handle_malloc(gpr_tiled* T, void** p, size_t bytes)
+{
+    const int rc = budget_malloc(T->budget, p, bytes);
+    if (rc == GPR_OK) T->dev_bytes += bytes;
+    return rc;
+}
+
+int ensure_device_bytes(const Budget& b, char** p, size_t* cap, size_t need)
 {
     if (need <= *cap) return GPR_OK;
     if (*p) {
         if (hipDeviceSynchronize() != hipSuccess) return GPR_EHIP;
-        (void)hipFree(*p);
+        budget_free(b, *p, *cap);
         *p = nullptr;
         *cap = 0;
     }
     size_t want = need + need / 4;
-    if (hipMalloc(reinterpret_cast<void**>(p), want) != hipSuccess) {
-        (void)hipGetLastError();
-        return GPR_ENOMEM;
-    }
+    const int rc = budget_malloc(b, reinterpret_cast<void**>(p), want);
+    if (rc) return rc;
     *cap = want;
     return GPR_OK;
 }
@@ -153,7 +201,7 @@ struct DescBuffer {
                 return GPR_ENOMEM;
             ctx->hdesc_cap = bytes * 2;
         }
-        int rc = ensure_device_bytes(&ctx->d_desc, &ctx->desc_cap, bytes);
+        int rc = ensure_device_bytes(ctx->budget, &ctx->d_desc, &ctx->desc_cap, bytes);
         if (rc) return rc;
         std::memcpy(ctx->h_desc, host.data(), bytes);
         HIP_TRY(hipMemcpyAsync(ctx->d_desc, ctx->h_desc, bytes, hipMemcpyHostToDevice, s));
@@ -329,7 +377,7 @@ int run_persist(gpr_ctx* ctx, const SweepMats& X, int mode, hipStream_t s)
         const size_t bytes = order.size() * sizeof(PItem);
         // the previous order may still be read by a running sweep
         HIP_TRY(hipStreamSynchronize(s));
-        int rc = ensure_device_bytes(&ctx->d_pitems, &ctx->pitems_cap, bytes > 0 ? bytes : 64);
+        int rc = ensure_device_bytes(ctx->budget, &ctx->d_pitems, &ctx->pitems_cap, bytes > 0 ? bytes : 64);
         if (rc) return rc;
         if (bytes) HIP_TRY(hipMemcpy(ctx->d_pitems, order.data(), bytes, hipMemcpyHostToDevice));
         std::copy(key, key + 6, ctx->pkey);
@@ -337,7 +385,7 @@ int run_persist(gpr_ctx* ctx, const SweepMats& X, int mode, hipStream_t s)
     }
     const PGeom g = persist_geom(M, Mhat, mode, m, bm);
     const int64_t ncnt = (int64_t)g.T * (g.T + 1) / 2;
-    int rc = ensure_device_bytes(&ctx->d_pcnt, &ctx->pcnt_cap, (size_t)(ncnt + 1) * sizeof(unsigned));
+    int rc = ensure_device_bytes(ctx->budget, &ctx->d_pcnt, &ctx->pcnt_cap, (size_t)(ncnt + 1) * sizeof(unsigned));
     if (rc) return rc;
     // flops of the tile tasks (Fig. 1 counts: POTRF m^3/3, TRSM m^3, SYRK m^3,
     // GEMM 2 m^3)
@@ -434,11 +482,12 @@ int alloc_tiled(gpr_ctx* ctx, int64_t n, int m, gpr_tiled** out)
     T->n = n;
     T->m = m;
     T->M = (int)((n + m - 1) / m);
+    T->budget = ctx->budget;
     const size_t tiles = (size_t)T->M * (T->M + 1) / 2;
-    if (hipMalloc(reinterpret_cast<void**>(&T->data), tiles * m * m * sizeof(double)) != hipSuccess) {
-        (void)hipGetLastError();
+    const int rc = handle_malloc(T, reinterpret_cast<void**>(&T->data), tiles * m * m * sizeof(double));
+    if (rc) {
         delete T;
-        return GPR_ENOMEM;
+        return rc;
     }
     *out = T;
     return GPR_OK;
@@ -456,10 +505,8 @@ size_t tiled_bytes(const gpr_tiled* T)
 int save_kcopy(gpr_tiled* K, hipStream_t s)
 {
     if (!K->kcopy) {
-        if (hipMalloc(reinterpret_cast<void**>(&K->kcopy), tiled_bytes(K)) != hipSuccess) {
-            (void)hipGetLastError();
-            return GPR_ENOMEM;
-        }
+        const int rc = handle_malloc(K, reinterpret_cast<void**>(&K->kcopy), tiled_bytes(K));
+        if (rc) return rc;
     }
     HIP_TRY(hipMemcpyAsync(K->kcopy, K->data, tiled_bytes(K), hipMemcpyDeviceToDevice, s));
     return GPR_OK;
@@ -488,11 +535,14 @@ int build_tinv_pairs(gpr_ctx* ctx, gpr_tiled* L, hipStream_t s)
         // the W_p / scratch tiles, and the two launches' descriptors, which
         // depend only on this handle's buffers: written once, kept with the
         // handle (the context's descriptor buffer may hold a pending plan)
-        if (hipMalloc(reinterpret_cast<void**>(&L->tpair), 2 * (size_t)P * mm * sizeof(double)) !=
-                hipSuccess ||
-            hipMalloc(reinterpret_cast<void**>(&L->tpair_desc), 2 * (ts + us)) != hipSuccess ||
-            hipHostMalloc(reinterpret_cast<void**>(&L->tpair_host), 2 * (ts + us)) != hipSuccess) {
+        int rc = handle_malloc(L, reinterpret_cast<void**>(&L->tpair),
+                               2 * (size_t)P * mm * sizeof(double));
+        if (rc == GPR_OK)
+            rc = handle_malloc(L, reinterpret_cast<void**>(&L->tpair_desc), 2 * (ts + us));
+        if (rc) return rc;
+        if (hipHostMalloc(reinterpret_cast<void**>(&L->tpair_host), 2 * (ts + us)) != hipSuccess) {
             (void)hipGetLastError();
+            L->tpair_host = nullptr;
             return GPR_ENOMEM;
         }
         double* W = L->tpair;
@@ -702,6 +752,11 @@ int gpr_ctx_create(gpr_ctx** out, int device, int n_streams, gpr_executor ex)
     gpr_ctx* c = new (std::nothrow) gpr_ctx;
     if (!c) return GPR_ENOMEM;
     c->device = device;
+    c->budget = std::make_shared<DevBudget>();
+    if (const char* cap = std::getenv("GPR_MAX_DEVICE_BYTES")) {
+        const unsigned long long v = std::strtoull(cap, nullptr, 10);
+        if (v > 0) c->budget->cap = v;
+    }
     c->executor = ex;
     c->n_streams = n_streams >= 3 ? 3 : n_streams;
     bool ok = hipStreamCreateWithFlags(&c->bulk, hipStreamNonBlocking) == hipSuccess &&
@@ -731,8 +786,8 @@ int gpr_ctx_destroy(gpr_ctx* c)
     (void)hipDeviceSynchronize();
     if (c->scratch) gpr_tiled_free(c->scratch);
     if (c->nlml_K) gpr_tiled_free(c->nlml_K);
-    if (c->d_fit) (void)hipFree(c->d_fit);
-    if (c->d_adj) (void)hipFree(c->d_adj);
+    budget_free(c->budget, c->d_fit, c->fit_cap);
+    budget_free(c->budget, c->d_adj, c->adj_cap);
     for (auto e : c->evpool) (void)hipEventDestroy(e);
     for (auto e : c->tpool) (void)hipEventDestroy(e);
     if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
@@ -743,11 +798,11 @@ int gpr_ctx_destroy(gpr_ctx* c)
     if (c->panel) (void)hipStreamDestroy(c->panel);
     if (c->d_info) (void)hipFree(c->d_info);
     if (c->d_flags) (void)hipFree(c->d_flags);
-    if (c->d_desc) (void)hipFree(c->d_desc);
+    budget_free(c->budget, c->d_desc, c->desc_cap);
     if (c->h_desc) (void)hipHostFree(c->h_desc);
-    if (c->d_ws) (void)hipFree(c->d_ws);
-    if (c->d_pitems) (void)hipFree(c->d_pitems);
-    if (c->d_pcnt) (void)hipFree(c->d_pcnt);
+    budget_free(c->budget, c->d_ws, c->ws_cap);
+    budget_free(c->budget, c->d_pitems, c->pitems_cap);
+    budget_free(c->budget, c->d_pcnt, c->pcnt_cap);
     delete c;
     return GPR_OK;
 }
@@ -796,11 +851,9 @@ int gpr_cholesky(gpr_ctx* ctx, gpr_tiled* K, gpr_precision prec, int32_t* info_d
         if (rc) return rc;
     }
     if (!K->tinv) {
-        if (hipMalloc(reinterpret_cast<void**>(&K->tinv), (size_t)M * m * m * sizeof(double)) !=
-            hipSuccess) {
-            (void)hipGetLastError();
-            return GPR_ENOMEM;
-        }
+        const int arc = handle_malloc(K, reinterpret_cast<void**>(&K->tinv),
+                                      (size_t)M * m * m * sizeof(double));
+        if (arc) return arc;
     }
     SweepMats X{kmat(K), K->tinv, TileMat{nullptr, m, 1, M}, TileMat{nullptr, m, 0, 0}, M, 0, m,
                 (int)prec};
@@ -887,15 +940,13 @@ int predict_impl(gpr_ctx* ctx, gpr_tiled* L, const double* X, const double* y, i
     const int fprec = fused ? prec : L->prec;
     // partial products of the refinement's K x (mixed precision only)
     const size_t sv_bytes = fprec != GPR_FP64 ? symv_work_doubles(M, m) * sizeof(double) : 0;
-    int rc = ensure_device_bytes(&ctx->d_ws, &ctx->ws_cap,
+    int rc = ensure_device_bytes(ctx->budget, &ctx->d_ws, &ctx->ws_cap,
                                  vec_bytes + v_bytes + s_bytes + mv_bytes + sv_bytes);
     if (rc) return rc;
     if (fused && !L->tinv) {
-        if (hipMalloc(reinterpret_cast<void**>(&L->tinv), (size_t)M * m * m * sizeof(double)) !=
-            hipSuccess) {
-            (void)hipGetLastError();
-            return GPR_ENOMEM;
-        }
+        const int arc = handle_malloc(L, reinterpret_cast<void**>(&L->tinv),
+                                      (size_t)M * m * m * sizeof(double));
+        if (arc) return arc;
     }
     double* r = reinterpret_cast<double*>(ctx->d_ws);
     double* beta = r + npad;
@@ -1109,17 +1160,15 @@ int nlml_prepare(gpr_ctx* ctx, int64_t n, int32_t tile, bool grad, NlmlRun& R, h
     }
     const int m = K->m, M = K->M;
     if (!K->tinv) {
-        if (hipMalloc(reinterpret_cast<void**>(&K->tinv), (size_t)M * m * m * sizeof(double)) !=
-            hipSuccess) {
-            (void)hipGetLastError();
-            return GPR_ENOMEM;
-        }
+        const int arc = handle_malloc(K, reinterpret_cast<void**>(&K->tinv),
+                                      (size_t)M * m * m * sizeof(double));
+        if (arc) return arc;
     }
     R.K = K;
     R.grad = grad;
     const size_t npad = (size_t)M * m;
     R.nparts = grad ? grad_reduce_parts(M, m) : 0;
-    int rc = ensure_device_bytes(&ctx->d_ws, &ctx->ws_cap,
+    int rc = ensure_device_bytes(ctx->budget, &ctx->d_ws, &ctx->ws_cap,
                                  (4 * npad + 3 * (size_t)(R.nparts + 1)) * sizeof(double) + 256);
     if (rc) return rc;
     R.r = reinterpret_cast<double*>(ctx->d_ws);
@@ -1134,7 +1183,7 @@ int nlml_prepare(gpr_ctx* ctx, int64_t n, int32_t tile, bool grad, NlmlRun& R, h
         R.AP = build_adjoint(M, ADJ_CHUNK);
         const size_t tb = tiled_bytes(K);
         const size_t m2b = (size_t)m * m * sizeof(double);
-        rc = ensure_device_bytes(&ctx->d_adj, &ctx->adj_cap,
+        rc = ensure_device_bytes(ctx->budget, &ctx->d_adj, &ctx->adj_cap,
                                  2 * tb + (size_t)(R.AP.max_part + 3) * m2b);
         if (rc) return rc;
         double* base = reinterpret_cast<double*>(ctx->d_adj);
@@ -1280,7 +1329,7 @@ int gpr_solve(gpr_ctx* ctx, gpr_tiled* L, const double* b, double* x, void* stre
     int rc = begin_call(ctx, s);
     if (rc) return rc;
     const size_t npad = (size_t)L->M * L->m;
-    rc = ensure_device_bytes(&ctx->d_ws, &ctx->ws_cap, 4 * npad * sizeof(double) + 256);
+    rc = ensure_device_bytes(ctx->budget, &ctx->d_ws, &ctx->ws_cap, 4 * npad * sizeof(double) + 256);
     if (rc) return rc;
     double* r = reinterpret_cast<double*>(ctx->d_ws);
     double* beta = r + npad;
@@ -1370,6 +1419,7 @@ int gpr_tiled_free(gpr_tiled* T)
     if (T->kcopy) (void)hipFree(T->kcopy);
     if (T->tpair) (void)hipFree(T->tpair);
     if (T->tpair_desc) (void)hipFree(T->tpair_desc);
+    if (T->budget) T->budget->used -= T->dev_bytes;
     if (T->tpair_host) (void)hipHostFree(T->tpair_host);
     delete T;
     return GPR_OK;
@@ -1393,7 +1443,7 @@ int gpr_fit_hyper(gpr_ctx* ctx, const double* X, const double* y, int64_t n, int
     // device buffer: NLML and gradient of the current step (4 doubles), the
     // Adam state, then the NLML trace (max_steps doubles)
     const size_t st_off = 64, tr_off = 64 + ((sizeof(AdamState) + 63) / 64) * 64;
-    rc = ensure_device_bytes(&ctx->d_fit, &ctx->fit_cap, tr_off + (size_t)max_steps * sizeof(double));
+    rc = ensure_device_bytes(ctx->budget, &ctx->d_fit, &ctx->fit_cap, tr_off + (size_t)max_steps * sizeof(double));
     if (rc) return rc;
     double* fit = reinterpret_cast<double*>(ctx->d_fit);
     AdamState* st = reinterpret_cast<AdamState*>(ctx->d_fit + st_off);
