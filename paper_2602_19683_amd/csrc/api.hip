@@ -37,6 +37,12 @@ struct DevBudget {
 };
 using Budget = std::shared_ptr<DevBudget>;
 
+// Device flag words of a context: [0, 64) the POTRF row-panel flags (two per
+// 32-row panel of a tile of up to 1024 rows), SIGNAL_FLAG the flag stored
+// after an update launch that a fused POTRF + TRSM launch waits for.
+constexpr int SIGNAL_FLAG = 64;
+constexpr int FLAG_WORDS = 128;
+
 struct gpr_ctx {
     int device = 0;
     Budget budget;                // device bytes held and their cap
@@ -50,6 +56,7 @@ struct gpr_ctx {
                                   // [2]: a device-side wait hit its limit
     unsigned* d_flags = nullptr;  // POTRF row-panel flags
     unsigned epoch = 0;
+    unsigned sigseq = 0;          // values stored by launch_signal (d_flags[SIGNAL_FLAG])
     char* d_desc = nullptr;
     size_t desc_cap = 0;
     char* h_desc = nullptr;       // pinned staging
@@ -426,6 +433,30 @@ int run_sweep(gpr_ctx* ctx, const SweepMats& X, const SweepPlan& P, const DescBu
     for (const auto& L : Ls)
         for (int k = 0; k < L.nwait; ++k)
             if (phys[Ls[L.wait[k]].stream] != phys[L.stream]) waited[L.wait[k]] = 1;
+    // A POTRF followed on its stream by the one-tile TRSM of the next tile row
+    // (the critical TRSM) runs as one launch, the TRSM strips following the
+    // POTRF's row panels. The TRSM's wait for an update on another stream
+    // becomes a device flag: that update launch is followed by a signal.
+    std::vector<char> fused(Ls.size(), 0);      // TRSM launch run inside the POTRF before it
+    std::vector<unsigned> signal(Ls.size(), 0); // value to signal after this launch (0: none)
+    std::vector<unsigned> ready(Ls.size(), 0);  // POTRF launch: value its TRSM strips wait for
+    for (size_t li = 0; li + 1 < Ls.size(); ++li) {
+        const SchedLaunch &Lp = Ls[li], &Lt = Ls[li + 1];
+        if (Lp.kind != LK_POTRF || Lt.kind != LK_TRSM || Lt.count != 1 || Lp.stream != Lt.stream)
+            continue;
+        int cross = -1, ncross = 0;
+        for (int k = 0; k < Lt.nwait; ++k)
+            if (phys[Ls[Lt.wait[k]].stream] != phys[Lt.stream]) {
+                cross = Lt.wait[k];
+                ++ncross;
+            }
+        if (ncross > 1) continue;
+        fused[li + 1] = 1;
+        if (cross >= 0) {
+            if (!signal[cross]) signal[cross] = ++ctx->sigseq;
+            ready[li] = signal[cross];
+        }
+    }
     HIP_TRY(hipEventRecord(ctx->ev_fork, s));
     for (int q = 1; q < 3; ++q) {
         if (phys[q] == s || (q == 2 && phys[2] == phys[1])) continue;
@@ -435,9 +466,14 @@ int run_sweep(gpr_ctx* ctx, const SweepMats& X, const SweepPlan& P, const DescBu
     // after a failed pivot the rest of a factorising sweep is skipped (the
     // record was reset before this sweep; a sweep with a given factor has none)
     const int* abort_info = sweep_factors(P.mode) ? ctx->d_info : nullptr;
+    unsigned* sigflag = ctx->d_flags + SIGNAL_FLAG;
     for (size_t li = 0; li < Ls.size(); ++li) {
         const SchedLaunch& L = Ls[li];
         hipStream_t st = phys[L.stream];
+        if (fused[li]) {  // issued with the POTRF before it
+            if (waited[li]) HIP_TRY(hipEventRecord(ctx->evpool[li], st));
+            continue;
+        }
         for (int k = 0; k < L.nwait; ++k)
             if (phys[Ls[L.wait[k]].stream] != st)
                 HIP_TRY(hipStreamWaitEvent(st, ctx->evpool[L.wait[k]], 0));
@@ -446,9 +482,17 @@ int run_sweep(gpr_ctx* ctx, const SweepMats& X, const SweepPlan& P, const DescBu
             const int J = L.step;
             double* A = X.at(J, J);
             double* Ti = X.tinv + (size_t)J * m * m;
-            ProfScope ps(ctx, st, PK_POTRF, m3 / 3.0, 0.0);
-            HIP_TRY(launch_potrf_f64(A, m, m, Ti, m, ctx->d_info, (int64_t)J * m, ctx->d_flags,
-                                     ++ctx->epoch, ctx->d_info + 2, st));
+            if (li + 1 < Ls.size() && fused[li + 1]) {
+                ProfScope ps(ctx, st, PK_POTRF, m3 / 3.0 + m3, 0.0);
+                HIP_TRY(launch_potrf_trsm_f64(A, m, m, Ti, m, ctx->d_info, (int64_t)J * m,
+                                              ctx->d_flags, ++ctx->epoch, ctx->d_info + 2,
+                                              db.dev<TrsmTask>(ctx, P.off[li + 1]),
+                                              ready[li] ? sigflag : nullptr, ready[li], st));
+            } else {
+                ProfScope ps(ctx, st, PK_POTRF, m3 / 3.0, 0.0);
+                HIP_TRY(launch_potrf_f64(A, m, m, Ti, m, ctx->d_info, (int64_t)J * m,
+                                         ctx->d_flags, ++ctx->epoch, ctx->d_info + 2, st));
+            }
         } else if (L.kind == LK_TRSM) {
             ProfScope ps(ctx, st, PK_TRSM, L.count * m3, 0.0);
             HIP_TRY(launch_trsm_f64(db.dev<TrsmTask>(ctx, P.off[li]), L.count, m, abort_info, st));
@@ -464,6 +508,7 @@ int run_sweep(gpr_ctx* ctx, const SweepMats& X, const SweepPlan& P, const DescBu
                 HIP_TRY(launch_update_mixed(db.dev<UpdateTask>(ctx, P.off[li]), L.count, m,
                                             X.prec, abort_info, st));
         }
+        if (signal[li]) HIP_TRY(launch_signal(sigflag, signal[li], st));
         if (waited[li]) HIP_TRY(hipEventRecord(ctx->evpool[li], st));
     }
     for (int q = 1; q < 3; ++q) {
@@ -767,8 +812,8 @@ int gpr_ctx_create(gpr_ctx** out, int device, int n_streams, gpr_executor ex)
               hipEventCreateWithFlags(&c->ev_desc, hipEventDisableTiming) == hipSuccess &&
               hipMalloc(reinterpret_cast<void**>(&c->d_info), 4 * sizeof(int)) == hipSuccess &&
               hipMemset(c->d_info, 0, 4 * sizeof(int)) == hipSuccess &&
-              hipMalloc(reinterpret_cast<void**>(&c->d_flags), 64 * sizeof(unsigned)) == hipSuccess &&
-              hipMemset(c->d_flags, 0, 64 * sizeof(unsigned)) == hipSuccess &&
+              hipMalloc(reinterpret_cast<void**>(&c->d_flags), FLAG_WORDS * sizeof(unsigned)) == hipSuccess &&
+              hipMemset(c->d_flags, 0, FLAG_WORDS * sizeof(unsigned)) == hipSuccess &&
               hipDeviceSynchronize() == hipSuccess;
     if (!ok) {
         gpr_ctx_destroy(c);

@@ -129,6 +129,17 @@ hipError_t launch_trsm_f64(const TrsmTask* d_tasks, int ntask, int m, const int*
 hipError_t launch_potrf_f64(double* A, int lda, int m, double* Tinv, int ldt, int* info,
                             int64_t col_base, unsigned* flags, unsigned epoch, int* err,
                             hipStream_t s);
+// POTRF of one diagonal tile and the TRSM task *trsm (the tile below it) in
+// one launch, the TRSM strips following the POTRF row panels (2 m/32
+// workgroups). ready (nullable): the strips first wait until *ready ==
+// ready_val (stored by launch_signal after the tile's last update on another
+// stream).
+hipError_t launch_potrf_trsm_f64(double* A, int lda, int m, double* Tinv, int ldt, int* info,
+                                 int64_t col_base, unsigned* flags, unsigned epoch, int* err,
+                                 const TrsmTask* trsm, const unsigned* ready, unsigned ready_val,
+                                 hipStream_t s);
+// *flag = v (release, device scope) once the launches before it on s are done.
+hipError_t launch_signal(unsigned* flag, unsigned v, hipStream_t s);
 // Inverses of the M factored diagonal tiles (J, J) of the lower-tiled K;
 // the inverse of tile J goes to Tinv + J m^2 (leading dimension m), whose
 // 32 x 32 diagonal blocks must already hold the block inverses.

@@ -28,6 +28,7 @@
 #include "k_accum.h"
 #include "k_common.h"
 #include "k_potrf_dev.h"
+#include "k_trsm_dev.h"
 
 namespace gpr {
 
@@ -47,6 +48,54 @@ __global__ __launch_bounds__(256) void k_potrf_f64(double* __restrict__ A, int l
     __shared__ PotrfLds sh;
     potrf_panel(A, lda, m, Tinv, ldt, info, col_base, flags, epoch, err, blockIdx.x, sh,
                 threadIdx.x);
+}
+
+// POTRF of the diagonal tile (J, J) and the TRSM of the tile below it,
+// (J + 1, J), in one launch: workgroups 0 .. P-1 are the POTRF row panels
+// as above, workgroups P .. 2P-1 the TRSM's 32-row strips. A strip takes
+// column block p as soon as row panel p of the factor is final (the panel's
+// second flag), so the TRSM runs beside the factorisation instead of after
+// it; the strips only wait for lower-numbered workgroups. The TRSM also needs
+// the last update of its own tile, done by a launch on another stream: that
+// launch is followed by a one-thread kernel that stores `ready_val` to
+// *ready (release), and the strips acquire it before they start (ready may be
+// null when the update is ordered by the stream itself).
+__global__ __launch_bounds__(256) void k_potrf_trsm_f64(
+    double* __restrict__ A, int lda, int m, double* __restrict__ Tinv, int ldt,
+    int* __restrict__ info, int64_t col_base, unsigned* __restrict__ flags, unsigned epoch,
+    int* __restrict__ err, const TrsmTask* __restrict__ trsm, const unsigned* __restrict__ ready,
+    unsigned ready_val)
+{
+    if (info != nullptr) {
+        const int f = *info;
+        if (f > 0 && f <= col_base) return;
+    }
+    __shared__ union {
+        PotrfLds potrf;
+        TrsmLds trsm;
+    } sh;
+    const int P = m / NB;
+    const int tid = threadIdx.x;
+    if ((int)blockIdx.x < P) {
+        potrf_panel(A, lda, m, Tinv, ldt, info, col_base, flags, epoch, err, blockIdx.x, sh.potrf,
+                    tid);
+        return;
+    }
+    if (ready != nullptr) {
+        if (tid == 0 && !wait_flag(ready, ready_val, err)) flag_error(err);
+        __syncthreads();
+    }
+    const unsigned* diag_done = flags + P;
+    trsm_strip(*trsm, (int)blockIdx.x - P, m, sh.trsm, tid, [&](int p) {
+        if (tid == 0 && !wait_flag(diag_done + p, epoch, err)) flag_error(err);
+        __syncthreads();
+    });
+}
+
+// Marks the end of the launches before it on its stream (see above).
+__global__ void k_signal(unsigned* __restrict__ flag, unsigned v)
+{
+    __hip_atomic_store(flag, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __global__ __launch_bounds__(256) void k_trtri_f64(TileMat K, double* __restrict__ Tall)
@@ -97,6 +146,22 @@ hipError_t launch_potrf_f64(double* A, int lda, int m, double* Tinv, int ldt, in
 {
     hipLaunchKernelGGL(k_potrf_f64, dim3(m / NB), dim3(256), 0, s, A, lda, m, Tinv, ldt, info,
                        col_base, flags, epoch, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_potrf_trsm_f64(double* A, int lda, int m, double* Tinv, int ldt, int* info,
+                                 int64_t col_base, unsigned* flags, unsigned epoch, int* err,
+                                 const TrsmTask* trsm, const unsigned* ready, unsigned ready_val,
+                                 hipStream_t s)
+{
+    hipLaunchKernelGGL(k_potrf_trsm_f64, dim3(2 * (m / NB)), dim3(256), 0, s, A, lda, m, Tinv, ldt,
+                       info, col_base, flags, epoch, err, trsm, ready, ready_val);
+    return hipGetLastError();
+}
+
+hipError_t launch_signal(unsigned* flag, unsigned v, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_signal, dim3(1), dim3(1), 0, s, flag, v);
     return hipGetLastError();
 }
 

@@ -20,8 +20,18 @@ struct TrsmLds {
     double Sacc[32][33];
 };
 
+// No wait before a column block: the diagonal tile is complete at the start.
+struct TrsmNoWait {
+    __device__ void operator()(int) const {}
+};
+
 // Strip s (rows 32 s .. 32 s + 31) of the task; 256 threads, tid = 0..255.
-__device__ inline void trsm_strip(const TrsmTask& tk, int s, int m, TrsmLds& sh, int tid)
+// before_block(p), called by every thread before column block p is read, can
+// wait until rows 32 p .. 32 p + 31 of the diagonal tile and their block
+// inverse are final (a POTRF still running beside the strip).
+template <class Wait = TrsmNoWait>
+__device__ inline void trsm_strip(const TrsmTask& tk, int s, int m, TrsmLds& sh, int tid,
+                                  Wait before_block = Wait())
 {
     double (*As)[TK][36] = sh.As;
     double (*Bs)[TK][36] = sh.Bs;
@@ -34,6 +44,7 @@ __device__ inline void trsm_strip(const TrsmTask& tk, int s, int m, TrsmLds& sh,
     const int qi = wave >> 1, qj = wave & 1;
     const int P = m / 32;
     for (int p = 0; p < P; ++p) {
+        before_block(p);
         const int c0 = 32 * p;
         dbl4 acc;
 #pragma unroll
