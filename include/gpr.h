@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define GPR_ABI_VERSION 6
+#define GPR_ABI_VERSION 7
 
 /* Status codes. */
 enum {
@@ -226,6 +226,20 @@ int gpr_fit_predict_var(gpr_ctx* ctx, const double* X, const double* y, int64_t 
  * L: handle holding a factor; b, x: device vectors of length n (may alias).
  */
 int gpr_solve(gpr_ctx* ctx, gpr_tiled* L, const double* b, double* x, void* stream);
+
+/* gpr_solve for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same launches and the same result bit for bit, with no allocation of any
+ * kind in the call. Its work vectors live in a fixed device array of the
+ * library (3 GPR_NOALLOC_MAX_N doubles, 3 MiB, one copy per GPU, held until
+ * the process ends; its address is taken when a context is created on that
+ * GPU). Every call on one GPU shares that array: calls that overlap on one
+ * GPU (other streams, other contexts, other threads) race and give wrong
+ * results; calls ordered on one stream or by the caller's synchronisation
+ * are safe. L, b, x as in gpr_solve; n rounded up to whole tiles must not
+ * exceed GPR_NOALLOC_MAX_N (GPR_EINVAL otherwise). */
+#define GPR_NOALLOC_MAX_N 131072
+int gpr_solve_noalloc(gpr_ctx* ctx, gpr_tiled* L, const double* b, double* x, void* stream);
 
 /* Negative log marginal likelihood
  *   NLML = 1/2 y^T K^{-1} y + 1/2 log det K + n/2 log(2 pi)

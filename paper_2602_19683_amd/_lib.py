@@ -53,6 +53,7 @@ SIGNATURES = {
                                            ctypes.c_int, ctypes.POINTER(_vp), _vp, _vp, _vp,
                                            _vp, ctypes.POINTER(IRStats), _vp]),
     "gpr_solve": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
+    "gpr_solve_noalloc": (ctypes.c_int, [_vp, _vp, _vp, _vp, _vp]),
     "gpr_nlml_grad": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, Hyper, _i32, ctypes.c_int, _vp,
                                      _vp, _vp, _vp]),
     "gpr_fit_hyper": (ctypes.c_int, [_vp, _vp, _vp, _i64, _i32, _i32,

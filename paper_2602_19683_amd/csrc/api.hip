@@ -20,12 +20,46 @@
 #include <cstdlib>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <vector>
 
 #include "gpr_internal.h"
 
 using namespace gpr;
+
+// Work vectors of gpr_solve_noalloc: the right-hand side padded to whole
+// tiles, the forward result and the solves' copy of their right-hand side,
+// GPR_NOALLOC_MAX_N doubles each (3 MiB). Every GPU the library runs on holds
+// one copy until the process ends. Host code never passes this name to a
+// kernel: it is a host-side stand-in; the device address of each GPU's copy
+// is taken once per device, at context creation, and kept below.
+static __device__ __align__(256) double scratch[3 * GPR_NOALLOC_MAX_N];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxDevices] = {};
+
+// Records the device address of `scratch` on the current device (`device`).
+int scratch_setup(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return GPR_ENODEV;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_dev[device]) return GPR_OK;
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr) return GPR_EHIP;
+    g_scratch_dev[device] = static_cast<double*>(p);
+    return GPR_OK;
+}
+
+double* scratch_device_ptr(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    return g_scratch_dev[device];
+}
+}  // namespace
 
 // Device bytes held by a context's workspace and by the handles it created,
 // against the cap read from the environment variable GPR_MAX_DEVICE_BYTES
@@ -819,6 +853,11 @@ int gpr_ctx_create(gpr_ctx** out, int device, int n_streams, gpr_executor ex)
         gpr_ctx_destroy(c);
         return GPR_EHIP;
     }
+    rc = scratch_setup(device);
+    if (rc) {
+        gpr_ctx_destroy(c);
+        return rc;
+    }
 
     *out = c;
     return GPR_OK;
@@ -1384,6 +1423,29 @@ int gpr_solve(gpr_ctx* ctx, gpr_tiled* L, const double* b, double* x, void* stre
     rc = run_trsv_pair(ctx, L, r, tmp, beta, alpha, s);
     if (rc) return rc;
     HIP_TRY(launch_copy_f64(alpha, x, L->n, L->n, s));
+    return end_call(ctx, s);
+}
+
+int gpr_solve_noalloc(gpr_ctx* ctx, gpr_tiled* L, const double* b, double* x, void* stream)
+{
+    if (!ctx || !L || !b || !x || L->state != GPR_STATE_L || L->device != ctx->device)
+        return GPR_EINVAL;
+    const size_t npad = (size_t)L->M * L->m;
+    if (npad > (size_t)GPR_NOALLOC_MAX_N) return GPR_EINVAL;
+    double* base = scratch_device_ptr(ctx->device);
+    if (!base) return GPR_EHIP;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int rc = begin_call(ctx, s);
+    if (rc) return rc;
+    // The same launches as gpr_solve; the right-hand side's buffer takes the
+    // result of the backward solve (it is no longer read by then).
+    double* r = base;
+    double* beta = r + npad;
+    double* tmp = beta + npad;
+    HIP_TRY(launch_copy_f64(b, r, L->n, (int64_t)npad, s));
+    HIP_TRY(launch_trsv(kmat(L), L->tinv, L->tpair, L->M, r, tmp, beta, false, s));
+    HIP_TRY(launch_trsv(kmat(L), L->tinv, L->tpair, L->M, beta, tmp, r, true, s));
+    HIP_TRY(launch_copy_f64(r, x, L->n, L->n, s));
     return end_call(ctx, s);
 }
 

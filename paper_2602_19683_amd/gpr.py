@@ -267,6 +267,16 @@ class Context:
                                    _stream(stream)), "gpr_solve")
         return x
 
+    def solve_noalloc(self, L, b, x, stream=None):
+        """x = K^{-1} b like solve(), into the caller's x, with no device
+        allocation in the library (work vectors in its fixed per-GPU array;
+        overlapping calls on one GPU race)."""
+        n = L.n
+        _check(self._lib.gpr_solve_noalloc(self._h, L.handle, _dev_ptr(b, "b", n),
+                                           _dev_ptr(x, "x", n), _stream(stream)),
+               "gpr_solve_noalloc")
+        return x
+
     def nlml_grad(self, X, y, hyper, tile, precision="fp64", grad=True, kbar=False,
                   out_nlml=None, out_grad=None, out_kbar=None, stream=None):
         """NLML and (if grad) its gradient in the order (l, v, sigma^2), as

@@ -29,7 +29,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_abi_version_and_strerror():
     lib = _lib.load()
-    assert lib.gpr_abi_version() == 6
+    assert lib.gpr_abi_version() == 7
     for code in [0, 1, -1, -2, -3, -4, -5]:
         assert lib.gpr_strerror(code)
     assert b"unknown" in lib.gpr_strerror(12345)
@@ -67,6 +67,7 @@ def test_host_argument_validation():
     assert lib.gpr_nlml_grad(None, None, None, 10, 8, H, 32, 0, None, None, None,
                              None) == _lib.GPR_EINVAL
     assert lib.gpr_solve(None, None, None, None, None) == _lib.GPR_EINVAL
+    assert lib.gpr_solve_noalloc(None, None, None, None, None) == _lib.GPR_EINVAL
     assert lib.gpr_fit_predict(None, None, None, 10, None, 5, 8, H, 32, 0, None, None, None,
                                None, None, None) == _lib.GPR_EINVAL
     assert lib.gpr_predict_var(None, None, None, None, 10, None, 5, 8, H, None, None, None, None,
