@@ -474,6 +474,25 @@ int run_sweep(gpr_ctx* ctx, const SweepMats& X, const SweepPlan& P, const DescBu
     std::vector<char> fused(Ls.size(), 0);      // TRSM launch run inside the POTRF before it
     std::vector<unsigned> signal(Ls.size(), 0); // value to signal after this launch (0: none)
     std::vector<unsigned> ready(Ls.size(), 0);  // POTRF launch: value its TRSM strips wait for
+    // In FP64, the one-tile SYRK that precedes a POTRF on its stream (the last
+    // update of the diagonal tile) is applied by the POTRF's own workgroups.
+    std::vector<int> syrk_of(Ls.size(), -1);    // POTRF launch: the SYRK launch it absorbs
+    std::vector<char> absorbed(Ls.size(), 0);   // SYRK launch issued with a later POTRF
+    {
+        std::vector<int> last_on(3, -1);
+        for (size_t li = 0; li < Ls.size(); ++li) {
+            const SchedLaunch& L = Ls[li];
+            const int pv = last_on[L.stream];
+            last_on[L.stream] = (int)li;
+            if (L.kind != LK_POTRF || pv < 0 || X.prec != GPR_FP64) continue;
+            const SchedLaunch& S = Ls[pv];
+            if (S.kind != LK_UPDATE || S.count != 1) continue;
+            const SchedTask& t = P.sched.tasks[S.first];
+            if (t.kind != K_SYRK || t.I != L.step || t.K != L.step) continue;
+            syrk_of[li] = pv;
+            absorbed[pv] = 1;
+        }
+    }
     for (size_t li = 0; li + 1 < Ls.size(); ++li) {
         const SchedLaunch &Lp = Ls[li], &Lt = Ls[li + 1];
         if (Lp.kind != LK_POTRF || Lt.kind != LK_TRSM || Lt.count != 1 || Lp.stream != Lt.stream)
@@ -508,25 +527,40 @@ int run_sweep(gpr_ctx* ctx, const SweepMats& X, const SweepPlan& P, const DescBu
             if (waited[li]) HIP_TRY(hipEventRecord(ctx->evpool[li], st));
             continue;
         }
-        for (int k = 0; k < L.nwait; ++k)
-            if (phys[Ls[L.wait[k]].stream] != st)
-                HIP_TRY(hipStreamWaitEvent(st, ctx->evpool[L.wait[k]], 0));
+        if (absorbed[li]) continue;  // issued with the POTRF after it
+        auto wait_for = [&](const SchedLaunch& W) -> int {
+            for (int k = 0; k < W.nwait; ++k)
+                if (phys[Ls[W.wait[k]].stream] != st)
+                    HIP_TRY(hipStreamWaitEvent(st, ctx->evpool[W.wait[k]], 0));
+            return GPR_OK;
+        };
+        if (L.kind == LK_POTRF && syrk_of[li] >= 0) {
+            rc = wait_for(Ls[syrk_of[li]]);
+            if (rc) return rc;
+        }
+        rc = wait_for(L);
+        if (rc) return rc;
         const double m3 = (double)m * m * m;
         if (L.kind == LK_POTRF) {
             const int J = L.step;
             double* A = X.at(J, J);
             double* Ti = X.tinv + (size_t)J * m * m;
+            const double* syrk =
+                syrk_of[li] >= 0 ? X.at(J, P.sched.tasks[Ls[syrk_of[li]].first].J) : nullptr;
+            const double fs = syrk ? m3 : 0.0;
             if (li + 1 < Ls.size() && fused[li + 1]) {
-                ProfScope ps(ctx, st, PK_POTRF, m3 / 3.0 + m3, 0.0);
+                ProfScope ps(ctx, st, PK_POTRF, m3 / 3.0 + m3 + fs, 0.0);
                 HIP_TRY(launch_potrf_trsm_f64(A, m, m, Ti, m, ctx->d_info, (int64_t)J * m,
                                               ctx->d_flags, ++ctx->epoch, ctx->d_info + 2,
                                               db.dev<TrsmTask>(ctx, P.off[li + 1]),
-                                              ready[li] ? sigflag : nullptr, ready[li], st));
+                                              ready[li] ? sigflag : nullptr, ready[li], st, syrk));
             } else {
-                ProfScope ps(ctx, st, PK_POTRF, m3 / 3.0, 0.0);
+                ProfScope ps(ctx, st, PK_POTRF, m3 / 3.0 + fs, 0.0);
                 HIP_TRY(launch_potrf_f64(A, m, m, Ti, m, ctx->d_info, (int64_t)J * m,
-                                         ctx->d_flags, ++ctx->epoch, ctx->d_info + 2, st));
+                                         ctx->d_flags, ++ctx->epoch, ctx->d_info + 2, st, syrk));
             }
+            if (syrk_of[li] >= 0 && waited[syrk_of[li]])
+                HIP_TRY(hipEventRecord(ctx->evpool[syrk_of[li]], st));
         } else if (L.kind == LK_TRSM) {
             ProfScope ps(ctx, st, PK_TRSM, L.count * m3, 0.0);
             HIP_TRY(launch_trsm_f64(db.dev<TrsmTask>(ctx, P.off[li]), L.count, m, abort_info, st));

@@ -125,10 +125,11 @@ hipError_t launch_trsm_f64(const TrsmTask* d_tasks, int ntask, int m, const int*
 // POTRF of one diagonal tile, m / 32 cooperating workgroups ordered by
 // flags[0 .. 2 m/32) (set to `epoch` as parts of a row panel are done; epoch
 // must differ from every value the flags hold). *err is set if a wait hits
-// its limit.
+// its limit. syrk (nullable): an m x m tile S (ld m); A -= S S^T is applied
+// first, by the POTRF's own workgroups (the tile's last SYRK update).
 hipError_t launch_potrf_f64(double* A, int lda, int m, double* Tinv, int ldt, int* info,
                             int64_t col_base, unsigned* flags, unsigned epoch, int* err,
-                            hipStream_t s);
+                            hipStream_t s, const double* syrk = nullptr);
 // POTRF of one diagonal tile and the TRSM task *trsm (the tile below it) in
 // one launch, the TRSM strips following the POTRF row panels (2 m/32
 // workgroups). ready (nullable): the strips first wait until *ready ==
@@ -137,7 +138,7 @@ hipError_t launch_potrf_f64(double* A, int lda, int m, double* Tinv, int ldt, in
 hipError_t launch_potrf_trsm_f64(double* A, int lda, int m, double* Tinv, int ldt, int* info,
                                  int64_t col_base, unsigned* flags, unsigned epoch, int* err,
                                  const TrsmTask* trsm, const unsigned* ready, unsigned ready_val,
-                                 hipStream_t s);
+                                 hipStream_t s, const double* syrk = nullptr);
 // *flag = v (release, device scope) once the launches before it on s are done.
 hipError_t launch_signal(unsigned* flag, unsigned v, hipStream_t s);
 // Inverses of the M factored diagonal tiles (J, J) of the lower-tiled K;

@@ -7,14 +7,17 @@
 // multiple of KC. Chunks of KC columns go through LDS k-major (the 16 lanes
 // sharing a k read consecutive words), double-buffered. All 256 threads must
 // call it (tid: the thread's index, 0..255); As and Bs are LDS arrays
-// [2][KC][32 + 4].
+// [2][KC][32 + 4]. ONE_CHAIN: every product is added to acc in k order
+// (one MFMA chain), the order of the tile-update kernels' blocks; otherwise
+// two chains (even and odd groups of four k) are added at the end of each
+// chunk.
 #pragma once
 
 #include "k_common.h"
 
 namespace gpr {
 
-template <bool NT, int KC>
+template <bool NT, int KC, bool ONE_CHAIN = false>
 __device__ inline dbl4 accum32(const double* __restrict__ A, int lda, const double* __restrict__ B,
                                int ldb, int K, dbl4 acc, double sign, double (*As)[KC][36],
                                double (*Bs)[KC][36], int tid)
@@ -66,14 +69,20 @@ __device__ inline dbl4 accum32(const double* __restrict__ A, int lda, const doub
     for (int kt = 0; kt < nk; ++kt) {
         const int cur = kt & 1;
         if (kt + 1 < nk) gload((kt + 1) * KC);
-        dbl4 acc2 = {0.0, 0.0, 0.0, 0.0};
+        if (ONE_CHAIN) {
 #pragma unroll
-        for (int kk = 0; kk < KC; kk += 8) {
-            acc = mfma16(As[cur][kk + lk][16 * qi + lr], Bs[cur][kk + lk][16 * qj + lr], acc);
-            acc2 = mfma16(As[cur][kk + 4 + lk][16 * qi + lr], Bs[cur][kk + 4 + lk][16 * qj + lr],
-                          acc2);
+            for (int kk = 0; kk < KC; kk += 4)
+                acc = mfma16(As[cur][kk + lk][16 * qi + lr], Bs[cur][kk + lk][16 * qj + lr], acc);
+        } else {
+            dbl4 acc2 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int kk = 0; kk < KC; kk += 8) {
+                acc = mfma16(As[cur][kk + lk][16 * qi + lr], Bs[cur][kk + lk][16 * qj + lr], acc);
+                acc2 = mfma16(As[cur][kk + 4 + lk][16 * qi + lr],
+                              Bs[cur][kk + 4 + lk][16 * qj + lr], acc2);
+            }
+            acc += acc2;
         }
-        acc += acc2;
         if (kt + 1 < nk) swrite(cur ^ 1);
         __syncthreads();
     }

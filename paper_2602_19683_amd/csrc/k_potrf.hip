@@ -36,7 +36,8 @@ __global__ __launch_bounds__(256) void k_potrf_f64(double* __restrict__ A, int l
                                                    double* __restrict__ Tinv, int ldt,
                                                    int* __restrict__ info, int64_t col_base,
                                                    unsigned* __restrict__ flags, unsigned epoch,
-                                                   int* __restrict__ err)
+                                                   int* __restrict__ err,
+                                                   const double* __restrict__ syrk)
 {
     // a pivot already failed in an earlier tile: nothing of this factorisation
     // is used any more. Failures of this launch are recorded as columns
@@ -47,7 +48,7 @@ __global__ __launch_bounds__(256) void k_potrf_f64(double* __restrict__ A, int l
     }
     __shared__ PotrfLds sh;
     potrf_panel(A, lda, m, Tinv, ldt, info, col_base, flags, epoch, err, blockIdx.x, sh,
-                threadIdx.x);
+                threadIdx.x, syrk);
 }
 
 // POTRF of the diagonal tile (J, J) and the TRSM of the tile below it,
@@ -59,12 +60,13 @@ __global__ __launch_bounds__(256) void k_potrf_f64(double* __restrict__ A, int l
 // the last update of its own tile, done by a launch on another stream: that
 // launch is followed by a one-thread kernel that stores `ready_val` to
 // *ready (release), and the strips acquire it before they start (ready may be
-// null when the update is ordered by the stream itself).
+// null when the update is ordered by the stream itself). With syrk given, the
+// POTRF panels first apply the tile's last SYRK update themselves.
 __global__ __launch_bounds__(256) void k_potrf_trsm_f64(
     double* __restrict__ A, int lda, int m, double* __restrict__ Tinv, int ldt,
     int* __restrict__ info, int64_t col_base, unsigned* __restrict__ flags, unsigned epoch,
     int* __restrict__ err, const TrsmTask* __restrict__ trsm, const unsigned* __restrict__ ready,
-    unsigned ready_val)
+    unsigned ready_val, const double* __restrict__ syrk)
 {
     if (info != nullptr) {
         const int f = *info;
@@ -78,7 +80,7 @@ __global__ __launch_bounds__(256) void k_potrf_trsm_f64(
     const int tid = threadIdx.x;
     if ((int)blockIdx.x < P) {
         potrf_panel(A, lda, m, Tinv, ldt, info, col_base, flags, epoch, err, blockIdx.x, sh.potrf,
-                    tid);
+                    tid, syrk);
         return;
     }
     if (ready != nullptr) {
@@ -142,20 +144,20 @@ __global__ __launch_bounds__(256) void k_trtri_f64(TileMat K, double* __restrict
 
 hipError_t launch_potrf_f64(double* A, int lda, int m, double* Tinv, int ldt, int* info,
                             int64_t col_base, unsigned* flags, unsigned epoch, int* err,
-                            hipStream_t s)
+                            hipStream_t s, const double* syrk)
 {
     hipLaunchKernelGGL(k_potrf_f64, dim3(m / NB), dim3(256), 0, s, A, lda, m, Tinv, ldt, info,
-                       col_base, flags, epoch, err);
+                       col_base, flags, epoch, err, syrk);
     return hipGetLastError();
 }
 
 hipError_t launch_potrf_trsm_f64(double* A, int lda, int m, double* Tinv, int ldt, int* info,
                                  int64_t col_base, unsigned* flags, unsigned epoch, int* err,
                                  const TrsmTask* trsm, const unsigned* ready, unsigned ready_val,
-                                 hipStream_t s)
+                                 hipStream_t s, const double* syrk)
 {
     hipLaunchKernelGGL(k_potrf_trsm_f64, dim3(2 * (m / NB)), dim3(256), 0, s, A, lda, m, Tinv, ldt,
-                       info, col_base, flags, epoch, err, trsm, ready, ready_val);
+                       info, col_base, flags, epoch, err, trsm, ready, ready_val, syrk);
     return hipGetLastError();
 }
 

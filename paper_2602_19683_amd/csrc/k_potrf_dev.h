@@ -194,11 +194,16 @@ struct PotrfLds {
 };
 
 // Row panel w of the POTRF of the m x m tile A (see k_potrf.hip). 256 threads;
-// tid is the thread's index (0..255).
+// tid is the thread's index (0..255). syrk (nullable): an m x m tile S
+// (leading dimension m) whose product S S^T is first subtracted from the
+// panel's blocks (the tile's last SYRK update, run by the panel itself). Each
+// element's products are summed in k order from zero and the sum subtracted
+// once, as the tile-update kernels do, so the result is bitwise theirs.
 __device__ inline void potrf_panel(double* __restrict__ A, int lda, int m, double* __restrict__ Tinv,
                                    int ldt, int* __restrict__ info, int64_t col_base,
                                    unsigned* __restrict__ flags, unsigned epoch,
-                                   int* __restrict__ err, int w, PotrfLds& sh, int tid)
+                                   int* __restrict__ err, int w, PotrfLds& sh, int tid,
+                                   const double* __restrict__ syrk = nullptr)
 {
     double (*As)[KC][SP] = sh.As;
     double (*Bs)[KC][SP] = sh.Bs;
@@ -216,6 +221,20 @@ __device__ inline void potrf_panel(double* __restrict__ A, int lda, int m, doubl
     unsigned* off_done = flags;
     unsigned* diag_done = flags + P;
 
+    if (syrk != nullptr) {
+        // K[w, q] -= S[w rows] S[q rows]^T for q <= w; the panel owns these blocks
+        for (int q = 0; q <= w; ++q) {
+            dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+            acc = accum32<true, KC, true>(syrk + (size_t)row0 * m, m, syrk + (size_t)NB * q * m, m,
+                                          m, acc, 1.0, As, Bs, tid);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                double* c = Aw + (size_t)(16 * qi + drow(lk, v)) * lda + NB * q + 16 * qj + lr;
+                gst(c, gld(c) - acc[v]);
+            }
+        }
+        __syncthreads();  // the updated blocks are read by every wave below
+    }
     // running sum of L[w, p] L[w, p]^T over the finished blocks p < q, this
     // wave's 16 x 16 quadrant of the diagonal block
     dbl4 dacc = {0.0, 0.0, 0.0, 0.0};
