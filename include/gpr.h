@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define GPR_ABI_VERSION 7
+#define GPR_ABI_VERSION 8
 
 /* Status codes. */
 enum {
@@ -94,6 +94,24 @@ typedef enum {
     GPR_EXEC_STREAMS = 0,
     GPR_EXEC_PERSISTENT = 1
 } gpr_executor;
+
+/* Order of the tile tasks of the factorisation (Sec. 4.2: the right-looking
+ * algorithm of Fig. 1, and its left-looking variant).
+ * GPR_RIGHT_LOOKING: after POTRF and the TRSMs of tile column J, every later
+ * tile is updated with column J (one rank-m update per step).
+ * GPR_LEFT_LOOKING: tile column K receives the products of all earlier
+ * columns just before it is factored: its terms 0 .. K-2 in one update task
+ * per tile, accumulated in registers and subtracted once (issued while
+ * column K-1 is being factored; a long task is split over several workgroups
+ * whose parts are added in a fixed order), then its last term; the test
+ * block of the covariance (eq. (3)) takes all its terms in one task per tile
+ * after the last column. Each tile is then read and written a few times
+ * instead of once per step. The two orders give the same factor up to
+ * rounding (different summation order); each is deterministic. */
+typedef enum {
+    GPR_RIGHT_LOOKING = 0,
+    GPR_LEFT_LOOKING = 1
+} gpr_variant;
 
 typedef struct gpr_ctx gpr_ctx;      /* device, streams, events, workspace   */
 typedef struct gpr_tiled gpr_tiled;  /* lower-tiled symmetric / triangular n x n matrix */
@@ -142,6 +160,14 @@ int gpr_ctx_create(gpr_ctx** out, int device, int n_streams, gpr_executor ex);
 
 /* Waits for all work of the context, frees its workspace and the context. */
 int gpr_ctx_destroy(gpr_ctx* ctx);
+
+/* Chooses the task order of every later factorisation of the context
+ * (gpr_cholesky, gpr_fit_predict, gpr_fit_predict_var, the forward sweep of
+ * gpr_nlml_grad and gpr_fit_hyper) and of the covariance solve of
+ * gpr_predict. Default GPR_RIGHT_LOOKING. A context made for
+ * GPR_EXEC_PERSISTENT runs left-looking sweeps on the streams. Host call;
+ * GPR_EINVAL for an unknown variant. */
+int gpr_ctx_set_variant(gpr_ctx* ctx, gpr_variant v);
 
 /* ---- the hot path --------------------------------------------------------- */
 
@@ -361,6 +387,15 @@ int gpr_schedule_describe(int32_t M, int32_t Mhat, int32_t mode,
                           int32_t* tasks, int64_t task_cap, int64_t* n_tasks,
                           int32_t* launches, int64_t launch_cap,
                           int64_t* n_launches);
+
+/* gpr_schedule_describe for either task order. tasks: 6 int32 per task:
+ * kind, I, K, J, nk, launch index; an update task (kind 2 or 3) of tile
+ * (I, K) holds the nk products of columns J .. J + nk - 1 (nk = 1 throughout
+ * for GPR_RIGHT_LOOKING, whose list equals gpr_schedule_describe's). */
+int gpr_schedule_describe_variant(int32_t M, int32_t Mhat, int32_t mode, int32_t variant,
+                                  int32_t* tasks, int64_t task_cap, int64_t* n_tasks,
+                                  int32_t* launches, int64_t launch_cap,
+                                  int64_t* n_launches);
 
 /* The reverse sweep of gpr_nlml_grad as a list of batched tile-product
  * launches, for M tile rows and a split of the long row sums into chunks of

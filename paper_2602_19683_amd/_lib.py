@@ -10,6 +10,7 @@ LIB_PATH = os.path.join(HERE, "libgpr.so")
 GPR_OK, GPR_ENOTPD, GPR_EINVAL, GPR_ENOMEM, GPR_EHIP, GPR_ENODEV, GPR_ENOTSUP = 0, 1, -1, -2, -3, -4, -5
 GPR_FP64, GPR_MIXED_FP32, GPR_MIXED_BF16 = 0, 1, 2
 GPR_EXEC_STREAMS, GPR_EXEC_PERSISTENT = 0, 1
+GPR_RIGHT_LOOKING, GPR_LEFT_LOOKING = 0, 1
 GPR_STATE_EMPTY, GPR_STATE_K, GPR_STATE_L = 0, 1, 2
 
 
@@ -39,6 +40,7 @@ SIGNATURES = {
     "gpr_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "gpr_ctx_create": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, ctypes.c_int]),
     "gpr_ctx_destroy": (ctypes.c_int, [_vp]),
+    "gpr_ctx_set_variant": (ctypes.c_int, [_vp, ctypes.c_int]),
     "gpr_assemble": (ctypes.c_int, [_vp, _vp, _i64, _i32, Hyper, _i32, ctypes.POINTER(_vp), _vp]),
     "gpr_cholesky": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, _vp]),
     "gpr_cholesky_dense": (ctypes.c_int, [_vp, _vp, _i64, _i32, ctypes.c_int, _vp, _vp]),
@@ -71,6 +73,8 @@ SIGNATURES = {
     "gpr_sync": (ctypes.c_int, [_vp, _vp, _i64p]),
     "gpr_schedule_describe": (ctypes.c_int, [_i32, _i32, _i32, _i32p, _i64, _i64p, _i32p, _i64,
                                              _i64p]),
+    "gpr_schedule_describe_variant": (ctypes.c_int, [_i32, _i32, _i32, _i32, _i32p, _i64, _i64p,
+                                                     _i32p, _i64, _i64p]),
     "gpr_adjoint_describe": (ctypes.c_int, [_i32, _i32, _i32p, _i64, _i64p, _i32p, _i64, _i64p,
                                             _i32p, _i64, _i64p]),
     "gpr_persist_describe": (ctypes.c_int, [_i32, _i32, _i32, _i32, _i32, _i32, _i32p, _i64p,

@@ -91,6 +91,9 @@ struct gpr_ctx {
     unsigned* d_flags = nullptr;  // POTRF row-panel flags
     unsigned epoch = 0;
     unsigned sigseq = 0;          // values stored by launch_signal (d_flags[SIGNAL_FLAG])
+    int variant = GPR_RIGHT_LOOKING;  // task order of the sweeps
+    char* d_part = nullptr;       // part tiles of split (left-looking) updates
+    size_t part_cap = 0;
     char* d_desc = nullptr;
     size_t desc_cap = 0;
     char* h_desc = nullptr;       // pinned staging
@@ -356,28 +359,77 @@ struct SweepPlan {
     bool persistent = false;  // run by the persistent executor (no descriptors)
     Schedule sched;
     std::vector<size_t> off;  // descriptor offset per launch
+    std::vector<int> nt;      // update launches: kernel tasks (split parts included)
+    std::vector<size_t> roff; // update launches: ReduceTask descriptors
+    std::vector<int> nred;    // update launches: tasks of the part sums (0: not split)
+    int err = GPR_OK;         // the part buffer could not be allocated
 };
+
+// A long multi-term update launch (left-looking) with few 128 x 128 blocks is
+// split along k so that it fills the chip: each task is cut into up to
+// SPLIT_MAX runs of consecutive terms, whose sums go to part tiles, added to
+// the tile in run order by a second kernel. Only bulk-stream launches split
+// (they run one after the other, so one part buffer serves them all).
+constexpr long SPLIT_TARGET = 1024;  // workgroups to aim for
+constexpr int SPLIT_MAX = 8;
 
 // The persistent executor runs FP64 and FP32-update sweeps; a context created
 // for it runs the BF16 sweeps (whose updates have no persistent form) on the
 // streams.
 bool use_persistent(const gpr_ctx* ctx, const SweepMats& X)
 {
-    return ctx->executor == GPR_EXEC_PERSISTENT &&
+    return ctx->executor == GPR_EXEC_PERSISTENT && ctx->variant == GPR_RIGHT_LOOKING &&
            (X.prec == GPR_FP64 || X.prec == GPR_MIXED_FP32);
 }
 
-// Builds the descriptors of a sweep into `db`.
-SweepPlan plan_sweep(const gpr_ctx* ctx, const SweepMats& X, int mode, DescBuffer& db)
+// Builds the descriptors of a sweep into `db` (and sizes the part buffer of
+// split updates).
+SweepPlan plan_sweep(gpr_ctx* ctx, const SweepMats& X, int mode, DescBuffer& db)
 {
     SweepPlan P;
     P.mode = mode;
     P.persistent = use_persistent(ctx, X);
     if (P.persistent) return P;
-    P.sched = build_schedule(X.M, X.Mhat, mode);
-    P.off.assign(P.sched.launches.size(), 0);
+    P.sched = build_schedule_variant(X.M, X.Mhat, mode, ctx->variant);
+    const size_t nl = P.sched.launches.size();
+    P.off.assign(nl, 0);
+    P.nt.assign(nl, 0);
+    P.roff.assign(nl, 0);
+    P.nred.assign(nl, 0);
     const int m = X.m;
-    for (size_t li = 0; li < P.sched.launches.size(); ++li) {
+    const size_t m2 = (size_t)m * m;
+    // runs per task of each update launch, and the part tiles it needs
+    std::vector<int> split(nl, 1);
+    size_t parts_max = 0;
+    for (size_t li = 0; li < nl; ++li) {
+        const SchedLaunch& L = P.sched.launches[li];
+        if (L.kind != LK_UPDATE || L.stream != 2 || m % 128 != 0) continue;
+        const long nb = m / 128;
+        long blocks = 0;
+        int maxnk = 1;
+        for (int t = L.first; t < L.first + L.count; ++t) {
+            const SchedTask& k = P.sched.tasks[t];
+            blocks += k.kind == K_SYRK ? nb * (nb + 1) / 2 : nb * nb;
+            maxnk = std::max(maxnk, k.nk);
+        }
+        if (maxnk < 2 || blocks >= SPLIT_TARGET) continue;
+        const int S = (int)std::min<long>({(long)maxnk, (SPLIT_TARGET + blocks - 1) / blocks,
+                                          (long)SPLIT_MAX});
+        if (S < 2) continue;
+        split[li] = S;
+        size_t parts = 0;
+        for (int t = L.first; t < L.first + L.count; ++t)
+            if (P.sched.tasks[t].nk >= 2) parts += std::min(S, P.sched.tasks[t].nk);
+        parts_max = std::max(parts_max, parts);
+    }
+    double* part_base = nullptr;
+    if (parts_max) {
+        P.err = ensure_device_bytes(ctx->budget, &ctx->d_part, &ctx->part_cap,
+                                    parts_max * m2 * sizeof(double));
+        if (P.err) return P;
+        part_base = reinterpret_cast<double*>(ctx->d_part);
+    }
+    for (size_t li = 0; li < nl; ++li) {
         const SchedLaunch& L = P.sched.launches[li];
         if (L.kind == LK_TRSM) {
             std::vector<TrsmTask> v;
@@ -389,12 +441,38 @@ SweepPlan plan_sweep(const gpr_ctx* ctx, const SweepMats& X, int mode, DescBuffe
             P.off[li] = db.add(v.data(), v.size() * sizeof(TrsmTask));
         } else if (L.kind == LK_UPDATE) {
             std::vector<UpdateTask> v;
+            std::vector<ReduceTask> red;
+            size_t used = 0;  // part tiles handed out in this launch
             for (int t = L.first; t < L.first + L.count; ++t) {
                 const SchedTask& k = P.sched.tasks[t];
-                v.push_back({X.at(k.I, k.K), X.at(k.I, k.J), X.at(k.K, k.J), m, m, m,
-                             k.kind == K_SYRK ? TASK_DIAG : 0});
+                UpdateTask u{X.at(k.I, k.K), X.at(k.I, k.J), X.at(k.K, k.J), m, m, m,
+                             k.kind == K_SYRK ? TASK_DIAG : 0};
+                u.nk = k.nk;
+                u.kstride = (long long)m2;  // tiles (I, k), k = J.. are adjacent
+                const int runs = k.nk >= 2 ? std::min(split[li], k.nk) : 1;
+                if (runs == 1) {
+                    v.push_back(u);
+                    continue;
+                }
+                ReduceTask r{u.C, part_base + used * m2, (long long)m2, m, runs, u.flags, 0};
+                red.push_back(r);
+                for (int c = 0; c < runs; ++c) {
+                    const int k0 = c * k.nk / runs, k1 = (c + 1) * k.nk / runs;
+                    UpdateTask w = u;
+                    w.A = X.at(k.I, k.J + k0);
+                    w.B = X.at(k.K, k.J + k0);
+                    w.nk = k1 - k0;
+                    w.part = part_base + (used + c) * m2;
+                    v.push_back(w);
+                }
+                used += runs;
             }
             P.off[li] = db.add(v.data(), v.size() * sizeof(UpdateTask));
+            P.nt[li] = (int)v.size();
+            if (!red.empty()) {
+                P.roff[li] = db.add(red.data(), red.size() * sizeof(ReduceTask));
+                P.nred[li] = (int)red.size();
+            }
         }
     }
     return P;
@@ -457,6 +535,7 @@ int run_persist(gpr_ctx* ctx, const SweepMats& X, int mode, hipStream_t s)
 int run_sweep(gpr_ctx* ctx, const SweepMats& X, const SweepPlan& P, const DescBuffer& db,
               hipStream_t s)
 {
+    if (P.err) return P.err;
     if (P.persistent) return run_persist(ctx, X, P.mode, s);
     const auto& Ls = P.sched.launches;
     int rc = ensure_events(ctx, Ls.size());
@@ -488,7 +567,7 @@ int run_sweep(gpr_ctx* ctx, const SweepMats& X, const SweepPlan& P, const DescBu
             const SchedLaunch& S = Ls[pv];
             if (S.kind != LK_UPDATE || S.count != 1) continue;
             const SchedTask& t = P.sched.tasks[S.first];
-            if (t.kind != K_SYRK || t.I != L.step || t.K != L.step) continue;
+            if (t.kind != K_SYRK || t.I != L.step || t.K != L.step || t.nk != 1) continue;
             syrk_of[li] = pv;
             absorbed[pv] = 1;
         }
@@ -567,14 +646,17 @@ int run_sweep(gpr_ctx* ctx, const SweepMats& X, const SweepPlan& P, const DescBu
         } else {
             double f = 0.0;
             for (int t = L.first; t < L.first + L.count; ++t)
-                f += P.sched.tasks[t].kind == K_SYRK ? m3 : 2.0 * m3;
+                f += (P.sched.tasks[t].kind == K_SYRK ? m3 : 2.0 * m3) * P.sched.tasks[t].nk;
             ProfScope ps(ctx, st, PK_UPDATE, f, 0.0);
             if (X.prec == GPR_FP64)
-                HIP_TRY(launch_update_f64(db.dev<UpdateTask>(ctx, P.off[li]), L.count, m,
+                HIP_TRY(launch_update_f64(db.dev<UpdateTask>(ctx, P.off[li]), P.nt[li], m,
                                           abort_info, st));
             else
-                HIP_TRY(launch_update_mixed(db.dev<UpdateTask>(ctx, P.off[li]), L.count, m,
+                HIP_TRY(launch_update_mixed(db.dev<UpdateTask>(ctx, P.off[li]), P.nt[li], m,
                                             X.prec, abort_info, st));
+            if (P.nred[li])
+                HIP_TRY(launch_update_reduce(db.dev<ReduceTask>(ctx, P.roff[li]), P.nred[li], m,
+                                             abort_info, st));
         }
         if (signal[li]) HIP_TRY(launch_signal(sigflag, signal[li], st));
         if (waited[li]) HIP_TRY(hipEventRecord(ctx->evpool[li], st));
@@ -897,6 +979,13 @@ int gpr_ctx_create(gpr_ctx** out, int device, int n_streams, gpr_executor ex)
     return GPR_OK;
 }
 
+int gpr_ctx_set_variant(gpr_ctx* ctx, gpr_variant v)
+{
+    if (!ctx || (v != GPR_RIGHT_LOOKING && v != GPR_LEFT_LOOKING)) return GPR_EINVAL;
+    ctx->variant = (int)v;
+    return GPR_OK;
+}
+
 int gpr_ctx_destroy(gpr_ctx* c)
 {
     if (!c) return GPR_EINVAL;
@@ -906,6 +995,7 @@ int gpr_ctx_destroy(gpr_ctx* c)
     if (c->nlml_K) gpr_tiled_free(c->nlml_K);
     budget_free(c->budget, c->d_fit, c->fit_cap);
     budget_free(c->budget, c->d_adj, c->adj_cap);
+    budget_free(c->budget, c->d_part, c->part_cap);
     for (auto e : c->evpool) (void)hipEventDestroy(e);
     for (auto e : c->tpool) (void)hipEventDestroy(e);
     if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);

@@ -51,6 +51,25 @@ struct UpdateTask {
     const double* A;
     const double* B;
     int ldc, lda, ldb, flags;
+    // nk consecutive products: C -= sum_{t < nk} A_t B_t^T with A_t = A + t kstride,
+    // B_t = B + t kstride (the tiles (I, k), k = k0 .. k0 + nk - 1, of one tile
+    // row are kstride = m^2 apart), summed in t order into one accumulator.
+    int nk = 1;
+    int pad = 0;
+    long long kstride = 0;
+    // part != null: store the accumulated sum there (leading dimension ldc)
+    // instead of subtracting it from C (one part of a split update).
+    double* part = nullptr;
+};
+
+// C -= part_0 + ... (subtracted one part after the other, in order) over the
+// tile, the lower 128-row blocks only for a symmetric task (flags & TASK_DIAG);
+// parts are m x m with leading dimension m, `stride` doubles apart.
+struct ReduceTask {
+    double* C;
+    const double* part;
+    long long stride;
+    int ldc, nparts, flags, pad;
 };
 
 // B := B * L_JJ^{-T} in place (TRSM of Fig. 1 read as L_IJ = K_IJ L_JJ^{-T}).
@@ -120,6 +139,9 @@ hipError_t launch_tiled_to_dense(const TileMat& T, int64_t n, double* out, int64
 // Pass it only for sweeps that factorise, where it was reset beforehand.
 hipError_t launch_update_f64(const UpdateTask* d_tasks, int ntask, int m, const int* abort_info,
                              hipStream_t s);
+// The part sums of split updates (ReduceTask).
+hipError_t launch_update_reduce(const ReduceTask* d_tasks, int ntask, int m, const int* abort_info,
+                                hipStream_t s);
 hipError_t launch_trsm_f64(const TrsmTask* d_tasks, int ntask, int m, const int* abort_info,
                            hipStream_t s);
 // POTRF of one diagonal tile, m / 32 cooperating workgroups ordered by
@@ -256,6 +278,7 @@ inline bool sweep_test_block(int mode) { return mode == SWEEP_PREDICT || mode ==
 
 struct SchedTask {
     int kind, I, K, J;
+    int nk = 1;  // update tasks: products of columns J .. J + nk - 1 (left-looking)
 };
 
 struct SchedLaunch {
@@ -308,6 +331,10 @@ AdjPlan build_adjoint(int M, int G);
 // Tile sweep over M training tile rows and Mhat test tile rows (see gpr.h,
 // gpr_schedule_describe).
 Schedule build_schedule(int M, int Mhat, int mode);
+// The left-looking task order (multi-term update tasks), and the schedule of
+// a variant (GPR_RIGHT_LOOKING: build_schedule).
+Schedule build_schedule_left(int M, int Mhat, int mode);
+Schedule build_schedule_variant(int M, int Mhat, int mode, int variant);
 
 // Persistent executor (persist.cpp, k_persist.hip): geometry, ticket order for
 // `workers` resident workgroups, update block size for a tile size, the

@@ -51,6 +51,49 @@ int update_block_f64(int ntask, int m)
     return 32;
 }
 
+// Sums of split updates: C -= part_0, then part_1, ... per element. One
+// workgroup per 128 x 128 block (256 threads, 64 elements each); for a
+// symmetric task only the lower 32 x 32 blocks (m a multiple of 128).
+__global__ __launch_bounds__(256) void k_update_reduce(const ReduceTask* __restrict__ tasks, int m,
+                                                       const int* __restrict__ abort_info)
+{
+    if (abort_info != nullptr && *abort_info > 0) return;
+    constexpr int BM = 128;
+    const int nb = m / BM;
+    const int t = blockIdx.x / (nb * nb);
+    const int sub = blockIdx.x - t * nb * nb;
+    const int bi = sub / nb, bj = sub - bi * nb;
+    const ReduceTask tk = tasks[t];
+    if ((tk.flags & TASK_DIAG) && bj > bi) return;
+    const size_t off = (size_t)bi * BM * m + (size_t)bj * BM;
+    double* __restrict__ C = tk.C + (size_t)bi * BM * tk.ldc + (size_t)bj * BM;
+    const bool diag = (tk.flags & TASK_DIAG) != 0;
+    for (int e = threadIdx.x; e < BM * BM / 2; e += 256) {
+        const int r = e / (BM / 2), c = (e % (BM / 2)) * 2;
+        // a symmetric task's parts hold its lower 32 x 32 blocks (every update
+        // block size computes those)
+        if (diag && (bj * BM + c) / 32 > (bi * BM + r) / 32) continue;
+        double2 v = gld2(C + (size_t)r * tk.ldc + c);
+        for (int p = 0; p < tk.nparts; ++p) {
+            const double2 q = gld2(tk.part + p * tk.stride + off + (size_t)r * m + c);
+            v.x -= q.x;
+            v.y -= q.y;
+        }
+        gst(C + (size_t)r * tk.ldc + c, v.x);
+        gst(C + (size_t)r * tk.ldc + c + 1, v.y);
+    }
+}
+
+hipError_t launch_update_reduce(const ReduceTask* d_tasks, int ntask, int m, const int* abort_info,
+                                hipStream_t s)
+{
+    if (ntask <= 0) return hipSuccess;
+    const int nb = m / 128;
+    hipLaunchKernelGGL(k_update_reduce, dim3(ntask * nb * nb), dim3(256), 0, s, d_tasks, m,
+                       abort_info);
+    return hipGetLastError();
+}
+
 hipError_t launch_update_f64(const UpdateTask* d_tasks, int ntask, int m, const int* abort_info,
                              hipStream_t s)
 {

@@ -39,8 +39,13 @@ __device__ inline void update_block(const UpdateTask& tk, int bi, int bj, int m,
     const int wr = (wave / WC) * (BM / WR), wc = (wave % WC) * (BM / WC);
     const int lr = lane & 15, lk = lane >> 4;
 
+    // slice kt of the k range: tile kt / spt of the run, columns 16 (kt % spt) ..
+    const int spt = m / KB;
+    const long long kstride = tk.kstride;
+    auto koff = [&](int kt) { return (size_t)(kt / spt) * kstride + (size_t)(kt % spt) * KB; };
     double2 ra[NLD], rb[NLD];
-    auto gload = [&](int k0) {
+    auto gload = [&](int kt) {
+        const size_t k0 = koff(kt);
 #pragma unroll
         for (int q = 0; q < NLD; ++q) {
             const int e = tid + NT * q;
@@ -70,10 +75,10 @@ __device__ inline void update_block(const UpdateTask& tk, int bi, int bj, int m,
     gload(0);
     swrite(0);
     __syncthreads();
-    const int nk = m / KB;
+    const int nk = spt * tk.nk;
     for (int kt = 0; kt < nk; ++kt) {
         const int cur = kt & 1;
-        if (kt + 1 < nk) gload((kt + 1) * KB);
+        if (kt + 1 < nk) gload(kt + 1);
 #pragma unroll
         for (int kk = 0; kk < KB; kk += 4) {
             double a[TR], b[TC];
@@ -90,6 +95,20 @@ __device__ inline void update_block(const UpdateTask& tk, int bi, int bj, int m,
         __syncthreads();
     }
 
+    if (tk.part != nullptr) {
+        double* __restrict__ Pp = tk.part + (size_t)bi * BM * ldc + (size_t)bj * BM;
+#pragma unroll
+        for (int i = 0; i < TR; ++i)
+#pragma unroll
+            for (int j = 0; j < TC; ++j)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = wr + 16 * i + drow(lk, v);
+                    const int col = wc + 16 * j + lr;
+                    gst(Pp + (size_t)row * ldc + col, acc[i][j][v]);
+                }
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < TR; ++i)
 #pragma unroll

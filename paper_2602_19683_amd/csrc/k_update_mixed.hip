@@ -10,7 +10,10 @@
 // order, LDS double buffering. FP32: v_mfma_f32_16x16x4_f32, k-slices of 16, LDS k-major.
 // BF16: v_mfma_f32_16x16x32_bf16, k-slices of 32, LDS row-major (each lane
 // reads 8 consecutive bf16 of one row). Both FP32-accumulator layouts put
-// element v of lane l at row 4 (l / 16) + v, column l % 16.
+// element v of lane l at row 4 (l / 16) + v, column l % 16. A task may hold
+// several consecutive products (left-looking updates), accumulated in FP32
+// before the one subtraction from the FP64 tile, or write its sum as an FP64
+// part of a split update.
 #include "gpr_internal.h"
 #include "k_common.h"
 #include "k_update_mixed_dev.h"
@@ -65,8 +68,11 @@ __global__ __launch_bounds__(WR * WC * 64, WR * WC / 2) void k_update_bf16(
     const int wr = (wave / WC) * (BM / WR), wc = (wave % WC) * (BM / WC);
     const int lr = lane & 15, lk = lane >> 4;
 
+    const int spt = m / KB;
+    const long long kstride = tk.kstride;
     double2 ra[NLD], rb[NLD];
-    auto gload = [&](int k0) {
+    auto gload = [&](int kt) {
+        const size_t k0 = (size_t)(kt / spt) * kstride + (size_t)(kt % spt) * KB;
 #pragma unroll
         for (int q = 0; q < NLD; ++q) {
             const int e = tid + NT * q;
@@ -98,10 +104,10 @@ __global__ __launch_bounds__(WR * WC * 64, WR * WC / 2) void k_update_bf16(
     gload(0);
     swrite(0);
     __syncthreads();
-    const int nk = m / KB;
+    const int nk = spt * tk.nk;
     for (int kt = 0; kt < nk; ++kt) {
         const int cur = kt & 1;
-        if (kt + 1 < nk) gload((kt + 1) * KB);
+        if (kt + 1 < nk) gload(kt + 1);
         bf16x8 a[TR], b[TC];
 #pragma unroll
         for (int i = 0; i < TR; ++i)
@@ -116,6 +122,20 @@ __global__ __launch_bounds__(WR * WC * 64, WR * WC / 2) void k_update_bf16(
                 acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
         if (kt + 1 < nk) swrite(cur ^ 1);
         __syncthreads();
+    }
+    if (tk.part != nullptr) {
+        double* __restrict__ Pp = tk.part + (size_t)bi * BM * ldc + (size_t)bj * BM;
+#pragma unroll
+        for (int i = 0; i < TR; ++i)
+#pragma unroll
+            for (int j = 0; j < TC; ++j)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = wr + 16 * i + frow(lk, v);
+                    const int col = wc + 16 * j + lr;
+                    gst(Pp + (size_t)row * ldc + col, (double)acc[i][j][v]);
+                }
+        return;
     }
 #pragma unroll
     for (int i = 0; i < TR; ++i)

@@ -43,8 +43,12 @@ __device__ inline void update_block_f32(const UpdateTask& tk, int bi, int bj, in
     const int wr = (wave / WC) * (BM / WR), wc = (wave % WC) * (BM / WC);
     const int lr = lane & 15, lk = lane >> 4;
 
+    const int spt = m / KB;
+    const long long kstride = tk.kstride;
+    auto koff = [&](int kt) { return (size_t)(kt / spt) * kstride + (size_t)(kt % spt) * KB; };
     double2 ra[NLD], rb[NLD];
-    auto gload = [&](int k0) {
+    auto gload = [&](int kt) {
+        const size_t k0 = koff(kt);
 #pragma unroll
         for (int q = 0; q < NLD; ++q) {
             const int e = tid + NT * q;
@@ -73,10 +77,10 @@ __device__ inline void update_block_f32(const UpdateTask& tk, int bi, int bj, in
     gload(0);
     swrite(0);
     __syncthreads();
-    const int nk = m / KB;
+    const int nk = spt * tk.nk;
     for (int kt = 0; kt < nk; ++kt) {
         const int cur = kt & 1;
-        if (kt + 1 < nk) gload((kt + 1) * KB);
+        if (kt + 1 < nk) gload(kt + 1);
 #pragma unroll
         for (int kk = 0; kk < KB; kk += 4) {
             float a[TR], b[TC];
@@ -92,6 +96,20 @@ __device__ inline void update_block_f32(const UpdateTask& tk, int bi, int bj, in
         }
         if (kt + 1 < nk) swrite(cur ^ 1);
         __syncthreads();
+    }
+    if (tk.part != nullptr) {
+        double* __restrict__ Pp = tk.part + (size_t)bi * BM * ldc + (size_t)bj * BM;
+#pragma unroll
+        for (int i = 0; i < TR; ++i)
+#pragma unroll
+            for (int j = 0; j < TC; ++j)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = wr + 16 * i + frow(lk, v);
+                    const int col = wc + 16 * j + lr;
+                    gst(Pp + (size_t)row * ldc + col, (double)acc[i][j][v]);
+                }
+        return;
     }
 #pragma unroll
     for (int i = 0; i < TR; ++i)

@@ -28,6 +28,8 @@ def _check(status, where):
     if status != GPR_OK:
         raise GPRError(status, where)
 
+_VARIANTS = {"right": 0, "left": 1}
+
 
 def _hyper(h):
     if isinstance(h, Hyper):
@@ -113,13 +115,21 @@ class Tiled:
 class Context:
     """A libgpr context on one GPU (streams, events, workspace)."""
 
-    def __init__(self, device=0, n_streams=3, executor=GPR_EXEC_STREAMS):
+    def __init__(self, device=0, n_streams=3, executor=GPR_EXEC_STREAMS, variant="right"):
         self._lib = _lib.load()
         h = ctypes.c_void_p()
         _check(self._lib.gpr_ctx_create(ctypes.byref(h), int(device), int(n_streams),
                                         int(executor)), "gpr_ctx_create")
         self._h = h
         self.device = device
+        self.set_variant(variant)
+
+    def set_variant(self, variant):
+        """Task order of the factorisations: "right" (right-looking, Fig. 1)
+        or "left" (left-looking)."""
+        v = _VARIANTS[variant] if isinstance(variant, str) else int(variant)
+        _check(self._lib.gpr_ctx_set_variant(self._h, v), "gpr_ctx_set_variant")
+        self.variant = variant
 
     def close(self):
         if self._h:
@@ -373,12 +383,30 @@ def _dev_ptr_int(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def schedule_describe(M, Mhat, mode):
+def schedule_describe(M, Mhat, mode, variant=None):
     """Host-only: the batched launch list of the tile sweep (see gpr.h).
 
     Returns ``(tasks, launches)``: int32 arrays of shape (T, 5) = (kind, I, K,
-    J, launch) and (L, 5) = (stream, wait0, wait1, wait2, launch kind)."""
+    J, launch) and (L, 5) = (stream, wait0, wait1, wait2, launch kind). With
+    a variant (0 / "right", 1 / "left"): tasks of shape (T, 6) = (kind, I, K,
+    J, nk, launch), an update task holding the products of columns
+    J .. J + nk - 1."""
     lib = _lib.load()
+    if variant is not None:
+        v = _VARIANTS[variant] if isinstance(variant, str) else int(variant)
+        nt = ctypes.c_int64()
+        nl = ctypes.c_int64()
+        st = lib.gpr_schedule_describe_variant(M, Mhat, mode, v, None, 0, ctypes.byref(nt), None,
+                                               0, ctypes.byref(nl))
+        if st not in (GPR_OK, _lib.GPR_EINVAL) or nt.value < 0:
+            raise GPRError(st, "gpr_schedule_describe_variant")
+        tasks = np.zeros((nt.value, 6), dtype=np.int32)
+        launches = np.zeros((nl.value, 5), dtype=np.int32)
+        _check(lib.gpr_schedule_describe_variant(
+            M, Mhat, mode, v, tasks.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), nt.value,
+            ctypes.byref(nt), launches.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), nl.value,
+            ctypes.byref(nl)), "gpr_schedule_describe_variant")
+        return tasks, launches
     nt = ctypes.c_int64()
     nl = ctypes.c_int64()
     st = lib.gpr_schedule_describe(M, Mhat, mode, None, 0, ctypes.byref(nt), None, 0,

@@ -2,7 +2,8 @@
 
 n = 16384 training points, n_test = 4096, D = 8, tile 512, FP64, through the
 fused call the benchmark times (gpr_fit_predict: assembly, factorisation and
-covariance rows in one sweep), on both executors. The oracle computes the
+covariance rows in one sweep), on both executors, and in the left-looking
+task order. The oracle computes the
 plain definitions (Sec. 4.1, eqs. (1)-(3)) on the host cores once for the
 module (about a minute on 16 cores, about 6 GB of host memory).
 
@@ -49,14 +50,15 @@ def host(t):
 
 
 @pytest.mark.timeout(900)
-@pytest.mark.parametrize("executor", ["streams", "persistent"])
+@pytest.mark.parametrize("executor", ["streams", "persistent", "streams-left"])
 def test_c3_fused_fp64_matches_oracle(data, executor):
     from paper_2602_19683_amd import GPR_EXEC_PERSISTENT, GPR_EXEC_STREAMS, Context
     X, y, Xs, ref = data
     say(f"gpr_fit_predict fp64 n={N} n_test={NS} tile={TILE} executor={executor}")
     ex = GPR_EXEC_PERSISTENT if executor == "persistent" else GPR_EXEC_STREAMS
+    variant = "left" if executor.endswith("left") else "right"
     dev = lambda a: torch.from_numpy(a).to("cuda:0")
-    with Context(0, executor=ex) as ctx:
+    with Context(0, executor=ex, variant=variant) as ctx:
         Xd, yd, Xsd = dev(X), dev(y), dev(Xs)
         info = torch.full((1,), -7, dtype=torch.int32, device="cuda:0")
         mean_d, cov_d, K = ctx.fit_predict(Xd, yd, Xsd, DEFAULT_HYPER, TILE, "fp64", info=info)
