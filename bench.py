@@ -249,6 +249,153 @@ def mixed_mid_run(ctx, args, log):
     return out
 
 
+def timed_calls(fn, steps, warm=1):
+    """Mean ms per call of fn() over `steps` calls after `warm` untimed ones
+    (device time between two events on the current stream)."""
+    import torch
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def left_looking_run(Xd, yd, Xsd, h, tile, ms64, mean64, cov64, flops, args, log):
+    """The left-looking task order: the benchmarked FP64 step and the FP32 /
+    BF16 forms at the same size, and the three precisions at n = 8192,
+    n_test = 2048, tile 256; errors against the right-looking FP64 results."""
+    import torch
+    from gpr_inputs import DEFAULT_HYPER, nfir_train_test
+    from paper_2602_19683_amd import Context
+    rel = lambda a, b: float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
+    out = {}
+    ctx = Context(0, variant="left")
+    ns = Xsd.shape[0]
+    mean = torch.empty_like(mean64)
+    cov = torch.empty_like(cov64)
+    K = None
+    for prec in ("fp64", "fp32", "bf16"):
+        st = {}
+
+        def call():
+            nonlocal K
+            _, _, K, s_ = ctx.fit_predict(Xd, yd, Xsd, h, tile, prec, K=K, mean=mean, cov=cov,
+                                          ir_stats=True)
+            st.update(s_)
+        ms = timed_calls(call, args.steps)
+        ctx.sync()
+        out[prec] = {"ms_per_step": round(ms, 4), "value": round(flops / (ms * 1e-3) / 1e9, 2),
+                     "vs_right_looking_fp64": round(ms64 / ms, 3),
+                     "rel_mean_vs_fp64": rel(mean, mean64), "rel_cov_vs_fp64": rel(cov, cov64)}
+        if prec != "fp64":
+            out[prec].update({"precision_used": {0: "fp64", 1: "fp32", 2: "bf16"}[st["precision"]],
+                              "refinement": st["method"], "refinement_steps": st["iters"]})
+        log(f"left-looking {prec}: {out[prec]}")
+    K.free()
+    n2, ns2, tile2 = 8192, 2048, 256
+    X, y, Xs = nfir_train_test(n2, ns2)
+    d = lambda a: torch.from_numpy(a).to("cuda:0")
+    X2, y2, Xs2 = d(X), d(y), d(Xs)
+    mid = {}
+    ref = None
+    for variant in ("right", "left"):
+        ctx.set_variant(variant)
+        for prec in ("fp64", "fp32", "bf16"):
+            m2 = torch.empty(ns2, dtype=torch.float64, device="cuda:0")
+            c2 = torch.empty(ns2, ns2, dtype=torch.float64, device="cuda:0")
+            K2 = None
+            st = {}
+
+            def call2():
+                nonlocal K2
+                _, _, K2, s_ = ctx.fit_predict(X2, y2, Xs2, DEFAULT_HYPER, tile2, prec, K=K2,
+                                               mean=m2, cov=c2, ir_stats=True)
+                st.update(s_)
+            ms = timed_calls(call2, args.steps)
+            ctx.sync()
+            r = {"ms_per_call": round(ms, 4)}
+            if ref is None:
+                ref = (m2.clone(), c2.clone())
+            else:
+                r.update({"rel_mean_vs_fp64": rel(m2, ref[0]), "rel_cov_vs_fp64": rel(c2, ref[1])})
+            if prec != "fp64":
+                r.update({"precision_used": {0: "fp64", 1: "fp32", 2: "bf16"}[st["precision"]],
+                          "refinement": st["method"], "refinement_steps": st["iters"]})
+            mid[f"{variant}_{prec}"] = r
+            K2.free()
+    mid["config"] = f"n={n2}, n_test={ns2}, D=8, tile {tile2}, (l, v, sigma^2) = {DEFAULT_HYPER}"
+    out["n8192_tile256"] = mid
+    log(f"left-looking at n=8192: {mid}")
+    ctx.close()
+    return out
+
+
+def sweep_runs(args, log):
+    """Smaller configurations: n = 4096, n_test = 1024 over tiles 128 / 256 /
+    512 (time per fused FP64 call, and the assembly and factorisation-sweep
+    parts from the per-launch timers), and the latency of n = 128,
+    n_test = 128, tile 32 in microseconds."""
+    import torch
+    from gpr_inputs import DEFAULT_HYPER, nfir_train_test
+    from paper_2602_19683_amd import Context
+    d = lambda a: torch.from_numpy(a).to("cuda:0")
+    out = {}
+    n, ns = 4096, 1024
+    X, y, Xs = nfir_train_test(n, ns)
+    Xd, yd, Xsd = d(X), d(y), d(Xs)
+    with Context(0) as ctx:
+        for tile in (128, 256, 512):
+            mean = torch.empty(ns, dtype=torch.float64, device="cuda:0")
+            cov = torch.empty(ns, ns, dtype=torch.float64, device="cuda:0")
+            K = None
+
+            def call():
+                nonlocal K
+                K = ctx.fit_predict(Xd, yd, Xsd, DEFAULT_HYPER, tile, "fp64", K=K, mean=mean,
+                                    cov=cov)[2]
+            ms = timed_calls(call, max(args.steps, 10))
+            ctx.profile(True)
+            ctx.profile_read(reset=True)
+            reps = max(args.steps, 10)
+            for _ in range(reps):
+                call()
+            prof = ctx.profile_read(reset=True)
+            ctx.profile(False)
+            part = lambda *ks: round(sum(prof[k][1] for k in ks) / reps, 4)
+            out[f"tile{tile}"] = {
+                "ms_per_call": round(ms, 4),
+                "gflops": round(path_flops(n, ns) / (ms * 1e-3) / 1e9, 1),
+                "assembly_ms": part("assemble"),
+                "sweep_kernels_ms": part("potrf", "trsm", "update"),
+                "solves_mean_export_ms": part("trtri", "trsv", "matvec", "export")}
+            K.free()
+        out["c2_config"] = f"n={n}, n_test={ns}, D=8, fp64, gpr_fit_predict; kernel times are " \
+                           f"sums over launches (the streams overlap)"
+        X1, y1, Xs1 = nfir_train_test(128, 128)
+        X1d, y1d, Xs1d = d(X1), d(y1), d(Xs1)
+        mean = torch.empty(128, dtype=torch.float64, device="cuda:0")
+        cov = torch.empty(128, 128, dtype=torch.float64, device="cuda:0")
+        K = None
+
+        def small():
+            nonlocal K
+            K = ctx.fit_predict(X1d, y1d, Xs1d, DEFAULT_HYPER, 32, "fp64", K=K, mean=mean,
+                                cov=cov)[2]
+        ms = timed_calls(small, 50, warm=5)
+        out["c1_latency_us"] = round(ms * 1e3, 1)
+        out["c1_config"] = "n=128, n_test=128, D=8, tile 32, fp64, gpr_fit_predict (mean + full " \
+                           "covariance), mean of 50 calls"
+        K.free()
+    log(f"sweeps: {out}")
+    return out
+
+
 def variants_run(ctx, K, Xd, yd, Xsd, h, tile, args, log):
     """The prediction variants of the same fit (FP64, one fused call each):
     mean only (no test rows swept) and mean + predictive variances (V^T
@@ -435,6 +582,12 @@ def main():
                     help="skip the mean-only and mean + variance timings")
     ap.add_argument("--executor", default="streams", choices=["streams", "persistent"],
                     help="executor of the timed line (persistent: one launch per sweep)")
+    ap.add_argument("--variant", default="right", choices=["right", "left"],
+                    help="task order of the timed line (right- or left-looking Cholesky)")
+    ap.add_argument("--no-left", action="store_true",
+                    help="skip the left-looking timings after the line")
+    ap.add_argument("--no-sweeps", action="store_true",
+                    help="skip the n = 4096 tile sweep and the n = 128 latency")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run one device-to-device copy of MIB MiB (for HBM counter scaling)")
     args = ap.parse_args()
@@ -468,7 +621,8 @@ def main():
     cov = torch.empty(ns, ns, dtype=torch.float64, device="cuda:0")
     persistent_line = args.executor == "persistent"
     ctx = Context(0, n_streams=args.streams,
-                  executor=GPR_EXEC_PERSISTENT if persistent_line else GPR_EXEC_STREAMS)
+                  executor=GPR_EXEC_PERSISTENT if persistent_line else GPR_EXEC_STREAMS,
+                  variant=args.variant)
     K = ctx.assemble(Xd, h, tile)
 
     def step(prec=args.precision, out_mean=mean, out_cov=cov):
@@ -563,6 +717,13 @@ def main():
     nlml = None
     if not args.no_nlml:
         nlml = nlml_run(ctx, args, log)
+    left = None
+    if not args.no_left and args.precision == "fp64" and args.path == "fused" \
+            and args.variant == "right" and not persistent_line:
+        left = left_looking_run(Xd, yd, Xsd, h, tile, ms, mean, cov, flops, args, log)
+    sweeps = None
+    if not args.no_sweeps:
+        sweeps = sweep_runs(args, log)
     del ref
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": "GFLOP/s", "n_gpus": 1,
@@ -578,7 +739,7 @@ def main():
                    "n": n, "n_test": ns, "D": D, "tile": tile, "precision": args.precision,
                    "entry": "gpr_fit_predict" if args.path == "fused" else
                             "gpr_assemble + gpr_cholesky + gpr_predict",
-                   "executor": args.executor,
+                   "executor": args.executor, "variant": args.variant,
                    "parallelism": "single GPU"},
         "pct_fp64_peak": round(100 * value / (FP64_PEAK_TFLOPS * 1e3), 2),
         "roofline": roofline,
@@ -589,6 +750,8 @@ def main():
         "prediction_variants": variants,
         "library_comparator": library,
         "nlml_grad": nlml,
+        "left_looking": left,
+        "sweeps": sweeps,
         "phases_ms_per_step": {k: round(v[1] / args.steps, 4) for k, v in prof.items()},
         "lib_source_hash": _lib.library_hash(),
     }
