@@ -396,6 +396,68 @@ def sweep_runs(args, log):
     return out
 
 
+def large_run(args, log):
+    """The large configuration: n = 32768, n_test = 8192, D = 8, tile 1024.
+    FP32-update factorisation with FP64 refinement and the full covariance
+    (one fused call), and the FP64 NLML with its gradient, on the stream
+    executor and on the persistent executor; errors of the mixed mean and
+    covariance against the FP64 streams result of the same run."""
+    import torch
+    from gpr_inputs import DEFAULT_HYPER, nfir_train_test
+    from paper_2602_19683_amd import GPR_EXEC_PERSISTENT, GPR_EXEC_STREAMS, Context
+    n, ns, tile = 32768, 8192, 1024
+    X, y, Xs = nfir_train_test(n, ns)
+    d = lambda a: torch.from_numpy(a).to("cuda:0")
+    Xd, yd, Xsd = d(X), d(y), d(Xs)
+    rel = lambda a, b: float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
+    out, ref = {}, None
+    steps = max(1, min(args.steps, 3))
+    for name, ex in (("streams", GPR_EXEC_STREAMS), ("persistent", GPR_EXEC_PERSISTENT)):
+        with Context(0, executor=ex) as ctx:
+            r = {}
+            for prec in ("fp64", "fp32"):
+                mean = torch.empty(ns, dtype=torch.float64, device="cuda:0")
+                cov = torch.empty(ns, ns, dtype=torch.float64, device="cuda:0")
+                K = None
+                st = {}
+
+                def call():
+                    nonlocal K
+                    _, _, K, s_ = ctx.fit_predict(Xd, yd, Xsd, DEFAULT_HYPER, tile, prec, K=K,
+                                                  mean=mean, cov=cov, ir_stats=True)
+                    st.update(s_)
+                ms = timed_calls(call, steps)
+                ctx.sync()
+                r[prec] = {"ms_per_call": round(ms, 2),
+                           "gflops": round(path_flops(n, ns) / (ms * 1e-3) / 1e9, 1)}
+                if ref is None:
+                    ref = (mean.clone(), cov.clone())
+                else:
+                    r[prec].update({"rel_mean_vs_fp64_streams": rel(mean, ref[0]),
+                                    "rel_cov_vs_fp64_streams": rel(cov, ref[1])})
+                if prec != "fp64":
+                    r[prec].update({"precision_used": {0: "fp64", 1: "fp32", 2: "bf16"}[st["precision"]],
+                                    "refinement": st["method"], "refinement_steps": st["iters"]})
+                K.free()
+                del mean, cov
+                torch.cuda.empty_cache()
+                log(f"large {name} {prec}: {r[prec]}")
+            res = {}
+
+            def nl():
+                res["v"] = ctx.nlml_grad(Xd, yd, DEFAULT_HYPER, tile)
+            ms = timed_calls(nl, 1)
+            ctx.sync()
+            r["nlml_grad_ms"] = round(ms, 2)
+            r["nlml"] = float(res["v"][0].cpu()[0])
+            r["grad"] = [float(v) for v in res["v"][1].cpu()]
+            log(f"large {name} nlml+grad: {ms:.1f} ms")
+            out[name] = r
+            torch.cuda.empty_cache()
+    out["config"] = f"n={n}, n_test={ns}, D=8, tile {tile}, (l, v, sigma^2) = {DEFAULT_HYPER}"
+    return out
+
+
 def variants_run(ctx, K, Xd, yd, Xsd, h, tile, args, log):
     """The prediction variants of the same fit (FP64, one fused call each):
     mean only (no test rows swept) and mean + predictive variances (V^T
@@ -541,7 +603,8 @@ def nlml_run(ctx, args, log):
         else:
             out["ms_nlml_only"] = round(ms, 4)
     # the hyperparameter fit (gpr_fit_hyper): Adam steps, each one NLML and
-    # gradient evaluation plus the host-side step and one synchronisation
+    # gradient evaluation plus the Adam step on the device (the host reads the
+    # stop flag every few steps)
     import time
     ctx.fit_hyper(Xd, yd, h, tile, max_steps=1)
     t0 = time.perf_counter()
@@ -588,6 +651,9 @@ def main():
                     help="skip the left-looking timings after the line")
     ap.add_argument("--no-sweeps", action="store_true",
                     help="skip the n = 4096 tile sweep and the n = 128 latency")
+    ap.add_argument("--large", action="store_true",
+                    help="only the n = 32768, n_test = 8192, tile 1024 runs (streams vs "
+                         "persistent; FP32-update prediction and the NLML gradient)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run one device-to-device copy of MIB MiB (for HBM counter scaling)")
     args = ap.parse_args()
@@ -606,6 +672,9 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         log(f"copied {args.calibrate_copy} MiB (read {args.calibrate_copy} MiB, write {args.calibrate_copy} MiB)")
+        return
+    if args.large:
+        print(json.dumps({"large": large_run(args, log)}), flush=True)
         return
     from gpr_inputs import DEFAULT_HYPER, nfir_train_test
     from paper_2602_19683_amd import GPR_EXEC_PERSISTENT, GPR_EXEC_STREAMS, Context, _lib
