@@ -73,7 +73,9 @@ def build(verbose: bool = False) -> str:
         with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
             list(ex.map(lambda so: _compile(so[0], so[1], verbose, digest), zip(srcs, objs)))
         out_tmp = LIB + ".tmp"
-        cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", out_tmp]
+        # roctx: the marker ranges of each entry point and launch group
+        cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", out_tmp,
+               "-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx"]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)

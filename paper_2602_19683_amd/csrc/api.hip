@@ -24,6 +24,8 @@
 #include <new>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "gpr_internal.h"
 
 using namespace gpr;
@@ -284,15 +286,30 @@ hipEvent_t timing_event(gpr_ctx* ctx)
     return ctx->tpool[ctx->tpool_used++];
 }
 
-// Brackets one launch with timing events while profiling is on.
+const char* const kProfName[PK_COUNT] = {"potrf", "trtri", "trsm", "update", "assemble", "trsv",
+                                         "matvec", "export", "adjoint", "reduce", "persist"};
+
+// A host-side range in a tool's marker trace (roctx; no cost without a tool):
+// one per entry point and one per launch group (ProfScope), so a trace shows
+// the phases of a call.
+struct Range {
+    explicit Range(const char* name) { roctxRangePushA(name); }
+    ~Range() { roctxRangePop(); }
+    Range(const Range&) = delete;
+    Range& operator=(const Range&) = delete;
+};
+
+// Brackets one launch with timing events while profiling is on, and with a
+// marker range named for its kind.
 struct ProfScope {
     gpr_ctx* c;
     hipStream_t s;
     int kind;
     double flops, bytes;
     hipEvent_t a = nullptr;
+    Range range;
     ProfScope(gpr_ctx* c_, hipStream_t s_, int k, double f, double b)
-        : c(c_), s(s_), kind(k), flops(f), bytes(b)
+        : c(c_), s(s_), kind(k), flops(f), bytes(b), range(kProfName[k])
     {
         if (c->prof_on && (a = timing_event(c)) != nullptr) (void)hipEventRecord(a, s);
     }
@@ -553,8 +570,9 @@ int run_sweep(gpr_ctx* ctx, const SweepMats& X, const SweepPlan& P, const DescBu
     std::vector<char> fused(Ls.size(), 0);      // TRSM launch run inside the POTRF before it
     std::vector<unsigned> signal(Ls.size(), 0); // value to signal after this launch (0: none)
     std::vector<unsigned> ready(Ls.size(), 0);  // POTRF launch: value its TRSM strips wait for
-    // In FP64, the one-tile SYRK that precedes a POTRF on its stream (the last
-    // update of the diagonal tile) is applied by the POTRF's own workgroups.
+    // In FP64 and FP32-update sweeps, the one-tile SYRK that precedes a POTRF
+    // on its stream (the last update of the diagonal tile) is applied by the
+    // POTRF's own workgroups, in the sweep's update arithmetic.
     std::vector<int> syrk_of(Ls.size(), -1);    // POTRF launch: the SYRK launch it absorbs
     std::vector<char> absorbed(Ls.size(), 0);   // SYRK launch issued with a later POTRF
     {
@@ -563,7 +581,8 @@ int run_sweep(gpr_ctx* ctx, const SweepMats& X, const SweepPlan& P, const DescBu
             const SchedLaunch& L = Ls[li];
             const int pv = last_on[L.stream];
             last_on[L.stream] = (int)li;
-            if (L.kind != LK_POTRF || pv < 0 || X.prec != GPR_FP64) continue;
+            if (L.kind != LK_POTRF || pv < 0) continue;
+            if (X.prec != GPR_FP64 && X.prec != GPR_MIXED_FP32) continue;
             const SchedLaunch& S = Ls[pv];
             if (S.kind != LK_UPDATE || S.count != 1) continue;
             const SchedTask& t = P.sched.tasks[S.first];
@@ -632,11 +651,13 @@ int run_sweep(gpr_ctx* ctx, const SweepMats& X, const SweepPlan& P, const DescBu
                 HIP_TRY(launch_potrf_trsm_f64(A, m, m, Ti, m, ctx->d_info, (int64_t)J * m,
                                               ctx->d_flags, ++ctx->epoch, ctx->d_info + 2,
                                               db.dev<TrsmTask>(ctx, P.off[li + 1]),
-                                              ready[li] ? sigflag : nullptr, ready[li], st, syrk));
+                                              ready[li] ? sigflag : nullptr, ready[li], st, syrk,
+                                              X.prec == GPR_MIXED_FP32));
             } else {
                 ProfScope ps(ctx, st, PK_POTRF, m3 / 3.0 + fs, 0.0);
                 HIP_TRY(launch_potrf_f64(A, m, m, Ti, m, ctx->d_info, (int64_t)J * m,
-                                         ctx->d_flags, ++ctx->epoch, ctx->d_info + 2, st, syrk));
+                                         ctx->d_flags, ++ctx->epoch, ctx->d_info + 2, st, syrk,
+                                         X.prec == GPR_MIXED_FP32));
             }
             if (syrk_of[li] >= 0 && waited[syrk_of[li]])
                 HIP_TRY(hipEventRecord(ctx->evpool[syrk_of[li]], st));
@@ -1018,6 +1039,7 @@ int gpr_ctx_destroy(gpr_ctx* c)
 int gpr_assemble(gpr_ctx* ctx, const double* X, int64_t n, int32_t D, gpr_hyper h, int32_t tile,
                  gpr_tiled** K_inout, void* stream)
 {
+    Range range("gpr_assemble");
     if (!ctx || !X || !K_inout || n < 1 || D < 1 || !valid_tile(tile) || !valid_hyper(h))
         return GPR_EINVAL;
     if (*K_inout && ((*K_inout)->n != n || (*K_inout)->m != tile)) return GPR_EINVAL;
@@ -1048,6 +1070,7 @@ int gpr_assemble(gpr_ctx* ctx, const double* X, int64_t n, int32_t D, gpr_hyper 
 
 int gpr_cholesky(gpr_ctx* ctx, gpr_tiled* K, gpr_precision prec, int32_t* info_dev, void* stream)
 {
+    Range range("gpr_cholesky");
     if (!ctx || !K || K->state != GPR_STATE_K || K->device != ctx->device) return GPR_EINVAL;
     if (!valid_prec(prec, K->m)) return GPR_EINVAL;
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -1089,6 +1112,7 @@ int gpr_cholesky(gpr_ctx* ctx, gpr_tiled* K, gpr_precision prec, int32_t* info_d
 int gpr_cholesky_dense(gpr_ctx* ctx, double* A, int64_t n, int32_t tile, gpr_precision prec,
                        int32_t* info_dev, void* stream)
 {
+    Range range("gpr_cholesky_dense");
     if (!ctx || !A || n < 1 || !valid_tile(tile) || !valid_prec(prec, tile)) return GPR_EINVAL;
     hipStream_t s = static_cast<hipStream_t>(stream);
     int rc = begin_call(ctx, s);
@@ -1469,6 +1493,7 @@ int gpr_predict_var(gpr_ctx* ctx, gpr_tiled* L, const double* X, const double* y
                     const double* Xs, int64_t n_test, int32_t D, gpr_hyper h, double* mean,
                     double* cov, double* var, gpr_ir_stats* ir, void* stream)
 {
+    Range range("gpr_predict_var");
     if (!ctx || !L || !X || !y || n < 1 || D < 1 || n_test < 0 || !valid_hyper(h))
         return GPR_EINVAL;
     if (L->state != GPR_STATE_L || L->n != n || L->device != ctx->device) return GPR_EINVAL;
@@ -1487,6 +1512,7 @@ int gpr_predict(gpr_ctx* ctx, gpr_tiled* L, const double* X, const double* y, in
                 const double* Xs, int64_t n_test, int32_t D, gpr_hyper h, double* mean,
                 double* cov, gpr_ir_stats* ir, void* stream)
 {
+    Range range("gpr_predict");
     return gpr_predict_var(ctx, L, X, y, n, Xs, n_test, D, h, mean, cov, nullptr, ir, stream);
 }
 
@@ -1495,6 +1521,7 @@ int gpr_fit_predict_var(gpr_ctx* ctx, const double* X, const double* y, int64_t 
                         gpr_precision prec, gpr_tiled** K_inout, double* mean, double* cov,
                         double* var, int32_t* info_dev, gpr_ir_stats* ir, void* stream)
 {
+    Range range("gpr_fit_predict_var");
     if (!ctx || !X || !y || !K_inout || n < 1 || D < 1 || n_test < 1 || !Xs || !mean ||
         !valid_tile(tile) || !valid_hyper(h) || !valid_prec(prec, tile))
         return GPR_EINVAL;
@@ -1525,12 +1552,14 @@ int gpr_fit_predict(gpr_ctx* ctx, const double* X, const double* y, int64_t n, c
                     gpr_tiled** K_inout, double* mean, double* cov, int32_t* info_dev,
                     gpr_ir_stats* ir, void* stream)
 {
+    Range range("gpr_fit_predict");
     return gpr_fit_predict_var(ctx, X, y, n, Xs, n_test, D, h, tile, prec, K_inout, mean, cov,
                                nullptr, info_dev, ir, stream);
 }
 
 int gpr_solve(gpr_ctx* ctx, gpr_tiled* L, const double* b, double* x, void* stream)
 {
+    Range range("gpr_solve");
     if (!ctx || !L || !b || !x || L->state != GPR_STATE_L || L->device != ctx->device)
         return GPR_EINVAL;
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -1577,6 +1606,7 @@ int gpr_nlml_grad(gpr_ctx* ctx, const double* X, const double* y, int64_t n, int
                   gpr_hyper h, int32_t tile, gpr_precision prec, double* out_nlml,
                   double* out_grad3, double* out_Kbar, void* stream)
 {
+    Range range("gpr_nlml_grad");
     if (!ctx || !X || !y || n < 1 || D < 1 || !valid_tile(tile) || !valid_hyper(h) || !out_nlml)
         return GPR_EINVAL;
     if (!valid_prec(prec, tile)) return GPR_EINVAL;
@@ -1631,6 +1661,7 @@ int gpr_tiled_info(const gpr_tiled* T, int64_t* n, int32_t* tile, int32_t* state
 
 int gpr_tiled_to_dense(gpr_ctx* ctx, const gpr_tiled* T, double* out, void* stream)
 {
+    Range range("gpr_tiled_to_dense");
     if (!ctx || !T || !out || T->state == GPR_STATE_EMPTY || T->device != ctx->device)
         return GPR_EINVAL;
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -1661,6 +1692,7 @@ int gpr_fit_hyper(gpr_ctx* ctx, const double* X, const double* y, int64_t n, int
                   double beta2, double eps, double tol, double* theta_out, double* nlml_trace,
                   int32_t* steps_done, void* stream)
 {
+    Range range("gpr_fit_hyper");
     if (!ctx || !X || !y || n < 1 || D < 1 || !valid_tile(tile) || !theta0 || !theta_out ||
         max_steps < 1 || !(lr > 0) || !(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) ||
         !(eps >= 0) || !(tol >= 0))

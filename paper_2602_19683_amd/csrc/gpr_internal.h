@@ -148,10 +148,11 @@ hipError_t launch_trsm_f64(const TrsmTask* d_tasks, int ntask, int m, const int*
 // flags[0 .. 2 m/32) (set to `epoch` as parts of a row panel are done; epoch
 // must differ from every value the flags hold). *err is set if a wait hits
 // its limit. syrk (nullable): an m x m tile S (ld m); A -= S S^T is applied
-// first, by the POTRF's own workgroups (the tile's last SYRK update).
+// first, by the POTRF's own workgroups (the tile's last SYRK update; FP32
+// operands and accumulation if syrk_f32).
 hipError_t launch_potrf_f64(double* A, int lda, int m, double* Tinv, int ldt, int* info,
                             int64_t col_base, unsigned* flags, unsigned epoch, int* err,
-                            hipStream_t s, const double* syrk = nullptr);
+                            hipStream_t s, const double* syrk = nullptr, bool syrk_f32 = false);
 // POTRF of one diagonal tile and the TRSM task *trsm (the tile below it) in
 // one launch, the TRSM strips following the POTRF row panels (2 m/32
 // workgroups). ready (nullable): the strips first wait until *ready ==
@@ -160,7 +161,7 @@ hipError_t launch_potrf_f64(double* A, int lda, int m, double* Tinv, int ldt, in
 hipError_t launch_potrf_trsm_f64(double* A, int lda, int m, double* Tinv, int ldt, int* info,
                                  int64_t col_base, unsigned* flags, unsigned epoch, int* err,
                                  const TrsmTask* trsm, const unsigned* ready, unsigned ready_val,
-                                 hipStream_t s, const double* syrk = nullptr);
+                                 hipStream_t s, const double* syrk = nullptr, bool syrk_f32 = false);
 // *flag = v (release, device scope) once the launches before it on s are done.
 hipError_t launch_signal(unsigned* flag, unsigned v, hipStream_t s);
 // Inverses of the M factored diagonal tiles (J, J) of the lower-tiled K;

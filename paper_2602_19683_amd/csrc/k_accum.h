@@ -89,4 +89,64 @@ __device__ inline dbl4 accum32(const double* __restrict__ A, int lda, const doub
     return acc;
 }
 
+typedef float flt4a __attribute__((ext_vector_type(4)));
+
+// The 32 x 32 block product of accum32<true, KC, true> (B(k, j) = B[j * ldb + k])
+// with both operands rounded to FP32 and FP32-accumulator MFMAs
+// (v_mfma_f32_16x16x4_f32), one chain in k order from zero: the arithmetic
+// of an FP32 tile-update block. Element v of a lane is row 4 (lane / 16) + v
+// of its quadrant (the FP32-accumulator layout).
+template <int KC>
+__device__ inline flt4a accum32_f32(const double* __restrict__ A, int lda,
+                                    const double* __restrict__ B, int ldb, int K,
+                                    double (*As)[KC][36], double (*Bs)[KC][36], int tid)
+{
+    static_assert(KC % 16 == 0, "chunk must hold whole double2 loads");
+    constexpr int NL = KC / 16;
+    constexpr int CPR = KC / 2;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int qi = wave >> 1, qj = wave & 1;
+    double2 ra[NL], rb[NL];
+    auto gload = [&](int k0) {
+#pragma unroll
+        for (int u = 0; u < NL; ++u) {
+            const int e = tid + 256 * u;
+            const int r = e / CPR, c = (e % CPR) * 2;
+            ra[u] = gld2(A + (size_t)r * lda + k0 + c);
+            rb[u] = gld2(B + (size_t)r * ldb + k0 + c);
+        }
+    };
+    auto swrite = [&](int buf) {
+#pragma unroll
+        for (int u = 0; u < NL; ++u) {
+            const int e = tid + 256 * u;
+            const int r = e / CPR, c = (e % CPR) * 2;
+            As[buf][c][r] = ra[u].x;
+            As[buf][c + 1][r] = ra[u].y;
+            Bs[buf][c][r] = rb[u].x;
+            Bs[buf][c + 1][r] = rb[u].y;
+        }
+    };
+    flt4a acc = {0.f, 0.f, 0.f, 0.f};
+    const int nk = K / KC;
+    if (nk == 0) return acc;
+    __syncthreads();  // LDS buffers free
+    gload(0);
+    swrite(0);
+    __syncthreads();
+    for (int kt = 0; kt < nk; ++kt) {
+        const int cur = kt & 1;
+        if (kt + 1 < nk) gload((kt + 1) * KC);
+#pragma unroll
+        for (int kk = 0; kk < KC; kk += 4)
+            acc = __builtin_amdgcn_mfma_f32_16x16x4f32((float)As[cur][kk + lk][16 * qi + lr],
+                                                       (float)Bs[cur][kk + lk][16 * qj + lr], acc,
+                                                       0, 0, 0);
+        if (kt + 1 < nk) swrite(cur ^ 1);
+        __syncthreads();
+    }
+    return acc;
+}
+
 }  // namespace gpr

@@ -37,7 +37,7 @@ __global__ __launch_bounds__(256) void k_potrf_f64(double* __restrict__ A, int l
                                                    int* __restrict__ info, int64_t col_base,
                                                    unsigned* __restrict__ flags, unsigned epoch,
                                                    int* __restrict__ err,
-                                                   const double* __restrict__ syrk)
+                                                   const double* __restrict__ syrk, int syrk_f32)
 {
     // a pivot already failed in an earlier tile: nothing of this factorisation
     // is used any more. Failures of this launch are recorded as columns
@@ -48,7 +48,7 @@ __global__ __launch_bounds__(256) void k_potrf_f64(double* __restrict__ A, int l
     }
     __shared__ PotrfLds sh;
     potrf_panel(A, lda, m, Tinv, ldt, info, col_base, flags, epoch, err, blockIdx.x, sh,
-                threadIdx.x, syrk);
+                threadIdx.x, syrk, syrk_f32 != 0);
 }
 
 // POTRF of the diagonal tile (J, J) and the TRSM of the tile below it,
@@ -61,12 +61,13 @@ __global__ __launch_bounds__(256) void k_potrf_f64(double* __restrict__ A, int l
 // launch is followed by a one-thread kernel that stores `ready_val` to
 // *ready (release), and the strips acquire it before they start (ready may be
 // null when the update is ordered by the stream itself). With syrk given, the
-// POTRF panels first apply the tile's last SYRK update themselves.
+// POTRF panels first apply the tile's last SYRK update themselves (with FP32
+// operands and accumulation if syrk_f32, the form of a mixed FP32 sweep).
 __global__ __launch_bounds__(256) void k_potrf_trsm_f64(
     double* __restrict__ A, int lda, int m, double* __restrict__ Tinv, int ldt,
     int* __restrict__ info, int64_t col_base, unsigned* __restrict__ flags, unsigned epoch,
     int* __restrict__ err, const TrsmTask* __restrict__ trsm, const unsigned* __restrict__ ready,
-    unsigned ready_val, const double* __restrict__ syrk)
+    unsigned ready_val, const double* __restrict__ syrk, int syrk_f32)
 {
     if (info != nullptr) {
         const int f = *info;
@@ -80,7 +81,7 @@ __global__ __launch_bounds__(256) void k_potrf_trsm_f64(
     const int tid = threadIdx.x;
     if ((int)blockIdx.x < P) {
         potrf_panel(A, lda, m, Tinv, ldt, info, col_base, flags, epoch, err, blockIdx.x, sh.potrf,
-                    tid, syrk);
+                    tid, syrk, syrk_f32 != 0);
         return;
     }
     if (ready != nullptr) {
@@ -144,20 +145,21 @@ __global__ __launch_bounds__(256) void k_trtri_f64(TileMat K, double* __restrict
 
 hipError_t launch_potrf_f64(double* A, int lda, int m, double* Tinv, int ldt, int* info,
                             int64_t col_base, unsigned* flags, unsigned epoch, int* err,
-                            hipStream_t s, const double* syrk)
+                            hipStream_t s, const double* syrk, bool syrk_f32)
 {
     hipLaunchKernelGGL(k_potrf_f64, dim3(m / NB), dim3(256), 0, s, A, lda, m, Tinv, ldt, info,
-                       col_base, flags, epoch, err, syrk);
+                       col_base, flags, epoch, err, syrk, syrk_f32 ? 1 : 0);
     return hipGetLastError();
 }
 
 hipError_t launch_potrf_trsm_f64(double* A, int lda, int m, double* Tinv, int ldt, int* info,
                                  int64_t col_base, unsigned* flags, unsigned epoch, int* err,
                                  const TrsmTask* trsm, const unsigned* ready, unsigned ready_val,
-                                 hipStream_t s, const double* syrk)
+                                 hipStream_t s, const double* syrk, bool syrk_f32)
 {
     hipLaunchKernelGGL(k_potrf_trsm_f64, dim3(2 * (m / NB)), dim3(256), 0, s, A, lda, m, Tinv, ldt,
-                       info, col_base, flags, epoch, err, trsm, ready, ready_val, syrk);
+                       info, col_base, flags, epoch, err, trsm, ready, ready_val, syrk,
+                       syrk_f32 ? 1 : 0);
     return hipGetLastError();
 }
 

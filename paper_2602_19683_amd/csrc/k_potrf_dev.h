@@ -198,12 +198,15 @@ struct PotrfLds {
 // (leading dimension m) whose product S S^T is first subtracted from the
 // panel's blocks (the tile's last SYRK update, run by the panel itself). Each
 // element's products are summed in k order from zero and the sum subtracted
-// once, as the tile-update kernels do, so the result is bitwise theirs.
+// once, as the tile-update kernels do, so the result is bitwise theirs; with
+// syrk_f32 the operands are rounded to FP32 and summed by FP32-accumulator
+// MFMAs, as in an FP32 tile update.
 __device__ inline void potrf_panel(double* __restrict__ A, int lda, int m, double* __restrict__ Tinv,
                                    int ldt, int* __restrict__ info, int64_t col_base,
                                    unsigned* __restrict__ flags, unsigned epoch,
                                    int* __restrict__ err, int w, PotrfLds& sh, int tid,
-                                   const double* __restrict__ syrk = nullptr)
+                                   const double* __restrict__ syrk = nullptr,
+                                   bool syrk_f32 = false)
 {
     double (*As)[KC][SP] = sh.As;
     double (*Bs)[KC][SP] = sh.Bs;
@@ -224,6 +227,16 @@ __device__ inline void potrf_panel(double* __restrict__ A, int lda, int m, doubl
     if (syrk != nullptr) {
         // K[w, q] -= S[w rows] S[q rows]^T for q <= w; the panel owns these blocks
         for (int q = 0; q <= w; ++q) {
+            if (syrk_f32) {
+                const flt4a acc = accum32_f32<KC>(syrk + (size_t)row0 * m, m,
+                                                  syrk + (size_t)NB * q * m, m, m, As, Bs, tid);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    double* c = Aw + (size_t)(16 * qi + 4 * lk + v) * lda + NB * q + 16 * qj + lr;
+                    gst(c, gld(c) - (double)acc[v]);
+                }
+                continue;
+            }
             dbl4 acc = {0.0, 0.0, 0.0, 0.0};
             acc = accum32<true, KC, true>(syrk + (size_t)row0 * m, m, syrk + (size_t)NB * q * m, m,
                                           m, acc, 1.0, As, Bs, tid);
@@ -303,6 +316,4 @@ __device__ inline void potrf_panel(double* __restrict__ A, int lda, int m, doubl
         Aw[(size_t)r * lda + row0 + NB + c] = 0.0;
     }
 }
-
-
 }  // namespace gpr
