@@ -34,51 +34,110 @@ __device__ inline double rsqrt_refined(double d)
 }
 
 // Cholesky factor and inverse of the 16 x 16 block S[r0.., r0..] (lower
-// triangle read), by one wave, right-looking with one reciprocal square root
-// per pivot. The 64 lanes split the block: lane (g, i) = (lane / 16, lane % 16)
-// holds row i, columns 4q + g (q = 0..3). After column j is scaled by its
-// owners (group j % 4), they write it to the LDS vector col; every lane reads
-// its row's entry and the entries of its own columns from there and updates
-// its four values. The inverse is formed one column per lane by forward
-// substitution with the stored pivot reciprocals. On return the block of S
-// holds L (zeros above the diagonal) and the block of Si holds L^{-1}. Returns
-// the first failing local column or -1. dv: 16 pivot reciprocals, col: 16
-// doubles of LDS scratch.
+// triangle read), by one wave, right-looking over four blocks of four
+// columns with one reciprocal square root per pivot. Lane (g, i) =
+// (lane / 16, lane % 16) holds row i, columns 4 g .. 4 g + 3, so the four
+// columns of block b are held by group b. Per block: group b puts its rows
+// of the block in the LDS panel; every lane of the group factors the 4 x 4
+// diagonal block (redundantly) and solves its own row against it; the group
+// puts the finished rows in the panel, and the lanes of later groups apply
+// the four columns to their entries. Every entry receives the same fused
+// multiply-adds in the same column order as a column-by-column factorisation
+// (so the bits are those of that order), with three wave-level LDS
+// handoffs per four columns instead of two per column. The inverse is formed
+// one column per lane by forward substitution with the stored pivot
+// reciprocals. On return the block of S holds L (zeros above the diagonal)
+// and the block of Si holds L^{-1}. Returns the first failing local column
+// or -1. dv: 16 pivot reciprocals; scratch: 80 doubles of LDS (the 16 x 4
+// panel and the 16 pivots).
 __device__ inline int chol_inv16(double (*S)[NB + 1], double (*Si)[NB + 1], int r0, double* dv,
-                                 double* col, int lane)
+                                 double* scratch, int lane)
 {
     const int i = lane & 15, g = lane >> 4;
-    double a[4];  // a[q] = row i, column 4 q + g
+    double (*pan)[4] = reinterpret_cast<double (*)[4]>(scratch);
+    double* piv = scratch + 64;
+    double a[4];  // a[q] = row i, column 4 g + q
 #pragma unroll
-    for (int q = 0; q < 4; ++q) a[q] = S[r0 + i][r0 + 4 * q + g];
-    int bad = -1;
+    for (int q = 0; q < 4; ++q) a[q] = S[r0 + i][r0 + 4 * g + q];
 #pragma unroll
-    for (int j = 0; j < 16; ++j) {
-        const int gj = j & 3, qj = j >> 2;
-        const double d = lane_bcast(a[qj], 16 * gj + j);
-        if (!(d > 0.0) && bad < 0) bad = j;
-        const double inv = rsqrt_refined(d);
-        const double ljj = d * inv;
-        if (g == gj) a[qj] = (i == j) ? ljj : (i > j ? a[qj] * inv : 0.0);
-        if (lane == 0) dv[j] = inv;
-        if (j < 15) {
-            if (g == gj) col[i] = a[qj];  // column j of L (zero above the pivot)
-            wave_lds_sync();
-            const double lij = col[i];
+    for (int b = 0; b < 4; ++b) {
+        const int c0 = 4 * b;
+        if (g == b) {
+#pragma unroll
+            for (int c = 0; c < 4; ++c) pan[i][c] = a[c];
+        }
+        wave_lds_sync();
+        if (g == b) {
+            // the 4 x 4 diagonal block, right-looking, column by column
+            double d[4][4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+#pragma unroll
+                for (int c = 0; c <= r; ++c) d[r][c] = pan[c0 + r][c];
+            double inv[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const double p = d[c][c];
+                inv[c] = rsqrt_refined(p);
+                if (i == 0) {
+                    piv[c0 + c] = p;
+                    dv[c0 + c] = inv[c];
+                }
+                d[c][c] = p * inv[c];
+#pragma unroll
+                for (int r = c + 1; r < 4; ++r) d[r][c] *= inv[c];
+#pragma unroll
+                for (int r = c + 1; r < 4; ++r)
+#pragma unroll
+                    for (int k = c + 1; k <= r; ++k) d[r][k] = fma(-d[r][c], d[k][c], d[r][k]);
+            }
+            if (i >= c0 + 4) {
+                // a row below the block: solve it against the block
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    a[c] *= inv[c];
+#pragma unroll
+                    for (int k = c + 1; k < 4; ++k) a[k] = fma(-a[c], d[k][c], a[k]);
+                }
+            } else {
+                // a row of the block (its factor, zeros above the diagonal), or
+                // a row above it (upper triangle: zeros)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    double v = 0.0;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        if (i == c0 + r && c <= r) v = d[r][c];
+                    a[c] = v;
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < 4; ++c) pan[i][c] = a[c];
+        }
+        wave_lds_sync();
+        if (g > b) {
+            double li[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) li[c] = pan[i][c];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                // a[k] -= L[i][j] L[k][j] for the columns k > j of this lane, in
-                // rows i >= k (entries above the diagonal are left alone)
-                const int k = 4 * q + g;
-                if (k > j && i >= k) a[q] = fma(-lij, col[k], a[q]);
+                // a[q] -= L[i][c0 + c] L[k][c0 + c], c = 0..3 in order, in rows i >= k
+                const int k = 4 * g + q;
+                if (i >= k) {
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) a[q] = fma(-li[c], pan[k][c], a[q]);
+                }
             }
-            wave_lds_sync();
         }
+        wave_lds_sync();
     }
-    wave_lds_sync();
+    int bad = -1;
+#pragma unroll
+    for (int j = 15; j >= 0; --j)
+        if (!(piv[j] > 0.0)) bad = j;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        const int k = 4 * q + g;
+        const int k = 4 * g + q;
         S[r0 + i][r0 + k] = (k <= i) ? a[q] : 0.0;
     }
     wave_lds_sync();
@@ -111,7 +170,7 @@ __device__ inline int chol_inv16(double (*S)[NB + 1], double (*Si)[NB + 1], int 
 // which halves the sequential depth of the 32-column factorisation and its
 // inverse. On return S holds L (zeros above the diagonal) and Si holds L^{-1}
 // (zeros above). Returns the first failing local column or -1. dv: 32 doubles
-// and col: 16 doubles of LDS scratch.
+// and col: 80 doubles of LDS scratch.
 __device__ inline int factor_diag32(double (*S)[NB + 1], double (*Si)[NB + 1], double* dv,
                                     double* col, int lane)
 {
@@ -190,7 +249,7 @@ struct PotrfLds {
     double Sacc[NB][NB + 1];
     double Si[NB][NB + 1];
     double dv[NB];
-    double col[16];  // column broadcast of the diagonal-block factorisation
+    double col[80];  // panel and pivots of the diagonal-block factorisation
 };
 
 // Row panel w of the POTRF of the m x m tile A (see k_potrf.hip). 256 threads;
