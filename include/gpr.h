@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define GPR_ABI_VERSION 8
+#define GPR_ABI_VERSION 9
 
 /* Status codes. */
 enum {
@@ -181,8 +181,9 @@ int gpr_assemble(gpr_ctx* ctx, const double* X, int64_t n, int32_t D,
 
 /* Factorises K = L L^T in place with the tiled right-looking algorithm of
  * Sec. 4.2 (Fig. 1). The handle must hold K (GPR_EINVAL otherwise); it holds
- * L afterwards, plus the inverse of every diagonal tile of L and of every
- * 2 x 2 block of tiles, which the solves use. prec chooses the precision of
+ * L afterwards, plus the inverse of every diagonal tile of L and of the
+ * blocks of G x G tiles that the solves take in one step (G = 4 for tiles up
+ * to 256, else 2; see gpr_solve_plan_describe). prec chooses the precision of
  * the GEMM/SYRK updates.
  * info_dev (optional, device int32): set to 0, or to the 1-based global
  * column of the first pivot that was not > 0 (LAPACK convention); gpr_sync
@@ -426,6 +427,24 @@ int gpr_adjoint_describe(int32_t M, int32_t G, int32_t* tasks, int64_t task_cap,
                          int64_t* n_tasks, int32_t* terms, int64_t term_cap,
                          int64_t* n_terms, int32_t* launches, int64_t launch_cap,
                          int64_t* n_launches);
+
+/* The tile products that build the group inverses of the vector solves
+ * (Sec. 4.1: beta = L^{-1} y and alpha = L^{-T} beta by block substitution,
+ * G tile rows per step) for M tile rows of size `tile`, without running
+ * anything (host only). *group receives G (4 for tiles up to 256, else 2).
+ * Group g holds tiles gG .. gG + G - 1; the off-diagonal tile (i, j), i > j,
+ * of the inverse of its block goes to W slot g G (G - 1) / 2 + i (i - 1) / 2
+ * + j. Operands are symbolic (kind, a, b): kind 0 tile (a, b) of L, 1 the
+ * inverse of diagonal tile a, 2 W slot a, 3 scratch slot a. Each task
+ * computes out = sum over its terms of alpha A B, the terms first_term ..
+ * first_term + nterm - 1 counted from the first term of its launch; the
+ * launches run in order. tasks: 6 int32 per task: launch, out (3),
+ * first_term, nterm. terms: 7 int32 per term: A (3), B (3), alpha (+1 or -1).
+ * Either array may be NULL; capacities in records; counts always written;
+ * GPR_EINVAL if a capacity is too small or M < 1 or the tile is invalid. */
+int gpr_solve_plan_describe(int32_t M, int32_t tile, int32_t* group, int32_t* tasks,
+                            int64_t task_cap, int64_t* n_tasks, int32_t* terms,
+                            int64_t term_cap, int64_t* n_terms);
 
 /* The ticket order of the persistent executor for one sweep shape (host
  * only): M, Mhat, mode as for gpr_schedule_describe, tile m, update block

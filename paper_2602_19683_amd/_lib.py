@@ -79,6 +79,8 @@ SIGNATURES = {
                                             _i32p, _i64, _i64p]),
     "gpr_persist_describe": (ctypes.c_int, [_i32, _i32, _i32, _i32, _i32, _i32, _i32p, _i64p,
                                             _i64, _i64p]),
+    "gpr_solve_plan_describe": (ctypes.c_int, [_i32, _i32, _i32p, _i32p, _i64, _i64p, _i32p,
+                                               _i64, _i64p]),
 }
 
 _LIB = None

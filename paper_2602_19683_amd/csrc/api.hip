@@ -131,6 +131,13 @@ struct gpr_ctx {
     double p_ms[11] = {}, p_flops[11] = {}, p_bytes[11] = {};
 };
 
+// One launch of the group-inverse build: byte offsets of its tasks and terms
+// in the handle's descriptor buffer, and its task count.
+struct TinvLaunch {
+    size_t task_off, term_off;
+    int ntask;
+};
+
 struct gpr_tiled {
     int device = 0;
     Budget budget;                // the creating context's counter
@@ -141,9 +148,11 @@ struct gpr_tiled {
     double* data = nullptr;
     double* tinv = nullptr;
     double* kcopy = nullptr;      // FP64 copy of K kept by a mixed-precision factorisation
-    double* tpair = nullptr;      // W_p of the two-tile solves (M / 2 tiles), then scratch
-    char* tpair_desc = nullptr;   // device descriptors of the two W_p launches (fixed per handle)
+    double* tpair = nullptr;      // off-diagonal tiles of the solves' group inverses, then scratch
+    char* tpair_desc = nullptr;   // device descriptors of the launches that build them (fixed per handle)
     char* tpair_host = nullptr;   // their pinned host copy
+    std::vector<TinvLaunch> tg_launches;  // those launches: descriptor offsets, task counts
+    double tg_flops = 0.0;
     int state = GPR_STATE_EMPTY;
     int prec = GPR_FP64;
 };
@@ -734,61 +743,88 @@ bool valid_prec(int prec, int m)
     return (prec == GPR_MIXED_FP32 || prec == GPR_MIXED_BF16) && m % 64 == 0;
 }
 
-// Off-diagonal blocks of the inverses of the 2 x 2 tile blocks (J, J + 1),
-// J = 2 p, for the two-tile vector solves (k_trsv.hip):
-//   W_p = -Tinv_{J+1} (L_{J+1,J} Tinv_J),
-// two batched adjoint-GEMM launches (the second reads the first's products
-// from the scratch half of tpair). Needs the diagonal-tile inverses; the
-// handle's data and tinv buffers are allocated before and never move.
+// Off-diagonal tiles of the inverses of the G x G blocks of tiles that the
+// vector solves take in one step (k_trsv.hip; G = trsv_group(m)), built by the
+// batched tile-product launches of plan_tinv_groups (solve_plan.cpp): W slots
+// in the first half of tpair, the scratch products Y in the second. Needs the
+// diagonal-tile inverses; the handle's data and tinv buffers are allocated
+// before and never move, so the descriptors are written once per handle.
 int build_tinv_pairs(gpr_ctx* ctx, gpr_tiled* L, hipStream_t s)
 {
-    const int M = L->M, m = L->m, P = M / 2;
-    if (P < 1) return GPR_OK;
+    const int M = L->M, m = L->m;
+    if (M < 2) return GPR_OK;
     const size_t mm = (size_t)m * m;
-    const size_t ts = ((size_t)P * sizeof(TGemmTask) + 63) & ~size_t(63);
-    const size_t us = ((size_t)P * sizeof(TGemmTerm) + 63) & ~size_t(63);
     if (!L->tpair) {
-        // the W_p / scratch tiles, and the two launches' descriptors, which
-        // depend only on this handle's buffers: written once, kept with the
-        // handle (the context's descriptor buffer may hold a pending plan)
-        int rc = handle_malloc(L, reinterpret_cast<void**>(&L->tpair),
-                               2 * (size_t)P * mm * sizeof(double));
-        if (rc == GPR_OK)
-            rc = handle_malloc(L, reinterpret_cast<void**>(&L->tpair_desc), 2 * (ts + us));
-        if (rc) return rc;
-        if (hipHostMalloc(reinterpret_cast<void**>(&L->tpair_host), 2 * (ts + us)) != hipSuccess) {
+        const TinvPlan P = plan_tinv_groups(M, trsv_group(m));
+        if (!tinv_plan_valid(P)) return GPR_EINVAL;
+        const size_t wbytes = 2 * (size_t)P.nslot * mm * sizeof(double);
+        const size_t tb = (P.tasks.size() * sizeof(TGemmTask) + 63) & ~size_t(63);
+        const size_t ub = P.terms.size() * sizeof(TGemmTerm);
+        double* W = nullptr;
+        char* desc = nullptr;
+        char* host = nullptr;
+        int rc = handle_malloc(L, reinterpret_cast<void**>(&W), wbytes);
+        if (rc == GPR_OK) rc = handle_malloc(L, reinterpret_cast<void**>(&desc), tb + ub);
+        if (rc == GPR_OK && hipHostMalloc(reinterpret_cast<void**>(&host), tb + ub) != hipSuccess) {
             (void)hipGetLastError();
-            L->tpair_host = nullptr;
-            return GPR_ENOMEM;
+            host = nullptr;
+            rc = GPR_ENOMEM;
         }
-        double* W = L->tpair;
-        double* Q = L->tpair + (size_t)P * mm;
-        TGemmTask* t1 = reinterpret_cast<TGemmTask*>(L->tpair_host);
-        TGemmTerm* u1 = reinterpret_cast<TGemmTerm*>(L->tpair_host + ts);
-        TGemmTask* t2 = reinterpret_cast<TGemmTask*>(L->tpair_host + ts + us);
-        TGemmTerm* u2 = reinterpret_cast<TGemmTerm*>(L->tpair_host + 2 * ts + us);
-        for (int p = 0; p < P; ++p) {
-            const int J = 2 * p;
-            t1[p] = TGemmTask{Q + p * mm, nullptr, nullptr, 0, 0.0, m, m, 0, p, 1, TG_EPI_NONE};
-            u1[p] = TGemmTerm{tile_ptr(kmat(L), J + 1, J), L->tinv + (size_t)J * mm, 1.0, m, m, 0, 0};
-            t2[p] = TGemmTask{W + p * mm, nullptr, nullptr, 0, 0.0, m, m, 0, p, 1, TG_EPI_NONE};
-            u2[p] = TGemmTerm{L->tinv + (size_t)(J + 1) * mm, Q + p * mm, -1.0, m, m, 0, 0};
+        if (rc) {   // nothing kept: the next call plans again
+            if (W) {
+                budget_free(L->budget, W, wbytes);
+                L->dev_bytes -= wbytes;
+            }
+            if (desc) {
+                budget_free(L->budget, desc, tb + ub);
+                L->dev_bytes -= tb + ub;
+            }
+            return rc;
         }
-        HIP_TRY(hipMemcpyAsync(L->tpair_desc, L->tpair_host, 2 * (ts + us), hipMemcpyHostToDevice,
-                               s));
+        L->tpair_desc = desc;
+        L->tpair_host = host;
+        double* Y = W + (size_t)P.nslot * mm;
+        const TileMat Lm = kmat(L);
+        auto ptr = [&](const TinvRef& r) -> const double* {
+            switch (r.kind) {
+            case TR_L: return tile_ptr(Lm, r.a, r.b);
+            case TR_TINV: return L->tinv + (size_t)r.a * mm;
+            case TR_W: return W + (size_t)r.a * mm;
+            default: return Y + (size_t)r.a * mm;
+            }
+        };
+        TGemmTask* tk = reinterpret_cast<TGemmTask*>(host);
+        TGemmTerm* tm = reinterpret_cast<TGemmTerm*>(host + tb);
+        for (size_t t = 0; t < P.tasks.size(); ++t) {
+            const TinvTaskPlan& k = P.tasks[t];
+            tk[t] = TGemmTask{const_cast<double*>(ptr(k.out)), nullptr, nullptr, 0, 0.0, m, m, 0,
+                              k.first_term, k.nterm, TG_EPI_NONE};
+        }
+        for (size_t u = 0; u < P.terms.size(); ++u)
+            tm[u] = TGemmTerm{ptr(P.terms[u].A), ptr(P.terms[u].B), P.terms[u].alpha, m, m, 0, 0};
+        HIP_TRY(hipMemcpyAsync(desc, host, tb + ub, hipMemcpyHostToDevice, s));
+        L->tg_launches.clear();
+        for (const TinvLaunchPlan& lp : P.launches)
+            L->tg_launches.push_back(TinvLaunch{lp.first_task * sizeof(TGemmTask),
+                                                tb + lp.first_term * sizeof(TGemmTerm),
+                                                lp.ntask});
+        L->tg_flops = 2.0 * (double)P.terms.size() * m * mm;
+        L->tpair = W;
     }
-    const char* d = L->tpair_desc;
-    ProfScope ps(ctx, s, PK_TRTRI, 4.0 * P * (double)m * m * m, 0.0);
-    const int bm = tgemm_block(P, m);
-    HIP_TRY(launch_tgemm_f64(reinterpret_cast<const TGemmTask*>(d), P,
-                             reinterpret_cast<const TGemmTerm*>(d + ts), m, bm, s));
-    HIP_TRY(launch_tgemm_f64(reinterpret_cast<const TGemmTask*>(d + ts + us), P,
-                             reinterpret_cast<const TGemmTerm*>(d + 2 * ts + us), m, bm, s));
+    ProfScope ps(ctx, s, PK_TRTRI, L->tg_flops, 0.0);
+    for (const TinvLaunch& t : L->tg_launches) {
+        if (t.ntask == 0) continue;
+        HIP_TRY(launch_tgemm_f64(reinterpret_cast<const TGemmTask*>(L->tpair_desc + t.task_off),
+                                 t.ntask,
+                                 reinterpret_cast<const TGemmTerm*>(L->tpair_desc + t.term_off),
+                                 m, tgemm_block(t.ntask, m), s));
+    }
     return GPR_OK;
 }
 
 // Vector solves with the factor: beta = L^{-1} rhs, alpha = L^{-T} beta
-// (k_trsv.hip); tmp is scratch. All vectors have length M m.
+// (k_trsv.hip; the second is skipped when alpha is null); tmp is scratch. All
+// vectors have length M m.
 int run_trsv_pair(gpr_ctx* ctx, const gpr_tiled* L, const double* rhs, double* tmp,
                   double* beta, double* alpha, hipStream_t s)
 {
@@ -798,7 +834,7 @@ int run_trsv_pair(gpr_ctx* ctx, const gpr_tiled* L, const double* rhs, double* t
         ProfScope ps(ctx, s, PK_TRSV, f, 0.0);
         HIP_TRY(launch_trsv(kmat(L), L->tinv, L->tpair, M, rhs, tmp, beta, false, s));
     }
-    {
+    if (alpha) {
         ProfScope ps(ctx, s, PK_TRSV, f, 0.0);
         HIP_TRY(launch_trsv(kmat(L), L->tinv, L->tpair, M, beta, tmp, alpha, true, s));
     }
@@ -1462,9 +1498,9 @@ int nlml_launch(gpr_ctx* ctx, NlmlRun& R, const double* X, const double* y, int6
     K->prec = GPR_FP64;
     rc = finish_info(ctx, nullptr, s);
     if (rc) return rc;
-    // beta = L^{-1} y (kept), alpha = L^{-T} beta
+    // beta = L^{-1} y (kept), and for the gradient alpha = L^{-T} beta
     HIP_TRY(launch_copy_f64(y, R.r, n, (int64_t)npad, s));
-    rc = run_trsv_pair(ctx, K, R.r, R.tmp, R.beta, R.alpha, s);
+    rc = run_trsv_pair(ctx, K, R.r, R.tmp, R.beta, R.grad ? R.alpha : nullptr, s);
     if (rc) return rc;
     if (R.grad) {
         {

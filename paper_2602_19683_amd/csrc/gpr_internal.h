@@ -137,6 +137,9 @@ hipError_t launch_tiled_to_dense(const TileMat& T, int64_t n, double* out, int64
 // the factorisation's failed-pivot record; when it is > 0 at a launch's start
 // the launch returns at once (nothing of a failed factorisation is used).
 // Pass it only for sweeps that factorise, where it was reset beforehand.
+// Block edge (128, 64 or 32) of the update kernels for a launch of ntask m x m
+// tasks.
+int update_block_size(int ntask, int m);
 hipError_t launch_update_f64(const UpdateTask* d_tasks, int ntask, int m, const int* abort_info,
                              hipStream_t s);
 // The part sums of split updates (ReduceTask).
@@ -168,11 +171,14 @@ hipError_t launch_signal(unsigned* flag, unsigned v, hipStream_t s);
 // the inverse of tile J goes to Tinv + J m^2 (leading dimension m), whose
 // 32 x 32 diagonal blocks must already hold the block inverses.
 hipError_t launch_trtri_f64(const TileMat& K, int M, double* Tinv, hipStream_t s);
+// Tile rows per step of the vector solves for tile size m (4 or 2).
+int trsv_group(int m);
 // x = L^{-1} b (trans: L^{-T} b) over the lower tiles of L with the inverses of
 // its diagonal tiles (Tinv, M tiles); r: scratch of length M m (b is copied
-// there first). W (nullable): the off-diagonal blocks W_p = -Tinv_{2p+1}
-// L_{2p+1,2p} Tinv_{2p} of the inverses of the 2 x 2 tile blocks (M / 2
-// tiles); with it, two launches per pair of tile rows, else per tile row.
+// there first). W (nullable): the off-diagonal tiles of the inverses of the
+// G x G blocks of tiles (G = trsv_group(m); group g = tiles g G ..), Inv_ij
+// (i > j, relative indices) at tile g G (G - 1) / 2 + i (i - 1) / 2 + j; with
+// it, two launches per group of tile rows, else per tile row.
 hipError_t launch_trsv(const TileMat& L, const double* Tinv, const double* W, int M,
                        const double* b, double* r, double* x, bool trans, hipStream_t s);
 
@@ -336,6 +342,37 @@ Schedule build_schedule(int M, int Mhat, int mode);
 // a variant (GPR_RIGHT_LOOKING: build_schedule).
 Schedule build_schedule_left(int M, int Mhat, int mode);
 Schedule build_schedule_variant(int M, int Mhat, int mode, int variant);
+
+// The tile products that build the off-diagonal tiles of the group inverses
+// of the vector solves (solve_plan.cpp), with symbolic operands: TR_L tile
+// (a, b) of L, TR_TINV the inverse of diagonal tile a, TR_W / TR_Y slot a of
+// the result / scratch tiles. A task computes out = sum over its terms of
+// alpha A B; first_term counts from its launch's first term.
+enum : int { TR_L = 0, TR_TINV = 1, TR_W = 2, TR_Y = 3 };
+struct TinvRef {
+    int kind, a, b;
+};
+struct TinvTaskPlan {
+    TinvRef out;
+    int first_term, nterm;
+};
+struct TinvTermPlan {
+    TinvRef A, B;
+    double alpha;
+};
+struct TinvLaunchPlan {
+    int first_task = 0, ntask = 0, first_term = 0, nterm = 0;
+};
+struct TinvPlan {
+    int G = 1;
+    long long nslot = 0;   // W slots (and as many Y slots)
+    std::vector<TinvTaskPlan> tasks;
+    std::vector<TinvTermPlan> terms;
+    std::vector<TinvLaunchPlan> launches;
+};
+TinvPlan plan_tinv_groups(int M, int G);
+// every task's terms lie inside its launch's terms
+bool tinv_plan_valid(const TinvPlan& P);
 
 // Persistent executor (persist.cpp, k_persist.hip): geometry, ticket order for
 // `workers` resident workgroups, update block size for a tile size, the

@@ -1,15 +1,21 @@
 // k_trsv.hip -- the triangular vector solves of the prediction (Sec. 4.1,
 // after eq. (2)): beta = L^{-1} b and alpha = L^{-T} beta by block
-// substitution over the lower tiles of L with the inverses of its diagonal
-// tiles. Forward, tile row by tile row (r = b on entry):
-//     beta_J = Tinv_J r_J                       (one launch, m / 32 workgroups)
-//     r_K -= L_KJ beta_J,  K > J                (one launch for all K)
-// Backward over J = M-1 .. 0 with transposed tiles:
-//     alpha_J = Tinv_J^T r_J,  r_K -= L_JK^T alpha_J,  K < J.
+// substitution over the lower tiles of L, a group of G consecutive tile rows
+// per step (G = trsv_group(m): 4 for tiles up to 256, else 2). The inverse of
+// the group's G x G block of tiles is known: its diagonal tiles are the
+// diagonal-tile inverses Tinv, its off-diagonal tiles Inv_ij (i > j) are built
+// once per factor (api.hip). Forward, group g = tiles J0 .. J0 + ns - 1
+// (r = b on entry):
+//     x_{J0+i} = sum_{j <= i} Inv_ij r_{J0+j}                  (one launch)
+//     r_K -= sum_j L_{K,J0+j} x_{J0+j},  K >= J0 + ns          (one launch)
+// Backward over the groups in reverse, with transposed tiles:
+//     x_{J0+j} = sum_{i >= j} Inv_ij^T r_{J0+i},
+//     r_K -= sum_i L_{J0+i,K}^T x_{J0+i},  K < J0.
 // The launch boundaries order the steps (a device-scope handoff between
-// workgroups costs more than a launch here). Tile addresses are computed from
-// the tile indices, so no task descriptors are needed. Every product sums in a
-// fixed order: results are bitwise reproducible.
+// workgroups costs more than a launch here), so a solve is 2 ceil(M / G) - 1
+// launches. Tile addresses are computed from the tile indices, so no task
+// descriptors are needed. Every product sums in a fixed order: results are
+// bitwise reproducible.
 #include "gpr_internal.h"
 #include "k_common.h"
 
@@ -26,81 +32,82 @@ __device__ inline double wave_sum(double x)
 
 // The products below are latency-bound: one step moves a few MB with a
 // dependent launch on either side. Each lane therefore issues all of its
-// loads before it adds anything (up to GV_LOADS in flight), and a workgroup
-// covers a small slice of the tile, so that a tile is spread over many
-// workgroups.
+// loads before it adds anything, and a workgroup covers a small slice of the
+// tile rows, so that a step is spread over many workgroups.
 constexpr int GV_ROWS = 8;    // non-transposed: rows per workgroup (2 per wave)
 constexpr int GV_COLS = 16;   // transposed: columns per workgroup
-constexpr int GV_LOADS = 32;  // transposed: rows per lane per unrolled chunk
+constexpr int GV_LOADS = 32;  // transposed: operand loads per lane per chunk
 
-// Sums (T x)[row0] and (T x)[row0 + 1] of an m x m tile for the calling wave
-// (every lane gets both). Lane l takes columns l + 64 k (k < m / 64, at most
-// 16), issuing all of its loads first; it sums in k order, then a fixed
-// butterfly adds the lanes.
-__device__ inline void row_pair_dot(const double* __restrict__ T, const double* __restrict__ x,
-                                    int row0, int m, int lane, double& s0, double& s1)
+// Offset (in tiles) of Inv_ij, i > j, within its group's block of slots.
+__host__ __device__ inline int inv_slot(int i, int j) { return i * (i - 1) / 2 + j; }
+
+// Rows row0, row0 + 1 of sum_{j < ns} T_j x_j for the calling wave (every lane
+// gets both sums), T_j = seg.tile(j) an m x m tile, x_j = seg.vec(j). Lane l
+// takes columns l + 64 q (q < Q) of every segment and issues all of its loads
+// first; it sums segment by segment in column order, then a fixed butterfly
+// adds the lanes. Needs m <= 64 Q and ns <= G.
+template <int G, int Q, class Seg>
+__device__ inline void rows_dot(const Seg& seg, int ns, int row0, int m, int lane, double& s0,
+                                double& s1)
 {
-    const double* T0 = T + (size_t)row0 * m;
-    const double* T1 = T0 + m;
-    double a0[16], a1[16], xv[16];
+    double a0[G][Q], a1[G][Q], xv[G][Q];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        const int c = lane + 64 * k;
-        const bool in = c < m;
-        a0[k] = in ? T0[c] : 0.0;
-        a1[k] = in ? T1[c] : 0.0;
-        xv[k] = in ? x[c] : 0.0;
+    for (int j = 0; j < G; ++j) {
+        const double* T0 = seg.tile(j) + (size_t)row0 * m;
+        const double* T1 = T0 + m;
+        const double* x = seg.vec(j);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int c = lane + 64 * q;
+            const bool in = j < ns && c < m;
+            a0[j][q] = in ? gld(T0 + c) : 0.0;
+            a1[j][q] = in ? gld(T1 + c) : 0.0;
+            xv[j][q] = in ? gld(x + c) : 0.0;
+        }
     }
     s0 = 0.0;
     s1 = 0.0;
 #pragma unroll
-    for (int k = 0; k < 16; ++k) {
-        s0 = fma(a0[k], xv[k], s0);
-        s1 = fma(a1[k], xv[k], s1);
-    }
+    for (int j = 0; j < G; ++j)
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            s0 = fma(a0[j][q], xv[j][q], s0);
+            s1 = fma(a1[j][q], xv[j][q], s1);
+        }
     s0 = wave_sum(s0);
     s1 = wave_sum(s1);
 }
 
-// y (-)= T x on rows GV_ROWS blk .. + GV_ROWS - 1 of an m x m tile, 256 threads;
-// wave w owns rows 2w, 2w + 1 of the slice.
-__device__ inline void gemv_rows(const double* __restrict__ T, const double* __restrict__ x,
-                                 double* __restrict__ y, int blk, int m, bool set)
-{
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int row0 = blk * GV_ROWS + 2 * wave;
-    double s0, s1;
-    row_pair_dot(T, x, row0, m, lane, s0, s1);
-    if (lane < 2) {
-        const int row = row0 + lane;
-        const double v = lane ? s1 : s0;
-        y[row] = set ? v : y[row] - v;
-    }
-}
-
-// (T^T x)[col] for the GV_COLS columns GV_COLS blk .. of an m x m tile, 256
-// threads: thread (g, c), g < 16, sums column c over rows g, g + 16, ...
-// (m / 16 of them, in chunks of GV_LOADS loads issued together); the 16
-// partial sums of a column are added in g order. The result is valid in
-// threads tid < GV_COLS (column GV_COLS blk + tid); part is free on return.
-__device__ inline double col_dot(const double* __restrict__ T, const double* __restrict__ x,
-                                 int blk, int m, double (*part)[GV_COLS])
+// Column col of sum_{i < ns} T_i^T x_i, 256 threads: thread (g, c), g < 16,
+// c < GV_COLS, sums over the rows g, g + 16, ... of every segment in turn, in
+// chunks of GV_LOADS loads issued together; the 16 partial sums of a column
+// are then added in g order. The result is valid in threads tid < GV_COLS
+// (column GV_COLS blk + tid); part is free on return.
+template <class Seg>
+__device__ inline double cols_dot(const Seg& seg, int ns, int blk, int m,
+                                  double (*part)[GV_COLS])
 {
     const int tid = threadIdx.x, c = tid & (GV_COLS - 1), g = tid / GV_COLS;
     const int col = blk * GV_COLS + c;
-    const int rows = m / 16;
+    const int rps = m / 16;          // rows per segment and thread
+    const int total = ns * rps;
+    int sg = 0, q = 0;               // position of the next load
     double s = 0.0;
-    for (int r0 = 0; r0 < rows; r0 += GV_LOADS) {
+    for (int base = 0; base < total; base += GV_LOADS) {
         double a[GV_LOADS], xv[GV_LOADS];
 #pragma unroll
-        for (int q = 0; q < GV_LOADS; ++q) {
-            const int r = 16 * (r0 + q) + g;
-            const bool in = r0 + q < rows;
-            a[q] = in ? T[(size_t)r * m + col] : 0.0;
-            xv[q] = in ? x[r] : 0.0;
+        for (int u = 0; u < GV_LOADS; ++u) {
+            const bool in = base + u < total;
+            const int r = 16 * q + g;
+            a[u] = in ? gld(seg.tile(sg) + (size_t)r * m + col) : 0.0;
+            xv[u] = in ? gld(seg.vec(sg) + r) : 0.0;
+            if (++q == rps) {
+                q = 0;
+                ++sg;
+            }
         }
 #pragma unroll
-        for (int q = 0; q < GV_LOADS; ++q) s = fma(a[q], xv[q], s);
+        for (int u = 0; u < GV_LOADS; ++u) s = fma(a[u], xv[u], s);
     }
     part[g][c] = s;
     __syncthreads();
@@ -108,189 +115,168 @@ __device__ inline double col_dot(const double* __restrict__ T, const double* __r
     if (tid < GV_COLS) {
         tot = part[0][c];
 #pragma unroll
-        for (int q = 1; q < 16; ++q) tot += part[q][c];
+        for (int k = 1; k < 16; ++k) tot += part[k][c];
     }
     __syncthreads();
     return tot;
 }
 
-// y (-)= T^T x on the columns GV_COLS blk .. of an m x m tile, 256 threads.
-__device__ inline void gemv_cols(const double* __restrict__ T, const double* __restrict__ x,
-                                 double* __restrict__ y, int blk, int m, bool set,
-                                 double (*part)[GV_COLS])
-{
-    const double tot = col_dot(T, x, blk, m, part);
-    if (threadIdx.x < GV_COLS) {
-        const int col = blk * GV_COLS + threadIdx.x;
-        y[col] = set ? tot : y[col] - tot;
+// Segments of the group inverse: row i of the block (forward) or column j
+// (backward, segments i = j + s). Inv_ii = Tinv_{J0+i}; the others sit at
+// slot inv_slot(i, j) of the group's block Wg.
+struct InvRow {
+    const double *Tinv, *Wg, *r;
+    size_t mm;
+    int J0, i, m;
+    __device__ const double* tile(int j) const
+    {
+        return j == i ? Tinv + (size_t)(J0 + i) * mm : Wg + (size_t)inv_slot(i, j) * mm;
     }
-}
-
-template <bool TRANS>
-__device__ inline void gemv_block(const double* __restrict__ T, const double* __restrict__ x,
-                                  double* __restrict__ y, int blk, int m, bool set,
-                                  double (*part)[GV_COLS])
-{
-    if (TRANS) gemv_cols(T, x, y, blk, m, set, part);
-    else gemv_rows(T, x, y, blk, m, set);
-}
-
-// workgroups per tile
-template <bool TRANS>
-__host__ __device__ inline int gv_per_tile(int m) { return TRANS ? m / GV_COLS : m / GV_ROWS; }
+    __device__ const double* vec(int j) const { return r + (size_t)(J0 + j) * m; }
+};
+struct InvCol {
+    const double *Tinv, *Wg, *r;
+    size_t mm;
+    int J0, j, m;
+    __device__ const double* tile(int s) const
+    {
+        const int i = j + s;
+        return s == 0 ? Tinv + (size_t)(J0 + j) * mm : Wg + (size_t)inv_slot(i, j) * mm;
+    }
+    __device__ const double* vec(int s) const { return r + (size_t)(J0 + j + s) * m; }
+};
+// Tiles (K, J0 + j) of L (forward) or (J0 + i, K) (backward).
+struct LRow {
+    TileMat L;
+    const double* x;
+    int K, J0;
+    __device__ const double* tile(int j) const { return tile_ptr(L, K, J0 + j); }
+    __device__ const double* vec(int j) const { return x + (size_t)(J0 + j) * L.m; }
+};
+struct LCol {
+    TileMat L;
+    const double* x;
+    int K, J0;
+    __device__ const double* tile(int i) const { return tile_ptr(L, J0 + i, K); }
+    __device__ const double* vec(int i) const { return x + (size_t)(J0 + i) * L.m; }
+};
 
 }  // namespace
 
-// x_J = op(Tinv_J) r_J; workgroup b takes slice b of the outputs.
-template <bool TRANS>
-__global__ __launch_bounds__(256) void k_trsv_diag(const double* __restrict__ Tinv, int J, int m,
-                                                   const double* __restrict__ r,
-                                                   double* __restrict__ x)
+// Diagonal step of group J0 (ns tiles): x_{J0..J0+ns-1} from r. Workgroup b
+// takes tile i = b / per of the group, slice b % per of its outputs.
+template <bool TRANS, int G, int Q>
+__global__ __launch_bounds__(256) void k_trsv_group_diag(const double* __restrict__ Tinv,
+                                                         const double* __restrict__ Wg, int J0,
+                                                         int ns, int m,
+                                                         const double* __restrict__ r,
+                                                         double* __restrict__ x)
 {
     __shared__ double part[16][GV_COLS];
-    const size_t off = (size_t)J * m;
-    gemv_block<TRANS>(Tinv + off * m, r + off, x + off, blockIdx.x, m, true, part);
+    const size_t mm = (size_t)m * m;
+    if (!TRANS) {
+        const int per = m / GV_ROWS;
+        const int i = blockIdx.x / per, blk = blockIdx.x % per;
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        const int row0 = blk * GV_ROWS + 2 * wave;
+        const InvRow seg{Tinv, Wg, r, mm, J0, i, m};
+        double s0, s1;
+        rows_dot<G, Q>(seg, i + 1, row0, m, lane, s0, s1);
+        if (lane < 2) gst(x + (size_t)(J0 + i) * m + row0 + lane, lane ? s1 : s0);
+    } else {
+        const int per = m / GV_COLS;
+        const int j = blockIdx.x / per, blk = blockIdx.x % per;
+        const InvCol seg{Tinv, Wg, r, mm, J0, j, m};
+        const double tot = cols_dot(seg, ns - j, blk, m, part);
+        if (threadIdx.x < GV_COLS)
+            gst(x + (size_t)(J0 + j) * m + blk * GV_COLS + threadIdx.x, tot);
+    }
 }
 
-// r_K -= L_KJ x_J for K > J (forward) or r_K -= L_JK^T x_J for K < J
-// (backward); workgroup b: tile row K = first + b / per, slice b % per.
-template <bool TRANS>
-__global__ __launch_bounds__(256) void k_trsv_update(TileMat L, int J, int first,
-                                                     const double* __restrict__ x,
-                                                     double* __restrict__ r)
+// Update after group J0 (ns tiles): forward r_K -= sum_j L_{K,J0+j} x_{J0+j}
+// for the tile rows K = first + b / per; backward r_K -= sum_i L_{J0+i,K}^T
+// x_{J0+i}. Workgroup b: tile row first + b / per, slice b % per.
+template <bool TRANS, int G, int Q>
+__global__ __launch_bounds__(256) void k_trsv_group_update(TileMat L, int J0, int ns, int first,
+                                                           const double* __restrict__ x,
+                                                           double* __restrict__ r)
 {
     __shared__ double part[16][GV_COLS];
     const int m = L.m;
-    const int per = gv_per_tile<TRANS>(m);
-    const int K = first + blockIdx.x / per, blk = blockIdx.x % per;
-    const double* T = TRANS ? tile_ptr(L, J, K) : tile_ptr(L, K, J);
-    gemv_block<TRANS>(T, x + (size_t)J * m, r + (size_t)K * m, blk, m, false, part);
-}
-
-// Two tile rows per step, with W_p = -Tinv_{J+1} L_{J+1,J} Tinv_J (J = 2 p),
-// the off-diagonal block of the inverse of the pair's 2 x 2 block:
-//   forward   x_J = Tinv_J r_J,             x_{J+1} = W_p r_J + Tinv_{J+1} r_{J+1}
-//   backward  x_{J+1} = Tinv_{J+1}^T r_{J+1}, x_J = Tinv_J^T r_J + W_p^T r_{J+1}
-// Workgroups [0, per) take x_J, [per, 2 per) take x_{J+1}.
-template <bool TRANS>
-__global__ __launch_bounds__(256) void k_trsv_diag2(const double* __restrict__ Tinv,
-                                                    const double* __restrict__ W, int J, int m,
-                                                    const double* __restrict__ r,
-                                                    double* __restrict__ x)
-{
-    __shared__ double part[16][GV_COLS];
-    const int per = gv_per_tile<TRANS>(m);
-    const int half = blockIdx.x / per, blk = blockIdx.x % per;
-    const size_t mm = (size_t)m * m, o0 = (size_t)J * m;
-    const double* T0 = Tinv + (size_t)J * mm;
-    const double* T1 = T0 + mm;
-    const double* r0 = r + o0;
-    const double* r1 = r0 + m;
-    double* x0 = x + o0;
-    double* x1 = x0 + m;
     if (!TRANS) {
-        if (half == 0) {
-            gemv_rows(T0, r0, x0, blk, m, true);
-        } else {
-            const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-            const int row0 = blk * GV_ROWS + 2 * wave;
-            double a0, a1, b0, b1;
-            row_pair_dot(W, r0, row0, m, lane, a0, a1);
-            row_pair_dot(T1, r1, row0, m, lane, b0, b1);
-            if (lane < 2) x1[row0 + lane] = lane ? a1 + b1 : a0 + b0;
+        const int per = m / GV_ROWS;
+        const int K = first + blockIdx.x / per, blk = blockIdx.x % per;
+        const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+        const int row0 = blk * GV_ROWS + 2 * wave;
+        const LRow seg{L, x, K, J0};
+        double s0, s1;
+        rows_dot<G, Q>(seg, ns, row0, m, lane, s0, s1);
+        if (lane < 2) {
+            double* y = r + (size_t)K * m + row0 + lane;
+            gst(y, gld(y) - (lane ? s1 : s0));
         }
     } else {
-        if (half == 1) {
-            gemv_cols(T1, r1, x1, blk, m, true, part);
-        } else {
-            const double a = col_dot(T0, r0, blk, m, part);
-            const double b = col_dot(W, r1, blk, m, part);
-            if (threadIdx.x < GV_COLS) x0[blk * GV_COLS + threadIdx.x] = a + b;
+        const int per = m / GV_COLS;
+        const int K = first + blockIdx.x / per, blk = blockIdx.x % per;
+        const LCol seg{L, x, K, J0};
+        const double tot = cols_dot(seg, ns, blk, m, part);
+        if (threadIdx.x < GV_COLS) {
+            double* y = r + (size_t)K * m + blk * GV_COLS + threadIdx.x;
+            gst(y, gld(y) - tot);
         }
     }
 }
 
-// Forward: r_K -= L_{K,J} x_J, then r_K -= L_{K,J+1} x_{J+1}, for K >= J + 2.
-// Backward: r_K -= L_{J+1,K}^T x_{J+1}, then r_K -= L_{J,K}^T x_J, for K < J
-// (the order of the one-tile steps). Workgroup b: tile row K = first + b /
-// per, slice b % per.
-template <bool TRANS>
-__global__ __launch_bounds__(256) void k_trsv_update2(TileMat L, int J, int first,
-                                                      const double* __restrict__ x,
-                                                      double* __restrict__ r)
+int trsv_group(int m) { return m <= 256 ? 4 : 2; }
+
+namespace {
+
+template <int G, int Q>
+void trsv_steps(const TileMat& L, const double* Tinv, const double* W, int M, double* r,
+                double* x, bool trans, hipStream_t s)
 {
-    __shared__ double part[16][GV_COLS];
     const int m = L.m;
-    const int per = gv_per_tile<TRANS>(m);
-    const int K = first + blockIdx.x / per, blk = blockIdx.x % per;
-    double* rk = r + (size_t)K * m;
-    if (!TRANS) {
-        gemv_rows(tile_ptr(L, K, J), x + (size_t)J * m, rk, blk, m, false);
-        gemv_rows(tile_ptr(L, K, J + 1), x + (size_t)(J + 1) * m, rk, blk, m, false);
-    } else {
-        gemv_cols(tile_ptr(L, J + 1, K), x + (size_t)(J + 1) * m, rk, blk, m, false, part);
-        gemv_cols(tile_ptr(L, J, K), x + (size_t)J * m, rk, blk, m, false, part);
+    const size_t mm = (size_t)m * m;
+    // without the off-diagonal inverse tiles: one tile row per step
+    const int g = W ? G : 1;
+    const int ng = (M + g - 1) / g;
+    const size_t gslots = (size_t)G * (G - 1) / 2;   // slots per group
+    const int per_f = m / GV_ROWS, per_b = m / GV_COLS;
+    for (int step = 0; step < ng; ++step) {
+        const int gi = trans ? ng - 1 - step : step;
+        const int J0 = gi * g, ns = M - J0 < g ? M - J0 : g;
+        const double* Wg = W ? W + gi * gslots * mm : nullptr;
+        if (!trans) {
+            hipLaunchKernelGGL((k_trsv_group_diag<false, G, Q>), dim3(ns * per_f), dim3(256), 0,
+                               s, Tinv, Wg, J0, ns, m, r, x);
+            const int rest = M - J0 - ns;
+            if (rest > 0)
+                hipLaunchKernelGGL((k_trsv_group_update<false, G, Q>), dim3(rest * per_f),
+                                   dim3(256), 0, s, L, J0, ns, J0 + ns, x, r);
+        } else {
+            hipLaunchKernelGGL((k_trsv_group_diag<true, G, Q>), dim3(ns * per_b), dim3(256), 0,
+                               s, Tinv, Wg, J0, ns, m, r, x);
+            if (J0 > 0)
+                hipLaunchKernelGGL((k_trsv_group_update<true, G, Q>), dim3(J0 * per_b),
+                                   dim3(256), 0, s, L, J0, ns, 0, x, r);
+        }
     }
 }
+
+}  // namespace
 
 hipError_t launch_trsv(const TileMat& L, const double* Tinv, const double* W, int M,
                        const double* b, double* r, double* x, bool trans, hipStream_t s)
 {
     if (M <= 0) return hipSuccess;
-    const int m = L.m, per = trans ? gv_per_tile<true>(m) : gv_per_tile<false>(m);
+    const int m = L.m;
     const hipError_t e = hipMemcpyAsync(r, b, (size_t)M * m * sizeof(double),
                                         hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess) return e;
-    if (W && M >= 2) {
-        const int P = M / 2;
-        const bool odd = M % 2 != 0;
-        const size_t mm = (size_t)m * m;
-        if (!trans) {
-            for (int p = 0; p < P; ++p) {
-                const int J = 2 * p, count = M - J - 2;
-                hipLaunchKernelGGL(k_trsv_diag2<false>, dim3(2 * per), dim3(256), 0, s, Tinv,
-                                   W + p * mm, J, m, r, x);
-                if (count > 0)
-                    hipLaunchKernelGGL(k_trsv_update2<false>, dim3(count * per), dim3(256), 0, s,
-                                       L, J, J + 2, x, r);
-            }
-            if (odd)
-                hipLaunchKernelGGL(k_trsv_diag<false>, dim3(per), dim3(256), 0, s, Tinv, M - 1, m,
-                                   r, x);
-        } else {
-            if (odd) {
-                hipLaunchKernelGGL(k_trsv_diag<true>, dim3(per), dim3(256), 0, s, Tinv, M - 1, m,
-                                   r, x);
-                hipLaunchKernelGGL(k_trsv_update<true>, dim3((M - 1) * per), dim3(256), 0, s, L,
-                                   M - 1, 0, x, r);
-            }
-            for (int p = P - 1; p >= 0; --p) {
-                const int J = 2 * p;
-                hipLaunchKernelGGL(k_trsv_diag2<true>, dim3(2 * per), dim3(256), 0, s, Tinv,
-                                   W + p * mm, J, m, r, x);
-                if (J > 0)
-                    hipLaunchKernelGGL(k_trsv_update2<true>, dim3(J * per), dim3(256), 0, s, L, J,
-                                       0, x, r);
-            }
-        }
-        return hipGetLastError();
-    }
-    for (int step = 0; step < M; ++step) {
-        const int J = trans ? M - 1 - step : step;
-        const int first = trans ? 0 : J + 1;
-        const int count = trans ? J : M - 1 - J;
-        if (trans) {
-            hipLaunchKernelGGL(k_trsv_diag<true>, dim3(per), dim3(256), 0, s, Tinv, J, m, r, x);
-            if (count > 0)
-                hipLaunchKernelGGL(k_trsv_update<true>, dim3(count * per), dim3(256), 0, s, L, J,
-                                   first, x, r);
-        } else {
-            hipLaunchKernelGGL(k_trsv_diag<false>, dim3(per), dim3(256), 0, s, Tinv, J, m, r, x);
-            if (count > 0)
-                hipLaunchKernelGGL(k_trsv_update<false>, dim3(count * per), dim3(256), 0, s, L, J,
-                                   first, x, r);
-        }
-    }
+    // group size and loads per lane and tile row (m <= 64 Q)
+    if (m <= 256) trsv_steps<4, 4>(L, Tinv, W, M, r, x, trans, s);
+    else if (m <= 512) trsv_steps<2, 8>(L, Tinv, W, M, r, x, trans, s);
+    else trsv_steps<2, 16>(L, Tinv, W, M, r, x, trans, s);
     return hipGetLastError();
 }
 

@@ -37,14 +37,15 @@ __global__ __launch_bounds__(WR * WC * 64, WR * WC / 2) void k_update_f64(
     update_block<BM, WR, WC>(tk, bi, bj, m, sh, threadIdx.x);
 }
 
-// Block size: the largest of 128, 64, 32 (dividing m) that still gives a
-// launch at least UPD_MIN_WG workgroups. Launches of one or two tiles (the
-// SYRK and the first GEMM of the next column, on the critical chain) thus use
-// small blocks spread over many compute units and finish sooner; every block
-// size accumulates each element over k in the same order (same bits).
+// Block size (FP64 and the mixed kernels): the largest of 128, 64, 32 (dividing
+// m) that still gives a launch at least UPD_MIN_WG workgroups. Launches of one
+// or two tiles (the SYRK and the first GEMM of the next column, on the
+// critical chain) thus use small blocks spread over many compute units and
+// finish sooner; every block size accumulates each element over k in the same
+// order (same bits).
 constexpr long UPD_MIN_WG = 128;
 
-int update_block_f64(int ntask, int m)
+int update_block_size(int ntask, int m)
 {
     if (m % 128 == 0 && (long)ntask * (m / 128) * (m / 128) >= UPD_MIN_WG) return 128;
     if (m % 64 == 0 && (long)ntask * (m / 64) * (m / 64) >= UPD_MIN_WG) return 64;
@@ -98,7 +99,7 @@ hipError_t launch_update_f64(const UpdateTask* d_tasks, int ntask, int m, const 
                              hipStream_t s)
 {
     if (ntask <= 0) return hipSuccess;
-    const int bm = update_block_f64(ntask, m);
+    const int bm = update_block_size(ntask, m);
     if (bm == 128) {
         const int nb = m / 128;
         hipLaunchKernelGGL((k_update_f64<128, 4, 4>), dim3(ntask * nb * nb), dim3(1024), 0, s, d_tasks, m, abort_info);

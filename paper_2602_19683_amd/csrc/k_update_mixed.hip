@@ -6,8 +6,8 @@
 // stay FP64.
 //
 // Same blocking as the FP64 kernel: one workgroup per 128 x 128 block of a
-// tile with 16 waves of 32 x 32 (a 64 x 64 block: 4 waves), XCD-aware block
-// order, LDS double buffering. FP32: v_mfma_f32_16x16x4_f32, k-slices of 16, LDS k-major.
+// tile with 16 waves of 32 x 32 (64 x 64 and 32 x 32 blocks, for launches of
+// few tiles: 4 waves), XCD-aware block order, LDS double buffering. FP32: v_mfma_f32_16x16x4_f32, k-slices of 16, LDS k-major.
 // BF16: v_mfma_f32_16x16x32_bf16, k-slices of 32, LDS row-major (each lane
 // reads 8 consecutive bf16 of one row). Both FP32-accumulator layouts put
 // element v of lane l at row 4 (l / 16) + v, column l % 16. A task may hold
@@ -154,16 +154,16 @@ hipError_t launch_update_mixed(const UpdateTask* d_tasks, int ntask, int m, int 
                                const int* abort_info, hipStream_t s)
 {
     if (ntask <= 0) return hipSuccess;
-    const bool big = m % 128 == 0;
-    const int BM = big ? 128 : 64;
-    const int nb = m / BM;
-    const dim3 grid(ntask * nb * nb);
+    const int bm = update_block_size(ntask, m);
+    const dim3 grid(ntask * (m / bm) * (m / bm));
     if (prec == GPR_MIXED_FP32) {
-        if (big) hipLaunchKernelGGL((k_update_f32<128, 4, 4>), grid, dim3(1024), 0, s, d_tasks, m, abort_info);
-        else hipLaunchKernelGGL((k_update_f32<64, 2, 2>), grid, dim3(256), 0, s, d_tasks, m, abort_info);
+        if (bm == 128) hipLaunchKernelGGL((k_update_f32<128, 4, 4>), grid, dim3(1024), 0, s, d_tasks, m, abort_info);
+        else if (bm == 64) hipLaunchKernelGGL((k_update_f32<64, 2, 2>), grid, dim3(256), 0, s, d_tasks, m, abort_info);
+        else hipLaunchKernelGGL((k_update_f32<32, 2, 2>), grid, dim3(256), 0, s, d_tasks, m, abort_info);
     } else {
-        if (big) hipLaunchKernelGGL((k_update_bf16<128, 4, 4>), grid, dim3(1024), 0, s, d_tasks, m, abort_info);
-        else hipLaunchKernelGGL((k_update_bf16<64, 2, 2>), grid, dim3(256), 0, s, d_tasks, m, abort_info);
+        if (bm == 128) hipLaunchKernelGGL((k_update_bf16<128, 4, 4>), grid, dim3(1024), 0, s, d_tasks, m, abort_info);
+        else if (bm == 64) hipLaunchKernelGGL((k_update_bf16<64, 2, 2>), grid, dim3(256), 0, s, d_tasks, m, abort_info);
+        else hipLaunchKernelGGL((k_update_bf16<32, 2, 2>), grid, dim3(256), 0, s, d_tasks, m, abort_info);
     }
     return hipGetLastError();
 }

@@ -423,6 +423,26 @@ def schedule_describe(M, Mhat, mode, variant=None):
     return tasks, launches
 
 
+def solve_plan_describe(M, tile):
+    """Host-only: the tile products that build the group inverses of the
+    vector solves (see gpr.h). Returns ``(G, tasks, terms)``: the group size
+    and int32 arrays of shape (T, 6) = (launch, out kind, out a, out b,
+    first_term, nterm) and (R, 7) = (A kind, a, b, B kind, a, b, alpha)."""
+    lib = _lib.load()
+    g, nt, nr = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int64()
+    st = lib.gpr_solve_plan_describe(M, tile, ctypes.byref(g), None, 0, ctypes.byref(nt), None, 0,
+                                     ctypes.byref(nr))
+    if st != GPR_OK:
+        raise GPRError(st, "gpr_solve_plan_describe")
+    tasks = np.zeros((nt.value, 6), dtype=np.int32)
+    terms = np.zeros((nr.value, 7), dtype=np.int32)
+    ip = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))  # noqa: E731
+    _check(lib.gpr_solve_plan_describe(M, tile, ctypes.byref(g), ip(tasks), nt.value,
+                                       ctypes.byref(nt), ip(terms), nr.value, ctypes.byref(nr)),
+           "gpr_solve_plan_describe")
+    return g.value, tasks, terms
+
+
 def adjoint_describe(M, G):
     """Host-only: the launch list of the reverse sweep of gpr_nlml_grad (see
     gpr.h). Returns ``(tasks, terms, launches)``: int32 arrays of shape
