@@ -340,10 +340,11 @@ def sweep_runs(args, log):
     """Smaller configurations: n = 4096, n_test = 1024 over tiles 128 / 256 /
     512 (time per fused FP64 call, and the assembly and factorisation-sweep
     parts from the per-launch timers), and the latency of n = 128,
-    n_test = 128, tile 32 in microseconds."""
+    n_test = 128, tile 32 in microseconds on the stream executor and on an
+    automatic-executor context (which picks the persistent one here)."""
     import torch
     from gpr_inputs import DEFAULT_HYPER, nfir_train_test
-    from paper_2602_19683_amd import Context
+    from paper_2602_19683_amd import GPR_EXEC_AUTO, Context
     d = lambda a: torch.from_numpy(a).to("cuda:0")
     out = {}
     n, ns = 4096, 1024
@@ -391,6 +392,20 @@ def sweep_runs(args, log):
         out["c1_latency_us"] = round(ms * 1e3, 1)
         out["c1_config"] = "n=128, n_test=128, D=8, tile 32, fp64, gpr_fit_predict (mean + full " \
                            "covariance), mean of 50 calls"
+        K.free()
+        ref = (mean.clone(), cov.clone())
+    # the same call on a GPR_EXEC_AUTO context, which runs this sweep on the
+    # persistent executor (one launch instead of the per-step launches)
+    with Context(0, executor=GPR_EXEC_AUTO) as actx:
+        K = None
+
+        def small_auto():
+            nonlocal K
+            K = actx.fit_predict(X1d, y1d, Xs1d, DEFAULT_HYPER, 32, "fp64", K=K, mean=mean,
+                                 cov=cov)[2]
+        ms = timed_calls(small_auto, 50, warm=5)
+        out["c1_latency_us_auto"] = round(ms * 1e3, 1)
+        out["c1_auto_bitwise_equal"] = bool(torch.equal(mean, ref[0]) and torch.equal(cov, ref[1]))
         K.free()
     log(f"sweeps: {out}")
     return out

@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define GPR_ABI_VERSION 9
+#define GPR_ABI_VERSION 10
 
 /* Status codes. */
 enum {
@@ -89,11 +89,19 @@ typedef enum {
  * a precomputed priority order and wait on per-tile progress counters in
  * device memory. Both give bitwise-identical results. The persistent
  * executor runs the FP64 and FP32-update sweeps; the BF16 sweeps of a context
- * created with it run on the streams. */
+ * created with it run on the streams. GPR_EXEC_AUTO chooses per sweep: the
+ * persistent executor for tiles of at most GPR_AUTO_PERSIST_TILE rows when
+ * the swept matrix (training rows, plus the test rows of a prediction sweep)
+ * has at most GPR_AUTO_PERSIST_ROWS rows, where its single launch beats the
+ * per-step launches of small tiles (measured on MI355X: about 2x at
+ * n = n_test = 128, tile 32), and the streams otherwise. */
 typedef enum {
     GPR_EXEC_STREAMS = 0,
-    GPR_EXEC_PERSISTENT = 1
+    GPR_EXEC_PERSISTENT = 1,
+    GPR_EXEC_AUTO = 2
 } gpr_executor;
+#define GPR_AUTO_PERSIST_TILE 64
+#define GPR_AUTO_PERSIST_ROWS 4096
 
 /* Order of the tile tasks of the factorisation (Sec. 4.2: the right-looking
  * algorithm of Fig. 1, and its left-looking variant).

@@ -9,5 +9,5 @@ calls that compute do, and they fail loudly when the library is missing."""
 from .gpr import (GPRError, Context, Tiled, NLML, schedule_describe, adjoint_describe,  # noqa: F401
                   persist_describe, solve_plan_describe, PRECISIONS)
 from ._lib import (GPR_FP64, GPR_MIXED_FP32, GPR_MIXED_BF16, GPR_EXEC_STREAMS,  # noqa: F401
-                   GPR_EXEC_PERSISTENT, GPR_STATE_K, GPR_STATE_L, GPR_ENOTPD, GPR_EINVAL,
-                   GPR_ENODEV, GPR_ENOTSUP)
+                   GPR_EXEC_PERSISTENT, GPR_EXEC_AUTO, GPR_STATE_K, GPR_STATE_L, GPR_ENOTPD,
+                   GPR_EINVAL, GPR_ENODEV, GPR_ENOTSUP)

@@ -9,7 +9,7 @@ LIB_PATH = os.path.join(HERE, "libgpr.so")
 
 GPR_OK, GPR_ENOTPD, GPR_EINVAL, GPR_ENOMEM, GPR_EHIP, GPR_ENODEV, GPR_ENOTSUP = 0, 1, -1, -2, -3, -4, -5
 GPR_FP64, GPR_MIXED_FP32, GPR_MIXED_BF16 = 0, 1, 2
-GPR_EXEC_STREAMS, GPR_EXEC_PERSISTENT = 0, 1
+GPR_EXEC_STREAMS, GPR_EXEC_PERSISTENT, GPR_EXEC_AUTO = 0, 1, 2
 GPR_RIGHT_LOOKING, GPR_LEFT_LOOKING = 0, 1
 GPR_STATE_EMPTY, GPR_STATE_K, GPR_STATE_L = 0, 1, 2
 

@@ -401,10 +401,15 @@ constexpr int SPLIT_MAX = 8;
 
 // The persistent executor runs FP64 and FP32-update sweeps; a context created
 // for it runs the BF16 sweeps (whose updates have no persistent form) on the
-// streams.
+// streams. GPR_EXEC_AUTO takes it for sweeps of small tiles over a small
+// matrix, where the streams' per-step launches dominate.
 bool use_persistent(const gpr_ctx* ctx, const SweepMats& X)
 {
-    return ctx->executor == GPR_EXEC_PERSISTENT && ctx->variant == GPR_RIGHT_LOOKING &&
+    const bool chosen =
+        ctx->executor == GPR_EXEC_PERSISTENT ||
+        (ctx->executor == GPR_EXEC_AUTO && X.m <= GPR_AUTO_PERSIST_TILE &&
+         (int64_t)(X.M + X.Mhat) * X.m <= GPR_AUTO_PERSIST_ROWS);
+    return chosen && ctx->variant == GPR_RIGHT_LOOKING &&
            (X.prec == GPR_FP64 || X.prec == GPR_MIXED_FP32);
 }
 
@@ -998,7 +1003,8 @@ int gpr_ctx_create(gpr_ctx** out, int device, int n_streams, gpr_executor ex)
 {
     if (!out || n_streams < 1) return GPR_EINVAL;
     *out = nullptr;
-    if (ex != GPR_EXEC_STREAMS && ex != GPR_EXEC_PERSISTENT) return GPR_EINVAL;
+    if (ex != GPR_EXEC_STREAMS && ex != GPR_EXEC_PERSISTENT && ex != GPR_EXEC_AUTO)
+        return GPR_EINVAL;
     int rc = check_device(device);
     if (rc) return rc;
     gpr_ctx* c = new (std::nothrow) gpr_ctx;

@@ -29,7 +29,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_abi_version_and_strerror():
     lib = _lib.load()
-    assert lib.gpr_abi_version() == 9
+    assert lib.gpr_abi_version() == 10
     for code in [0, 1, -1, -2, -3, -4, -5]:
         assert lib.gpr_strerror(code)
     assert b"unknown" in lib.gpr_strerror(12345)

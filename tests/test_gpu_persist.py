@@ -118,6 +118,37 @@ def test_mixed_precision_bitwise_equal_to_streams(ctxs, prec, n, ns, tile):
     say(f"  refinement {out[1][3]}")
 
 
+@pytest.mark.parametrize("n,ns,tile,persistent", [(128, 128, 32, True), (2048, 512, 64, True),
+                                                   (1000, 300, 128, False), (4096, 1024, 64, False)])
+def test_auto_executor_choice_and_bits(ctxs, n, ns, tile, persistent):
+    """GPR_EXEC_AUTO runs a sweep of small tiles over a small matrix on the
+    persistent executor and everything else on the streams (the profile's
+    launch counts show which), with the stream executor's bits either way."""
+    from paper_2602_19683_amd import GPR_EXEC_AUTO, Context
+    say(f"auto executor n={n} n_test={ns} tile={tile} (persistent expected: {persistent})")
+    s, _ = ctxs
+    X, y, Xs = nfir_train_test(n, ns)
+    Xd, yd, Xsd = dev(X), dev(y), dev(Xs)
+    mean_s, cov_s, K = s.fit_predict(Xd, yd, Xsd, DEFAULT_HYPER, tile)
+    ref = (host(mean_s), host(cov_s))
+    K.free()
+    with Context(0, executor=GPR_EXEC_AUTO) as a:
+        a.profile(True)
+        a.profile_read(reset=True)
+        mean, cov, K = a.fit_predict(Xd, yd, Xsd, DEFAULT_HYPER, tile)
+        got = (host(mean), host(cov))
+        assert a.sync()[0] == 0
+        prof = a.profile_read(reset=True)
+        a.profile(False)
+        K.free()
+    ran_persistent = prof["persist"][0] > 0
+    say(f"  persistent launches {prof['persist'][0]}, potrf launches {prof['potrf'][0]}")
+    assert ran_persistent == persistent
+    assert (prof["potrf"][0] == 0) == persistent
+    np.testing.assert_array_equal(got[0], ref[0])
+    np.testing.assert_array_equal(got[1], ref[1])
+
+
 def test_nlml_and_gradient_bitwise_equal_to_streams(ctxs):
     n, tile, h = 1024, 128, (0.3, 2.0, 0.5)
     say(f"persistent nlml_grad n={n} tile={tile}")
