@@ -26,7 +26,7 @@ FP64_PEAK_TFLOPS = 78.6     # MI355X dense FP64 (vector = matrix)
 # HBM bytes per dispatch of the tile-update kernel from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs scaled by a 1 GiB copy (profiles/fp64_c3_hbm_traffic.md); only
 # valid for the kernel source they were taken on (k_update.hip + k_update_dev.h).
-UPDATE_TRAFFIC = {"k_update_sha256_16": "b35aec3ee134a486", "bytes_per_launch": 971300717}
+UPDATE_TRAFFIC = {"k_update_sha256_16": "d33c82f84f89af05", "bytes_per_launch": 972816478}
 
 
 def update_source_hash():
