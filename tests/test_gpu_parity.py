@@ -197,6 +197,26 @@ def test_solve_matches_oracle(ctx):
     K.free()
 
 
+@pytest.mark.parametrize("tile,M", [(32, 1), (32, 5), (64, 2), (64, 3), (64, 7), (96, 9),
+                                    (256, 4), (256, 6), (512, 3), (512, 5)])
+def test_grouped_solves_ragged(ctx, tile, M):
+    """The vector solves take four tile rows per step (two above tile 256),
+    with the last group holding the rest: every remainder of M tile rows
+    (the last one ragged) against the oracle's alpha = K^{-1} y."""
+    n = M * tile - 5 if M * tile > 5 else M * tile
+    say(f"grouped solves n={n} tile={tile} (M={M})")
+    X, y = nfir(n, seed=M + tile)
+    K = ctx.assemble(dev(X), DEFAULT_HYPER, tile)
+    ctx.cholesky(K)
+    a = host(ctx.solve(K, dev(y)))
+    assert ctx.sync()[0] == 0
+    ref = oracle.predict(X, y, X[:1], DEFAULT_HYPER, want=("alpha",))["alpha"]
+    e = oracle.rel_err(a, ref)
+    say(f"  rel(alpha) = {e:.3e}")
+    assert e <= TOL
+    K.free()
+
+
 def run_predict(ctx, X, y, Xs, h, tile):
     Xd, yd, Xsd = dev(X), dev(y), dev(Xs)
     K = ctx.assemble(Xd, h, tile)
