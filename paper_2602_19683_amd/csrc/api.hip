@@ -563,8 +563,23 @@ int run_persist(gpr_ctx* ctx, const SweepMats& X, int mode, hipStream_t s)
 // Issues the launches of a planned sweep. Logical streams: 0 critical (the
 // caller's stream s), 1 panel, 2 bulk; with fewer streams in the context
 // they fold onto s. The extra streams fork from s and join back into it.
+// The extra streams join back into s: s waits for everything issued on them.
+int join_sweep(gpr_ctx* ctx, hipStream_t s)
+{
+    hipStream_t phys[3] = {s, ctx->n_streams >= 3 ? ctx->panel : s,
+                           ctx->n_streams >= 2 ? ctx->bulk : s};
+    for (int q = 1; q < 3; ++q) {
+        if (phys[q] == s || (q == 2 && phys[2] == phys[1])) continue;
+        HIP_TRY(hipEventRecord(ctx->ev_join, phys[q]));
+        HIP_TRY(hipStreamWaitEvent(s, ctx->ev_join, 0));
+    }
+    return GPR_OK;
+}
+
+// With join false the caller joins later (join_sweep): work issued on s in
+// between runs after the sweep's launches on s only, beside the rest.
 int run_sweep(gpr_ctx* ctx, const SweepMats& X, const SweepPlan& P, const DescBuffer& db,
-              hipStream_t s)
+              hipStream_t s, bool join = true)
 {
     if (P.err) return P.err;
     if (P.persistent) return run_persist(ctx, X, P.mode, s);
@@ -696,12 +711,7 @@ int run_sweep(gpr_ctx* ctx, const SweepMats& X, const SweepPlan& P, const DescBu
         if (signal[li]) HIP_TRY(launch_signal(sigflag, signal[li], st));
         if (waited[li]) HIP_TRY(hipEventRecord(ctx->evpool[li], st));
     }
-    for (int q = 1; q < 3; ++q) {
-        if (phys[q] == s || (q == 2 && phys[2] == phys[1])) continue;
-        HIP_TRY(hipEventRecord(ctx->ev_join, phys[q]));
-        HIP_TRY(hipStreamWaitEvent(s, ctx->ev_join, 0));
-    }
-    return GPR_OK;
+    return join ? join_sweep(ctx, s) : GPR_OK;
 }
 
 int alloc_tiled(gpr_ctx* ctx, int64_t n, int m, gpr_tiled** out)
@@ -1260,9 +1270,32 @@ int predict_impl(gpr_ctx* ctx, gpr_tiled* L, const double* X, const double* y, i
                                     h.vertical_variance, h.noise_variance, false, false, s));
     }
     if (fused) HIP_TRY(launch_set_int(ctx->d_info, 0, s));
+    // In a factorising sweep with test rows, the critical stream's last launch
+    // (POTRF of the last tile column) completes the training factor: every
+    // training tile was final before it (its own updates waited for them).
+    // What the other streams still run touches only the test rows (V^T and
+    // the test block), so the inverses, the solves and the mean go on s
+    // beside it, and s joins them before the covariance or variances are
+    // read. Every return below joins first.
+    struct DeferredJoin {
+        gpr_ctx* c;
+        hipStream_t st;
+        bool pending;
+        int now()
+        {
+            pending = false;
+            return join_sweep(c, st);
+        }
+        ~DeferredJoin()
+        {
+            if (pending) (void)join_sweep(c, st);
+        }
+    } dj{ctx, s, false};
     if (fused || rows) {
-        rc = run_sweep(ctx, SM, PP, db, s);
+        const bool defer = fused && rows && !PP.persistent;
+        rc = run_sweep(ctx, SM, PP, db, s, !defer);
         if (rc) return rc;
+        dj.pending = defer;
     }
     if (fused) {
         {
@@ -1387,6 +1420,10 @@ int predict_impl(gpr_ctx* ctx, gpr_tiled* L, const double* X, const double* y, i
         HIP_TRY(launch_kernel_matvec(Xs, n_test, X, n, D, h.lengthscale, h.vertical_variance,
                                      h.noise_variance, false, alpha_used, nullptr, mean, mvw,
                                      s));
+    }
+    if (dj.pending) {
+        rc = dj.now();
+        if (rc) return rc;
     }
     if (cov) {
         ProfScope ps(ctx, s, PK_EXPORT, 0.0, (double)n_test * n_test * sizeof(double));
