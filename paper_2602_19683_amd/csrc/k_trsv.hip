@@ -4,8 +4,8 @@
 // per step (G = trsv_group(m): 4 for tiles up to 256, else 2). The inverse of
 // the group's G x G block of tiles is known: its diagonal tiles are the
 // diagonal-tile inverses Tinv, its off-diagonal tiles Inv_ij (i > j) are built
-// once per factor (api.hip). Forward, group g = tiles J0 .. J0 + ns - 1
-// (r = b on entry):
+// once per factor (the plan in solve_plan.cpp, run by api.hip). Forward,
+// group g = tiles J0 .. J0 + ns - 1 (r = b on entry):
 //     x_{J0+i} = sum_{j <= i} Inv_ij r_{J0+j}                  (one launch)
 //     r_K -= sum_j L_{K,J0+j} x_{J0+j},  K >= J0 + ns          (one launch)
 // Backward over the groups in reverse, with transposed tiles:
