@@ -164,11 +164,21 @@ namespace {
         if ((expr) != hipSuccess) return GPR_EHIP;    \
     } while (0)
 
+// The number of devices is read once per process (the query costs far more
+// than a launch, and every entry point checks its device); the device is made
+// current only when it is not already.
 int check_device(int device)
 {
-    int count = 0;
-    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return GPR_ENODEV;
+    static int count = 0;
+    static std::once_flag once;
+    std::call_once(once, [] {
+        int c = 0;
+        count = hipGetDeviceCount(&c) == hipSuccess ? c : 0;
+    });
+    if (count <= 0) return GPR_ENODEV;
     if (device < 0 || device >= count) return GPR_ENODEV;
+    int cur = -1;
+    if (hipGetDevice(&cur) == hipSuccess && cur == device) return GPR_OK;
     if (hipSetDevice(device) != hipSuccess) return GPR_EHIP;
     return GPR_OK;
 }
