@@ -673,7 +673,7 @@ def main():
                     help="only run one device-to-device copy of MIB MiB (for HBM counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs the GP hot path on one GPU only; "
+        print("bench.py: the GP hot path runs on one GPU only here; "
               "multi-GPU sharding is a design note, not a measured path (use --gpus 1)",
               file=sys.stderr)
         sys.exit(2)

@@ -58,7 +58,7 @@ enum {
     GPR_ENOMEM = -2,  /* device allocation failed or exceeded the cap      */
     GPR_EHIP = -3,    /* a HIP runtime call failed                         */
     GPR_ENODEV = -4,  /* no usable GPU                                     */
-    GPR_ENOTSUP = -5  /* option not available in this build                */
+    GPR_ENOTSUP = -5  /* option not available in this library              */
 };
 
 /* Hyperparameters of eq. (1): lengthscale l, vertical variance v and noise
@@ -156,7 +156,7 @@ enum { GPR_STATE_EMPTY = 0, GPR_STATE_K = 1, GPR_STATE_L = 2 };
  * schedule order (no overlap; useful to time kernels in isolation); with 2
  * the panel work shares the caller's stream.
  * Returns GPR_ENODEV if the device does not exist, GPR_ENOTSUP for an
- * executor this build lacks. On success *out must later go to
+ * executor this library lacks. On success *out must later go to
  * gpr_ctx_destroy.
  * Device-memory cap: if the environment variable GPR_MAX_DEVICE_BYTES holds a
  * positive integer when the context is created, the device memory held by

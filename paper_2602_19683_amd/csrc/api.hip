@@ -1014,7 +1014,7 @@ const char* gpr_strerror(int status)
     case GPR_ENOMEM: return "device allocation failed";
     case GPR_EHIP: return "HIP runtime error";
     case GPR_ENODEV: return "no usable GPU device";
-    case GPR_ENOTSUP: return "not supported by this build";
+    case GPR_ENOTSUP: return "not supported by this library";
     default: return "unknown status";
     }
 }
