@@ -191,7 +191,8 @@ int gpr_assemble(gpr_ctx* ctx, const double* X, int64_t n, int32_t D,
  * Sec. 4.2 (Fig. 1). The handle must hold K (GPR_EINVAL otherwise); it holds
  * L afterwards, plus the inverse of every diagonal tile of L and of the
  * blocks of G x G tiles that the solves take in one step (G = 4 for tiles up
- * to 256, else 2; see gpr_solve_plan_describe). prec chooses the precision of
+ * to 256, and up to 512 with FP32 or BF16 updates, whose refinement runs many
+ * solves; else 2; see gpr_solve_plan_describe). prec chooses the precision of
  * the GEMM/SYRK updates.
  * info_dev (optional, device int32): set to 0, or to the 1-based global
  * column of the first pivot that was not > 0 (LAPACK convention); gpr_sync
@@ -439,7 +440,10 @@ int gpr_adjoint_describe(int32_t M, int32_t G, int32_t* tasks, int64_t task_cap,
 /* The tile products that build the group inverses of the vector solves
  * (Sec. 4.1: beta = L^{-1} y and alpha = L^{-T} beta by block substitution,
  * G tile rows per step) for M tile rows of size `tile`, without running
- * anything (host only). *group receives G (4 for tiles up to 256, else 2).
+ * anything (host only), as for an FP64 factor. *group receives G (4 for
+ * tiles up to 256, else 2). The plan depends on M and G only: a factor with
+ * FP32 or BF16 updates and a tile above 256 and up to 512 (G = 4) has the plan
+ * returned for the same M and tile 256.
  * Group g holds tiles gG .. gG + G - 1; the off-diagonal tile (i, j), i > j,
  * of the inverse of its block goes to W slot g G (G - 1) / 2 + i (i - 1) / 2
  * + j. Operands are symbolic (kind, a, b): kind 0 tile (a, b) of L, 1 the

@@ -153,6 +153,9 @@ struct gpr_tiled {
     char* tpair_host = nullptr;   // their pinned host copy
     std::vector<TinvLaunch> tg_launches;  // those launches: descriptor offsets, task counts
     double tg_flops = 0.0;
+    int tgroup = 0;               // tile rows per step of the vector solves (G)
+    size_t tpair_bytes = 0;       // sizes of tpair and tpair_desc
+    size_t tdesc_bytes = 0;
     int state = GPR_STATE_EMPTY;
     int prec = GPR_FP64;
 };
@@ -769,18 +772,34 @@ bool valid_prec(int prec, int m)
 }
 
 // Off-diagonal tiles of the inverses of the G x G blocks of tiles that the
-// vector solves take in one step (k_trsv.hip; G = trsv_group(m)), built by the
-// batched tile-product launches of plan_tinv_groups (solve_plan.cpp): W slots
-// in the first half of tpair, the scratch products Y in the second. Needs the
-// diagonal-tile inverses; the handle's data and tinv buffers are allocated
-// before and never move, so the descriptors are written once per handle.
-int build_tinv_pairs(gpr_ctx* ctx, gpr_tiled* L, hipStream_t s)
+// vector solves take in one step (k_trsv.hip; G = trsv_group(m, prec)), built
+// by the batched tile-product launches of plan_tinv_groups (solve_plan.cpp):
+// W slots in the first half of tpair, the scratch products Y in the second.
+// Needs the diagonal-tile inverses; the handle's data and tinv buffers are
+// allocated before and never move, so the descriptors are written once per
+// handle and group size (a factorisation in another precision may change G).
+int build_tinv_pairs(gpr_ctx* ctx, gpr_tiled* L, int prec, hipStream_t s)
 {
     const int M = L->M, m = L->m;
+    const int G = trsv_group(m, prec);
+    if (L->tpair && L->tgroup != G) {
+        // earlier solves on any stream may still read the old tiles
+        if (hipDeviceSynchronize() != hipSuccess) return GPR_EHIP;
+        budget_free(L->budget, L->tpair, L->tpair_bytes);
+        budget_free(L->budget, L->tpair_desc, L->tdesc_bytes);
+        L->dev_bytes -= L->tpair_bytes + L->tdesc_bytes;
+        (void)hipHostFree(L->tpair_host);
+        L->tpair = nullptr;
+        L->tpair_desc = nullptr;
+        L->tpair_host = nullptr;
+        L->tpair_bytes = L->tdesc_bytes = 0;
+        L->tg_launches.clear();
+    }
+    L->tgroup = G;
     if (M < 2) return GPR_OK;
     const size_t mm = (size_t)m * m;
     if (!L->tpair) {
-        const TinvPlan P = plan_tinv_groups(M, trsv_group(m));
+        const TinvPlan P = plan_tinv_groups(M, G);
         if (!tinv_plan_valid(P)) return GPR_EINVAL;
         const size_t wbytes = 2 * (size_t)P.nslot * mm * sizeof(double);
         const size_t tb = (P.tasks.size() * sizeof(TGemmTask) + 63) & ~size_t(63);
@@ -795,7 +814,7 @@ int build_tinv_pairs(gpr_ctx* ctx, gpr_tiled* L, hipStream_t s)
             host = nullptr;
             rc = GPR_ENOMEM;
         }
-        if (rc) {   // nothing kept: the next call plans again
+        auto drop = [&](int code) {   // nothing kept: the next call plans again
             if (W) {
                 budget_free(L->budget, W, wbytes);
                 L->dev_bytes -= wbytes;
@@ -804,10 +823,10 @@ int build_tinv_pairs(gpr_ctx* ctx, gpr_tiled* L, hipStream_t s)
                 budget_free(L->budget, desc, tb + ub);
                 L->dev_bytes -= tb + ub;
             }
-            return rc;
-        }
-        L->tpair_desc = desc;
-        L->tpair_host = host;
+            if (host) (void)hipHostFree(host);
+            return code;
+        };
+        if (rc) return drop(rc);
         double* Y = W + (size_t)P.nslot * mm;
         const TileMat Lm = kmat(L);
         auto ptr = [&](const TinvRef& r) -> const double* {
@@ -827,7 +846,12 @@ int build_tinv_pairs(gpr_ctx* ctx, gpr_tiled* L, hipStream_t s)
         }
         for (size_t u = 0; u < P.terms.size(); ++u)
             tm[u] = TGemmTerm{ptr(P.terms[u].A), ptr(P.terms[u].B), P.terms[u].alpha, m, m, 0, 0};
-        HIP_TRY(hipMemcpyAsync(desc, host, tb + ub, hipMemcpyHostToDevice, s));
+        if (hipMemcpyAsync(desc, host, tb + ub, hipMemcpyHostToDevice, s) != hipSuccess) {
+            (void)hipGetLastError();
+            return drop(GPR_EHIP);
+        }
+        L->tpair_desc = desc;
+        L->tpair_host = host;
         L->tg_launches.clear();
         for (const TinvLaunchPlan& lp : P.launches)
             L->tg_launches.push_back(TinvLaunch{lp.first_task * sizeof(TGemmTask),
@@ -835,6 +859,8 @@ int build_tinv_pairs(gpr_ctx* ctx, gpr_tiled* L, hipStream_t s)
                                                 lp.ntask});
         L->tg_flops = 2.0 * (double)P.terms.size() * m * mm;
         L->tpair = W;
+        L->tpair_bytes = wbytes;
+        L->tdesc_bytes = tb + ub;
     }
     ProfScope ps(ctx, s, PK_TRTRI, L->tg_flops, 0.0);
     for (const TinvLaunch& t : L->tg_launches) {
@@ -857,11 +883,11 @@ int run_trsv_pair(gpr_ctx* ctx, const gpr_tiled* L, const double* rhs, double* t
     const double f = 2.0 * (double)m * m * ((double)M * (M - 1) / 2 + M);
     {
         ProfScope ps(ctx, s, PK_TRSV, f, 0.0);
-        HIP_TRY(launch_trsv(kmat(L), L->tinv, L->tpair, M, rhs, tmp, beta, false, s));
+        HIP_TRY(launch_trsv(kmat(L), L->tinv, L->tpair, L->tgroup, M, rhs, tmp, beta, false, s));
     }
     if (alpha) {
         ProfScope ps(ctx, s, PK_TRSV, f, 0.0);
-        HIP_TRY(launch_trsv(kmat(L), L->tinv, L->tpair, M, beta, tmp, alpha, true, s));
+        HIP_TRY(launch_trsv(kmat(L), L->tinv, L->tpair, L->tgroup, M, beta, tmp, alpha, true, s));
     }
     return GPR_OK;
 }
@@ -1162,7 +1188,7 @@ int gpr_cholesky(gpr_ctx* ctx, gpr_tiled* K, gpr_precision prec, int32_t* info_d
         ProfScope ps(ctx, s, PK_TRTRI, M * (double)m * m * m / 3.0, 0.0);
         HIP_TRY(launch_trtri_f64(kmat(K), M, K->tinv, s));
     }
-    rc = build_tinv_pairs(ctx, K, s);
+    rc = build_tinv_pairs(ctx, K, prec, s);
     if (rc) return rc;
     rc = finish_info(ctx, info_dev, s);
     if (rc) return rc;
@@ -1312,7 +1338,7 @@ int predict_impl(gpr_ctx* ctx, gpr_tiled* L, const double* X, const double* y, i
             ProfScope ps(ctx, s, PK_TRTRI, M * (double)m * m * m / 3.0, 0.0);
             HIP_TRY(launch_trtri_f64(kmat(L), M, L->tinv, s));
         }
-        rc = build_tinv_pairs(ctx, L, s);
+        rc = build_tinv_pairs(ctx, L, prec, s);
         if (rc) return rc;
     }
     if (fused) {
@@ -1545,7 +1571,7 @@ int nlml_launch(gpr_ctx* ctx, NlmlRun& R, const double* X, const double* y, int6
         ProfScope ps(ctx, s, PK_TRTRI, M * (double)m * m * m / 3.0, 0.0);
         HIP_TRY(launch_trtri_f64(kmat(K), M, K->tinv, s));
     }
-    rc = build_tinv_pairs(ctx, K, s);
+    rc = build_tinv_pairs(ctx, K, GPR_FP64, s);
     if (rc) return rc;
     K->state = GPR_STATE_L;
     K->prec = GPR_FP64;
@@ -1685,8 +1711,8 @@ int gpr_solve_noalloc(gpr_ctx* ctx, gpr_tiled* L, const double* b, double* x, vo
     double* beta = r + npad;
     double* tmp = beta + npad;
     HIP_TRY(launch_copy_f64(b, r, L->n, (int64_t)npad, s));
-    HIP_TRY(launch_trsv(kmat(L), L->tinv, L->tpair, L->M, r, tmp, beta, false, s));
-    HIP_TRY(launch_trsv(kmat(L), L->tinv, L->tpair, L->M, beta, tmp, r, true, s));
+    HIP_TRY(launch_trsv(kmat(L), L->tinv, L->tpair, L->tgroup, L->M, r, tmp, beta, false, s));
+    HIP_TRY(launch_trsv(kmat(L), L->tinv, L->tpair, L->tgroup, L->M, beta, tmp, r, true, s));
     HIP_TRY(launch_copy_f64(r, x, L->n, L->n, s));
     return end_call(ctx, s);
 }

@@ -171,15 +171,16 @@ hipError_t launch_signal(unsigned* flag, unsigned v, hipStream_t s);
 // the inverse of tile J goes to Tinv + J m^2 (leading dimension m), whose
 // 32 x 32 diagonal blocks must already hold the block inverses.
 hipError_t launch_trtri_f64(const TileMat& K, int M, double* Tinv, hipStream_t s);
-// Tile rows per step of the vector solves for tile size m (4 or 2).
-int trsv_group(int m);
+// Tile rows per step of the vector solves for tile size m and the precision
+// of the factor's updates (4 or 2).
+int trsv_group(int m, int prec);
 // x = L^{-1} b (trans: L^{-T} b) over the lower tiles of L with the inverses of
 // its diagonal tiles (Tinv, M tiles); r: scratch of length M m (b is copied
 // there first). W (nullable): the off-diagonal tiles of the inverses of the
-// G x G blocks of tiles (G = trsv_group(m); group g = tiles g G ..), Inv_ij
-// (i > j, relative indices) at tile g G (G - 1) / 2 + i (i - 1) / 2 + j; with
-// it, two launches per group of tile rows, else per tile row.
-hipError_t launch_trsv(const TileMat& L, const double* Tinv, const double* W, int M,
+// G x G blocks of tiles (G = 4 with m <= 512, or 2; group g = tiles g G ..),
+// Inv_ij (i > j, relative indices) at tile g G (G - 1) / 2 + i (i - 1) / 2 + j;
+// with it, two launches per group of tile rows, else per tile row.
+hipError_t launch_trsv(const TileMat& L, const double* Tinv, const double* W, int G, int M,
                        const double* b, double* r, double* x, bool trans, hipStream_t s);
 
 // out_i = base_i - k(A_i, B) x  (subtract) or out_i = k(A_i, B) x  (base == nullptr),

@@ -1,7 +1,9 @@
 // k_trsv.hip -- the triangular vector solves of the prediction (Sec. 4.1,
 // after eq. (2)): beta = L^{-1} b and alpha = L^{-T} beta by block
 // substitution over the lower tiles of L, a group of G consecutive tile rows
-// per step (G = trsv_group(m): 4 for tiles up to 256, else 2). The inverse of
+// per step (G = trsv_group(m, prec): 4 for tiles up to 256, and up to 512
+// for a factor with mixed-precision updates, whose refinement runs many
+// solves; else 2). The inverse of
 // the group's G x G block of tiles is known: its diagonal tiles are the
 // diagonal-tile inverses Tinv, its off-diagonal tiles Inv_ij (i > j) are built
 // once per factor (the plan in solve_plan.cpp, run by api.hip). Forward,
@@ -227,7 +229,10 @@ __global__ __launch_bounds__(256) void k_trsv_group_update(TileMat L, int J0, in
     }
 }
 
-int trsv_group(int m) { return m <= 256 ? 4 : 2; }
+int trsv_group(int m, int prec)
+{
+    return (m <= 256 || (prec != GPR_FP64 && m <= 512)) ? 4 : 2;
+}
 
 namespace {
 
@@ -265,7 +270,7 @@ void trsv_steps(const TileMat& L, const double* Tinv, const double* W, int M, do
 
 }  // namespace
 
-hipError_t launch_trsv(const TileMat& L, const double* Tinv, const double* W, int M,
+hipError_t launch_trsv(const TileMat& L, const double* Tinv, const double* W, int G, int M,
                        const double* b, double* r, double* x, bool trans, hipStream_t s)
 {
     if (M <= 0) return hipSuccess;
@@ -273,11 +278,12 @@ hipError_t launch_trsv(const TileMat& L, const double* Tinv, const double* W, in
     const hipError_t e = hipMemcpyAsync(r, b, (size_t)M * m * sizeof(double),
                                         hipMemcpyDeviceToDevice, s);
     if (e != hipSuccess) return e;
-    // group size and loads per lane and tile row (m <= 64 Q)
-    if (m <= 256) trsv_steps<4, 4>(L, Tinv, W, M, r, x, trans, s);
-    else if (m <= 512) trsv_steps<2, 8>(L, Tinv, W, M, r, x, trans, s);
-    else trsv_steps<2, 16>(L, Tinv, W, M, r, x, trans, s);
+    // group size of W, and loads per lane and tile row (m <= 64 Q)
+    if (G == 4 && m <= 256) trsv_steps<4, 4>(L, Tinv, W, M, r, x, trans, s);
+    else if (G == 4 && m <= 512) trsv_steps<4, 8>(L, Tinv, W, M, r, x, trans, s);
+    else if (G == 2 && m <= 512) trsv_steps<2, 8>(L, Tinv, W, M, r, x, trans, s);
+    else if (G == 2) trsv_steps<2, 16>(L, Tinv, W, M, r, x, trans, s);
+    else return hipErrorInvalidValue;
     return hipGetLastError();
 }
-
 }  // namespace gpr

@@ -2,7 +2,7 @@
 // of the vector solves (Sec. 4.1, the two triangular solves after eq. (2)),
 // planned on the host with symbolic operands.
 //
-// The solves take G consecutive tile rows per step (G = trsv_group(m)); a step
+// The solves take G consecutive tile rows per step (G = trsv_group(m, prec)); a step
 // applies the inverse of the group's G x G block of tiles of L. Its diagonal
 // tiles are the inverses of the diagonal tiles of L; its off-diagonal tiles
 // Inv_ij (i > j, indices relative to the group's first tile J0) are built by
@@ -96,7 +96,7 @@ extern "C" int gpr_solve_plan_describe(int32_t M, int32_t tile, int32_t* group, 
     using namespace gpr;
     if (M < 1 || tile < 32 || tile > 1024 || tile % 32 != 0 || !n_tasks || !n_terms)
         return GPR_EINVAL;
-    const TinvPlan P = plan_tinv_groups(M, trsv_group(tile));
+    const TinvPlan P = plan_tinv_groups(M, trsv_group(tile, GPR_FP64));
     if (group) *group = P.G;
     *n_tasks = (int64_t)P.tasks.size();
     *n_terms = (int64_t)P.terms.size();

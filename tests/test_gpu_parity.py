@@ -466,3 +466,41 @@ def test_mixed_cholesky_then_predict(ctx):
     say(f"  IR steps {st['iters']}, ||r||/||y|| {st['rel_residual']:.2e}, rel(mean) {em:.2e}")
     assert st["iters"] >= 1 and em <= MEAN_TOL_MIXED
     K.free()
+
+
+@pytest.mark.parametrize("M", [5, 6, 7, 8])
+def test_mixed_grouped_solves_tile512(ctx, M):
+    """A factor with FP32 updates takes four tile rows per solve step up to
+    tile 512 (an FP64 factor two there), for each remainder of M tile rows
+    (the last one ragged): the solves against triangular solves with the
+    factor actually held, the refined mean against the oracle, then the same
+    handle factored in FP64 again (back to two rows per step) against the
+    oracle's alpha."""
+    from scipy.linalg import solve_triangular
+    tile = 512
+    n, ns = M * tile - 5, 64
+    say(f"mixed fp32 grouped solves n={n} tile={tile} (M={M})")
+    X, y, Xs = nfir_train_test(n, ns)
+    ref = oracle.predict(X, y, Xs, DEFAULT_HYPER, want=("alpha", "mean"))
+    Xd, yd, Xsd = dev(X), dev(y), dev(Xs)
+    K = ctx.assemble(Xd, DEFAULT_HYPER, tile)
+    ctx.cholesky(K, "fp32")
+    a = host(ctx.solve(K, yd))
+    L = host(ctx.to_dense(K))
+    mean, _, st = ctx.predict(K, Xd, yd, Xsd, DEFAULT_HYPER, full_cov=False, ir_stats=True)
+    assert ctx.sync()[0] == 0
+    L = np.tril(L)
+    held = solve_triangular(L.T, solve_triangular(L, y, lower=True), lower=False)
+    ea = oracle.rel_err(a, held)
+    em = oracle.rel_err(host(mean), ref["mean"])
+    say(f"  rel(alpha vs held factor) {ea:.2e}; refinement steps {st['iters']}, "
+        f"rel(mean) {em:.2e}")
+    assert ea <= TOL and em <= MEAN_TOL_MIXED
+    ctx.assemble(Xd, DEFAULT_HYPER, tile, K=K)
+    ctx.cholesky(K)
+    a64 = host(ctx.solve(K, yd))
+    assert ctx.sync()[0] == 0
+    e64 = oracle.rel_err(a64, ref["alpha"])
+    say(f"  FP64 again: rel(alpha) {e64:.2e}")
+    assert e64 <= TOL
+    K.free()
