@@ -22,6 +22,13 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Cholesky+predict GFLOP/s & % peak at n=16384, FP64 vs mixed, at stated error"
 FP64_PEAK_TFLOPS = 78.6     # MI355X dense FP64 (vector = matrix)
+# the tile-update kernel of each precision and the dense matrix peak of its
+# operand type (TFLOP/s)
+UPDATE_KERNEL = {"fp64": ("k_update_f64 (GEMM/SYRK tile updates)", FP64_PEAK_TFLOPS),
+                 "fp32": ("k_update_f32 (GEMM/SYRK tile updates, FP32 operands and "
+                          "accumulator)", 157.3),
+                 "bf16": ("k_update_bf16 (GEMM/SYRK tile updates, BF16 operands, FP32 "
+                          "accumulator)", 2500.0)}
 
 # HBM bytes per dispatch of the tile-update kernel from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs scaled by a 1 GiB copy (profiles/fp64_c3_hbm_traffic.md); only
@@ -535,7 +542,8 @@ def isolated_update_run(Xd, yd, Xsd, h, tile, precision, args, log):
            "update_avg_launch_ms": round(tms / max(nl, 1), 4),
            "update_ms_per_step": round(tms / args.steps, 4),
            "achieved": round(fl / (tms * 1e-3) / 1e12, 3) if tms else None,
-           "frac": round(fl / (tms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4) if tms else None}
+           "frac": round(fl / (tms * 1e-3) / 1e12 / UPDATE_KERNEL[precision][1], 4)
+           if tms else None}
     K.free()
     ctx.close()
     log(f"isolated update kernel (one stream): {out}")
@@ -753,12 +761,16 @@ def main():
     value = flops / (ms * 1e-3) / 1e9
     nl, tms, fl, _ = prof["persist" if persistent_line else "update"]
     achieved = fl / (tms * 1e-3) / 1e12 if tms else 0.0
+    kname, peak = UPDATE_KERNEL[args.precision]
+    if persistent_line:
+        kname = "k_persist (the whole sweep: POTRF panels, TRSM strips, update blocks)"
     roofline = {"bound": "mfma",
-                "kernel": "k_persist (the whole sweep: POTRF panels, TRSM strips, update blocks)"
-                          if persistent_line else "k_update_f64 (GEMM/SYRK tile updates)",
-                "achieved": round(achieved, 3), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
-                "traffic": None if persistent_line else update_traffic(),
+                "kernel": kname,
+                "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(achieved / peak, 4),
+                # counters were taken for the FP64 kernel only
+                "traffic": update_traffic() if args.precision == "fp64" and not persistent_line
+                           else None,
                 "traffic_unit": "bytes per launch",
                 "avg_launch_ms": round(tms / max(nl, 1), 4),
                 "flops_per_launch": round(fl / max(nl, 1), 1),
@@ -768,7 +780,7 @@ def main():
                         "per step by the whole step time",
                 "step_level": {"achieved": round(fl / args.steps / (ms * 1e-3) / 1e12, 3),
                                "frac": round(fl / args.steps / (ms * 1e-3) / 1e12
-                                             / FP64_PEAK_TFLOPS, 4)}}
+                                             / peak, 4)}}
     if not args.no_isolated and not persistent_line:
         roofline["isolated"] = isolated_update_run(Xd, yd, Xsd, h, tile, args.precision, args,
                                                    log)
