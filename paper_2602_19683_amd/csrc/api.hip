@@ -1124,14 +1124,14 @@ int gpr_ctx_destroy(gpr_ctx* c)
     return GPR_OK;
 }
 
-int gpr_assemble(gpr_ctx* ctx, const double* X, int64_t n, int32_t D, gpr_hyper h, int32_t tile,
-                 gpr_tiled** K_inout, void* stream)
+namespace {
+// gpr_assemble; with_copy: the same launch also writes the FP64 copy of K that
+// a mixed-precision factorisation keeps for its refinement (K->kcopy), so
+// that no separate copy of the matrix is needed.
+int assemble_impl(gpr_ctx* ctx, const double* X, int64_t n, int32_t D, gpr_hyper h,
+                  int32_t tile, gpr_tiled** K_inout, hipStream_t s, bool with_copy)
 {
     Range range("gpr_assemble");
-    if (!ctx || !X || !K_inout || n < 1 || D < 1 || !valid_tile(tile) || !valid_hyper(h))
-        return GPR_EINVAL;
-    if (*K_inout && ((*K_inout)->n != n || (*K_inout)->m != tile)) return GPR_EINVAL;
-    hipStream_t s = static_cast<hipStream_t>(stream);
     int rc = begin_call(ctx, s);
     if (rc) return rc;
     gpr_tiled* K = *K_inout;
@@ -1139,12 +1139,19 @@ int gpr_assemble(gpr_ctx* ctx, const double* X, int64_t n, int32_t D, gpr_hyper 
         rc = alloc_tiled(ctx, n, tile, &K);
         if (rc) return rc;
     }
+    if (with_copy && !K->kcopy) {
+        rc = handle_malloc(K, reinterpret_cast<void**>(&K->kcopy), tiled_bytes(K));
+        if (rc) {
+            if (!*K_inout) gpr_tiled_free(K);
+            return rc;
+        }
+    }
     hipError_t e;
     {
-        ProfScope ps(ctx, s, PK_ASSEMBLE, 0.0,
-                     (double)K->M * (K->M + 1) / 2 * (double)K->m * K->m * sizeof(double));
+        ProfScope ps(ctx, s, PK_ASSEMBLE, 0.0, (with_copy ? 2.0 : 1.0) * (double)tiled_bytes(K));
         e = launch_assemble(kmat(K), K->M, X, n, X, n, D, h.lengthscale, h.vertical_variance,
-                            h.noise_variance, true, true, s);
+                            h.noise_variance, true, true, s, nullptr,
+                            with_copy ? K->kcopy : nullptr);
     }
     if (e != hipSuccess) {
         if (!*K_inout) gpr_tiled_free(K);
@@ -1154,6 +1161,16 @@ int gpr_assemble(gpr_ctx* ctx, const double* X, int64_t n, int32_t D, gpr_hyper 
     K->prec = GPR_FP64;
     *K_inout = K;
     return end_call(ctx, s);
+}
+}  // namespace
+
+int gpr_assemble(gpr_ctx* ctx, const double* X, int64_t n, int32_t D, gpr_hyper h, int32_t tile,
+                 gpr_tiled** K_inout, void* stream)
+{
+    if (!ctx || !X || !K_inout || n < 1 || D < 1 || !valid_tile(tile) || !valid_hyper(h))
+        return GPR_EINVAL;
+    if (*K_inout && ((*K_inout)->n != n || (*K_inout)->m != tile)) return GPR_EINVAL;
+    return assemble_impl(ctx, X, n, D, h, tile, K_inout, static_cast<hipStream_t>(stream), false);
 }
 
 int gpr_cholesky(gpr_ctx* ctx, gpr_tiled* K, gpr_precision prec, int32_t* info_dev, void* stream)
@@ -1247,7 +1264,7 @@ constexpr int RETRY_HIGHER = 100;
 int predict_impl(gpr_ctx* ctx, gpr_tiled* L, const double* X, const double* y, int64_t n,
                  const double* Xs, int64_t n_test, int32_t D, const gpr_hyper& h, double* mean,
                  double* cov, double* var, int32_t* info_dev, hipStream_t s, bool fused,
-                 int prec, gpr_ir_stats* ir)
+                 int prec, gpr_ir_stats* ir, bool kcopy_written = false)
 {
     const int m = L->m, M = L->M;
     const int Mhat = (int)((n_test + m - 1) / m);
@@ -1292,7 +1309,7 @@ int predict_impl(gpr_ctx* ctx, gpr_tiled* L, const double* X, const double* y, i
     rc = db.upload(ctx, s);
     if (rc) return rc;
 
-    if (fused && prec != GPR_FP64) {
+    if (fused && prec != GPR_FP64 && !kcopy_written) {
         rc = save_kcopy(L, s);
         if (rc) return rc;
     }
@@ -1341,19 +1358,18 @@ int predict_impl(gpr_ctx* ctx, gpr_tiled* L, const double* X, const double* y, i
         rc = build_tinv_pairs(ctx, L, prec, s);
         if (rc) return rc;
     }
+    // a mixed factorisation made by this call: its pivot record is read on the
+    // host (a failed pivot makes the caller retry one precision higher, and
+    // the failure is not reported: no finish_info for this attempt), in the
+    // same round trip as the norms of y and of the first residual below
+    const bool check_pivot = fused && prec != GPR_FP64;
     if (fused) {
         L->state = GPR_STATE_L;
         L->prec = prec;
-        if (prec != GPR_FP64) {
-            // a failed pivot in a mixed precision: the caller retries higher,
-            // and the failure is not reported (no finish_info for this attempt)
-            int info = 0;
-            HIP_TRY(hipMemcpyAsync(&info, ctx->d_info, sizeof(int), hipMemcpyDeviceToHost, s));
-            HIP_TRY(hipStreamSynchronize(s));
-            if (info > 0) return RETRY_HIGHER;
+        if (!check_pivot) {
+            rc = finish_info(ctx, info_dev, s);
+            if (rc) return rc;
         }
-        rc = finish_info(ctx, info_dev, s);
-        if (rc) return rc;
     }
     // alpha = K^{-1} y via the two triangular solves (Sec. 4.1)
     HIP_TRY(launch_copy_f64(y, r, n, (int64_t)npad, s));
@@ -1370,30 +1386,44 @@ int predict_impl(gpr_ctx* ctx, gpr_tiled* L, const double* X, const double* y, i
         if (!L->kcopy) return GPR_EINVAL;
         const TileMat Kc{L->kcopy, m, 0, 0};
         HIP_TRY(launch_copy_f64(alpha, acc, (int64_t)npad, (int64_t)npad, s));
-        HIP_TRY(launch_sumsq(y, n, scal, s));
-        double yy = 0.0;
-        HIP_TRY(hipMemcpyAsync(&yy, scal, sizeof(double), hipMemcpyDeviceToHost, s));
+        // ||y||^2 in scal[1]; r = y - K acc (FP64, padding of r stays zero)
+        // and ||r||^2 in scal[0]; one host round trip for both (and the pivot)
+        HIP_TRY(launch_sumsq(y, n, scal + 1, s));
+        HIP_TRY(launch_symv_tiled(Kc, M, acc, y, r, n, svw, s));
+        HIP_TRY(launch_sumsq(r, n, scal, s));
+        double sq[2] = {0.0, 0.0};
+        int info = 0;
+        HIP_TRY(hipMemcpyAsync(sq, scal, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+        if (check_pivot)
+            HIP_TRY(hipMemcpyAsync(&info, ctx->d_info, sizeof(int), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
-        const double yn = std::sqrt(yy);
+        if (info > 0) return RETRY_HIGHER;
+        if (check_pivot) {
+            rc = finish_info(ctx, info_dev, s);
+            if (rc) return rc;
+        }
+        const double yn = std::sqrt(sq[1]);
+        auto rel_of = [&](double rr) { return yn > 0 ? std::sqrt(rr) / yn : std::sqrt(rr); };
         // ||r|| / ||y|| of the residual held in r (host round trip)
         auto residual = [&](double* out_rel) -> int {
             HIP_TRY(launch_sumsq(r, n, scal, s));
             double rr = 0.0;
             HIP_TRY(hipMemcpyAsync(&rr, scal, sizeof(double), hipMemcpyDeviceToHost, s));
             HIP_TRY(hipStreamSynchronize(s));
-            const double rn = std::sqrt(rr);
-            *out_rel = yn > 0 ? rn / yn : rn;
+            *out_rel = rel_of(rr);
             return GPR_OK;
         };
         constexpr int max_steps = 50;
-        double prev = -1.0, rel = -1.0;
+        double prev = -1.0, rel = rel_of(sq[0]);
         int it = 0;
         bool to_cg = false;
         for (; it <= max_steps; ++it) {
-            // r = y - K acc (FP64), padding of r stays zero
-            HIP_TRY(launch_symv_tiled(Kc, M, acc, y, r, n, svw, s));
-            rc = residual(&rel);
-            if (rc) return rc;
+            if (it > 0) {
+                // r = y - K acc (FP64), padding of r stays zero
+                HIP_TRY(launch_symv_tiled(Kc, M, acc, y, r, n, svw, s));
+                rc = residual(&rel);
+                if (rc) return rc;
+            }
             if (rel <= 1e-14 || it == max_steps) break;
             // a step that gains less than a factor 4 far above the rounding
             // floor: the iteration matrix I - (L~ L~^T)^{-1} K contracts slowly
@@ -1643,14 +1673,17 @@ int gpr_fit_predict_var(gpr_ctx* ctx, const double* X, const double* y, int64_t 
     hipStream_t s = static_cast<hipStream_t>(stream);
     // a mixed factorisation that fails (pivot, or refinement) is redone one
     // precision step higher: BF16 -> FP32 -> FP64
+    if (*K_inout && ((*K_inout)->n != n || (*K_inout)->m != tile)) return GPR_EINVAL;
     for (int p = (int)prec;; p = (p == GPR_MIXED_BF16) ? GPR_MIXED_FP32 : GPR_FP64) {
-        int rc = gpr_assemble(ctx, X, n, D, h, tile, K_inout, stream);
+        // a mixed factorisation's FP64 copy of K is written by the assembly
+        const bool copy = p != GPR_FP64;
+        int rc = assemble_impl(ctx, X, n, D, h, tile, K_inout, s, copy);
         if (rc) return rc;
         rc = begin_call(ctx, s);
         if (rc) return rc;
         gpr_tiled* K = *K_inout;
         rc = predict_impl(ctx, K, X, y, n, Xs, n_test, D, h, mean, cov, var, info_dev, s, true, p,
-                          ir);
+                          ir, copy);
         if (rc == RETRY_HIGHER && p != GPR_FP64) {
             rc = end_call(ctx, s);
             if (rc) return rc;

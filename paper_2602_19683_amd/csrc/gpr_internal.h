@@ -118,11 +118,12 @@ struct TGemmTask {
 // v exp(-|a_i - b_j|^2 / (2 l)) plus s2 where diag_noise and i == j;
 // otherwise (padding) 1 where identity_pad and i == j, else 0.
 // hyp (nullable, device, 3 doubles): when given, (l, v, s2) are read from it
-// by the kernel instead (hyperparameters kept on the device).
+// by the kernel instead (hyperparameters kept on the device). copy (nullable):
+// a second tile array of T's layout that receives the same values.
 hipError_t launch_assemble(const TileMat& T, int tile_rows, const double* A, int64_t na,
                            const double* B, int64_t nb, int D, double l, double v,
                            double s2, bool diag_noise, bool identity_pad,
-                           hipStream_t s, const double* hyp = nullptr);
+                           hipStream_t s, const double* hyp = nullptr, double* copy = nullptr);
 
 // Dense row-major n x n (ld) -> lower tiles of T (padding: identity).
 hipError_t launch_dense_to_tiled(const double* A, int64_t n, int64_t lda, const TileMat& T,

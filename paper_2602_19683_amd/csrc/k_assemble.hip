@@ -37,7 +37,8 @@ __global__ __launch_bounds__(256) void k_assemble(TileMat T, int tile_rows, int6
                                                   const double* __restrict__ A, int64_t na,
                                                   const double* __restrict__ B, int64_t nb, int D,
                                                   double l, double v, double s2, int diag_noise,
-                                                  int identity_pad, const double* __restrict__ hyp)
+                                                  int identity_pad, const double* __restrict__ hyp,
+                                                  double* __restrict__ copy)
 {
     if (hyp) {  // hyperparameters held on the device (l, v, sigma^2)
         l = hyp[0];
@@ -64,6 +65,7 @@ __global__ __launch_bounds__(256) void k_assemble(TileMat T, int tile_rows, int6
         const int64_t i0 = (int64_t)I * m + si * SB;
         const int64_t j0 = (int64_t)J * m + sj * SB;
         double* out = tile_ptr(T, I, J) + (size_t)si * SB * m + sj * SB;
+        double* cout = copy ? copy + (out - T.base) : nullptr;
 
         __syncthreads();
         for (int e = tid; e < SB * Dl; e += 256) {
@@ -106,6 +108,7 @@ __global__ __launch_bounds__(256) void k_assemble(TileMat T, int tile_rows, int6
                 val = (identity_pad && i == j) ? 1.0 : 0.0;
             }
             out[(size_t)r * m + c] = val;
+            if (cout) cout[(size_t)r * m + c] = val;
         }
     }
 }
@@ -120,7 +123,8 @@ __global__ __launch_bounds__(256) void k_assemble_w(TileMat T, int64_t ntiles,
                                                     const double* __restrict__ A, int64_t na,
                                                     const double* __restrict__ B, int64_t nb,
                                                     double l, double v, double s2, int diag_noise,
-                                                    int identity_pad, const double* __restrict__ hyp)
+                                                    int identity_pad, const double* __restrict__ hyp,
+                                                    double* __restrict__ copy)
 {
     if (hyp) {  // hyperparameters held on the device (l, v, sigma^2)
         l = hyp[0];
@@ -144,6 +148,7 @@ __global__ __launch_bounds__(256) void k_assemble_w(TileMat T, int64_t ntiles,
         const int r0 = si * 64 + wave * 16;    // first row of this wave, within the tile
         const int64_t j = (int64_t)J * m + sj * 64 + lane;
         double* out = tile_ptr(T, I, J) + (size_t)r0 * m + sj * 64 + lane;
+        double* cout = copy ? copy + (out - T.base) : nullptr;
         const bool jin = j < nb;
         double bc[DT];
 #pragma unroll
@@ -165,13 +170,15 @@ __global__ __launch_bounds__(256) void k_assemble_w(TileMat T, int64_t ntiles,
                 val = (identity_pad && i == j) ? 1.0 : 0.0;
             }
             out[(size_t)r * m] = val;
+            if (cout) cout[(size_t)r * m] = val;
         }
     }
 }
 
 hipError_t launch_assemble(const TileMat& T, int tile_rows, const double* A, int64_t na,
                            const double* B, int64_t nb, int D, double l, double v, double s2,
-                           bool diag_noise, bool identity_pad, hipStream_t s, const double* hyp)
+                           bool diag_noise, bool identity_pad, hipStream_t s, const double* hyp,
+                           double* copy)
 {
     const int64_t ntiles = T.layout == 0 ? (int64_t)tile_rows * (tile_rows + 1) / 2
                                          : (int64_t)tile_rows * T.ncolt;
@@ -184,7 +191,7 @@ hipError_t launch_assemble(const TileMat& T, int tile_rows, const double* A, int
         const int64_t g = items < 65536 ? items : 65536;
 #define GPR_ASMW(DT)                                                                             \
     hipLaunchKernelGGL(k_assemble_w<DT>, dim3((unsigned)g), dim3(256), 0, s, T, ntiles, A, na, B, \
-                       nb, l, v, s2, dn, ip, hyp)
+                       nb, l, v, s2, dn, ip, hyp, copy)
         switch (D) {
         case 1: GPR_ASMW(1); break;
         case 2: GPR_ASMW(2); break;
@@ -200,7 +207,7 @@ hipError_t launch_assemble(const TileMat& T, int tile_rows, const double* A, int
     }
 #define GPR_ASM(DT)                                                                              \
     hipLaunchKernelGGL(k_assemble<DT>, dim3((unsigned)grid), dim3(256), 0, s, T, tile_rows,     \
-                       ntiles, A, na, B, nb, D, l, v, s2, dn, ip, hyp)
+                       ntiles, A, na, B, nb, D, l, v, s2, dn, ip, hyp, copy)
     switch (D) {
     case 1: GPR_ASM(1); break;
     case 2: GPR_ASM(2); break;
