@@ -1022,6 +1022,46 @@ int finish_info(gpr_ctx* ctx, int32_t* info_dev, hipStream_t s)
 }
 }  // namespace
 
+namespace {
+// gpr_assemble; with_copy: the same launch also writes the FP64 copy of K that
+// a mixed-precision factorisation keeps for its refinement (K->kcopy), so
+// that no separate copy of the matrix is needed.
+int assemble_impl(gpr_ctx* ctx, const double* X, int64_t n, int32_t D, gpr_hyper h,
+                  int32_t tile, gpr_tiled** K_inout, hipStream_t s, bool with_copy)
+{
+    Range range("gpr_assemble");
+    int rc = begin_call(ctx, s);
+    if (rc) return rc;
+    gpr_tiled* K = *K_inout;
+    if (!K) {
+        rc = alloc_tiled(ctx, n, tile, &K);
+        if (rc) return rc;
+    }
+    if (with_copy && !K->kcopy) {
+        rc = handle_malloc(K, reinterpret_cast<void**>(&K->kcopy), tiled_bytes(K));
+        if (rc) {
+            if (!*K_inout) gpr_tiled_free(K);
+            return rc;
+        }
+    }
+    hipError_t e;
+    {
+        ProfScope ps(ctx, s, PK_ASSEMBLE, 0.0, (with_copy ? 2.0 : 1.0) * (double)tiled_bytes(K));
+        e = launch_assemble(kmat(K), K->M, X, n, X, n, D, h.lengthscale, h.vertical_variance,
+                            h.noise_variance, true, true, s, nullptr,
+                            with_copy ? K->kcopy : nullptr);
+    }
+    if (e != hipSuccess) {
+        if (!*K_inout) gpr_tiled_free(K);
+        return GPR_EHIP;
+    }
+    K->state = GPR_STATE_K;
+    K->prec = GPR_FP64;
+    *K_inout = K;
+    return end_call(ctx, s);
+}
+}  // namespace
+
 extern "C" {
 
 int gpr_abi_version(void) { return GPR_ABI_VERSION; }
@@ -1123,46 +1163,6 @@ int gpr_ctx_destroy(gpr_ctx* c)
     delete c;
     return GPR_OK;
 }
-
-namespace {
-// gpr_assemble; with_copy: the same launch also writes the FP64 copy of K that
-// a mixed-precision factorisation keeps for its refinement (K->kcopy), so
-// that no separate copy of the matrix is needed.
-int assemble_impl(gpr_ctx* ctx, const double* X, int64_t n, int32_t D, gpr_hyper h,
-                  int32_t tile, gpr_tiled** K_inout, hipStream_t s, bool with_copy)
-{
-    Range range("gpr_assemble");
-    int rc = begin_call(ctx, s);
-    if (rc) return rc;
-    gpr_tiled* K = *K_inout;
-    if (!K) {
-        rc = alloc_tiled(ctx, n, tile, &K);
-        if (rc) return rc;
-    }
-    if (with_copy && !K->kcopy) {
-        rc = handle_malloc(K, reinterpret_cast<void**>(&K->kcopy), tiled_bytes(K));
-        if (rc) {
-            if (!*K_inout) gpr_tiled_free(K);
-            return rc;
-        }
-    }
-    hipError_t e;
-    {
-        ProfScope ps(ctx, s, PK_ASSEMBLE, 0.0, (with_copy ? 2.0 : 1.0) * (double)tiled_bytes(K));
-        e = launch_assemble(kmat(K), K->M, X, n, X, n, D, h.lengthscale, h.vertical_variance,
-                            h.noise_variance, true, true, s, nullptr,
-                            with_copy ? K->kcopy : nullptr);
-    }
-    if (e != hipSuccess) {
-        if (!*K_inout) gpr_tiled_free(K);
-        return GPR_EHIP;
-    }
-    K->state = GPR_STATE_K;
-    K->prec = GPR_FP64;
-    *K_inout = K;
-    return end_call(ctx, s);
-}
-}  // namespace
 
 int gpr_assemble(gpr_ctx* ctx, const double* X, int64_t n, int32_t D, gpr_hyper h, int32_t tile,
                  gpr_tiled** K_inout, void* stream)
