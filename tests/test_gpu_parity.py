@@ -296,6 +296,38 @@ def test_fused_sweep_equals_three_calls(ctx, n, ns, tile):
     K3.free()
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_mixed_fused_equals_three_calls(ctx, prec):
+    """FP32 / BF16 updates: the fused call (whose assembly also writes the
+    FP64 copy of K that the refinement reads) and assemble + cholesky +
+    predict (which copies the assembled K) give the same factor, the same
+    refinement and the same mean and covariance, bit for bit."""
+    n, ns, tile = 2000, 300, 256
+    say(f"mixed {prec}: fit_predict vs assemble+cholesky+predict n={n} n_test={ns} tile={tile}")
+    X, y, Xs = nfir_train_test(n, ns)
+    Xd, yd, Xsd = dev(X), dev(y), dev(Xs)
+    K = ctx.assemble(Xd, DEFAULT_HYPER, tile)
+    ctx.cholesky(K, prec)
+    m1, c1, st1 = ctx.predict(K, Xd, yd, Xsd, DEFAULT_HYPER, ir_stats=True)
+    L1 = host(ctx.to_dense(K))
+    m1, c1 = host(m1), host(c1)
+    m2, c2, K2, st2 = ctx.fit_predict(Xd, yd, Xsd, DEFAULT_HYPER, tile, precision=prec,
+                                      ir_stats=True)
+    L2 = host(ctx.to_dense(K2))
+    assert ctx.sync()[0] == 0
+    say(f"  refinement steps {st1['iters']} / {st2['iters']} ({st1['method']} / "
+        f"{st2['method']}), precision used {st2['precision']}")
+    if st2["precision"] == st1["precision"] != 0:
+        np.testing.assert_array_equal(L2, L1)
+        assert st2["iters"] == st1["iters"] and st2["method"] == st1["method"]
+        np.testing.assert_array_equal(host(m2), m1)
+        np.testing.assert_array_equal(host(c2), c1)
+    ref = oracle.predict(X, y, Xs, DEFAULT_HYPER, want=("mean",))
+    assert oracle.rel_err(host(m2), ref["mean"]) <= MEAN_TOL_MIXED
+    K.free()
+    K2.free()
+
+
 def test_prediction_is_deterministic(ctx):
     n, ns, tile = 1024, 256, 128
     say(f"determinism n={n} n_test={ns} tile={tile}")
