@@ -1371,9 +1371,13 @@ int predict_impl(gpr_ctx* ctx, gpr_tiled* L, const double* X, const double* y, i
             if (rc) return rc;
         }
     }
-    // alpha = K^{-1} y via the two triangular solves (Sec. 4.1)
+    // With the test rows formed and an FP64 factor the mean is V^T beta
+    // (eqs. (2), (3): K_{X*,X} K^{-1} y = (L^{-1} K_{X,X*})^T L^{-1} y), so only
+    // the forward solve runs; otherwise alpha = K^{-1} y via both triangular
+    // solves (Sec. 4.1), refined for a mixed-precision factor.
+    const bool mean_from_v = rows && L->prec == GPR_FP64;
     HIP_TRY(launch_copy_f64(y, r, n, (int64_t)npad, s));
-    rc = run_trsv_pair(ctx, L, r, tmp, beta, alpha, s);
+    rc = run_trsv_pair(ctx, L, r, tmp, beta, mean_from_v ? nullptr : alpha, s);
     if (rc) return rc;
     const double* alpha_used = alpha;
     if (ir) {
@@ -1481,7 +1485,7 @@ int predict_impl(gpr_ctx* ctx, gpr_tiled* L, const double* X, const double* y, i
         alpha_used = acc;
     }
     // mean = K_{X*,X} alpha, eq. (2), without storing K_{X*,X}
-    {
+    if (!mean_from_v) {
         ProfScope ps(ctx, s, PK_MATVEC, 2.0 * (double)n_test * (double)n, 0.0);
         HIP_TRY(launch_kernel_matvec(Xs, n_test, X, n, D, h.lengthscale, h.vertical_variance,
                                      h.noise_variance, false, alpha_used, nullptr, mean, mvw,
@@ -1490,6 +1494,11 @@ int predict_impl(gpr_ctx* ctx, gpr_tiled* L, const double* X, const double* y, i
     if (dj.pending) {
         rc = dj.now();
         if (rc) return rc;
+    }
+    if (mean_from_v) {
+        // V^T is complete once the sweep's streams have joined
+        ProfScope ps(ctx, s, PK_MATVEC, 2.0 * (double)n_test * (double)n, 0.0);
+        HIP_TRY(launch_rowdot_mean(SM.V, M, n_test, beta, mean, s));
     }
     if (cov) {
         ProfScope ps(ctx, s, PK_EXPORT, 0.0, (double)n_test * n_test * sizeof(double));

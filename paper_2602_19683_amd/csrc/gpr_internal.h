@@ -264,6 +264,10 @@ hipError_t launch_adam_step(AdamState* st, const double* fit, double* trace, int
 hipError_t launch_rowsq_var(const TileMat& V, int M, int64_t n_test, double v, double* var,
                             hipStream_t s);
 hipError_t launch_tile_diag(const TileMat& S, int64_t n, double* out, hipStream_t s);
+// mean_i = sum_j V^T_ij beta_j over the M tiles of test-tile row i / m of V
+// (layout 1), i < n_test; beta: M m entries.
+hipError_t launch_rowdot_mean(const TileMat& V, int M, int64_t n_test, const double* beta,
+                              double* mean, hipStream_t s);
 
 hipError_t launch_set_int(int* p, int value, hipStream_t s);
 hipError_t launch_copy_f64(const double* src, double* dst, int64_t n, int64_t n_pad,

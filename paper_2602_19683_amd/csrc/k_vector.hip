@@ -460,6 +460,31 @@ __global__ __launch_bounds__(256) void k_rowsq_var(TileMat V, int M, int64_t n_t
     if (lane == 0) var[i] = v - acc;
 }
 
+// Predictive mean from the test rows (eqs. (2) and (3) share V = L^{-1}
+// K_{X,X*}): mean = K_{X*,X} L^{-T} L^{-1} y = V^T beta with beta = L^{-1} y,
+// so no backward solve is needed once V^T is formed. One wave per test row;
+// each lane sums its columns of every tile in order, then a fixed butterfly:
+// bitwise reproducible. beta has M m entries (zero padding).
+__global__ __launch_bounds__(256) void k_rowdot_mean(TileMat V, int M, int64_t n_test,
+                                                     const double* __restrict__ beta,
+                                                     double* __restrict__ mean)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= n_test) return;
+    const int m = V.m;
+    const int I = (int)(i / m), r = (int)(i % m);
+    double acc = 0.0;
+    for (int J = 0; J < M; ++J) {
+        const double* row = tile_ptr(V, I, J) + (size_t)r * m;
+        const double* b = beta + (size_t)J * m;
+#pragma unroll 4
+        for (int c = lane; c < m; c += 64) acc = fma(gld(row + c), gld(b + c), acc);
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) mean[i] = acc;
+}
+
 // The diagonal of a lower-tiled matrix (the predictive variances when the
 // full covariance is formed): out_i = S_ii, i < n.
 __global__ void k_tile_diag(TileMat S, int64_t n, double* __restrict__ out)
@@ -477,6 +502,15 @@ hipError_t launch_rowsq_var(const TileMat& V, int M, int64_t n_test, double v, d
     if (n_test <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_rowsq_var, dim3((unsigned)((n_test + 3) / 4)), dim3(256), 0, s, V, M,
                        n_test, v, var);
+    return hipGetLastError();
+}
+
+hipError_t launch_rowdot_mean(const TileMat& V, int M, int64_t n_test, const double* beta,
+                              double* mean, hipStream_t s)
+{
+    if (n_test <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rowdot_mean, dim3((unsigned)((n_test + 3) / 4)), dim3(256), 0, s, V, M,
+                       n_test, beta, mean);
     return hipGetLastError();
 }
 

@@ -288,10 +288,15 @@ def test_fused_sweep_equals_three_calls(ctx, n, ns, tile):
     m2, c2 = ctx.predict(K, Xd, yd, Xsd, DEFAULT_HYPER)
     np.testing.assert_array_equal(host(m2), m)
     np.testing.assert_array_equal(host(c2), c)
-    # mean only
+    # mean only: no test rows, so the mean is K_{X*,X} alpha after both solves
+    # (with the test rows it is V^T beta): the same value, other roundings
     m3, c3, K3 = ctx.fit_predict(Xd, yd, Xsd, DEFAULT_HYPER, tile, full_cov=False)
     assert c3 is None
-    np.testing.assert_array_equal(host(m3), m)
+    m3 = host(m3)
+    e3 = oracle.rel_err(m3, m)
+    say(f"  mean only vs with the covariance: rel {e3:.2e}")
+    assert e3 <= 1e-12
+    assert oracle.rel_err(m3, ref["mean"]) <= TOL
     K.free()
     K3.free()
 
